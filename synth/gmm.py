@@ -1,0 +1,99 @@
+"""Seeded Gaussian-mixture vectors standing in for SIFT1B (u8, d=128), DEEP1B
+(f32, d=96) and SPACEV1B (i8, d=100), the datasets of the paper's evaluation
+(section 5.1), which are not available here.  Only their dtype, dimension and
+query counts are copied; the value distributions are the mixture recipes below.
+
+Recipes (component weights uniform; numpy PCG64):
+  u8  : centres ~ U[40, 215]^d, x = rint(c + 20 z), clipped to [0, 255]
+  i8  : centres ~ U[-88, 87]^d, x = rint(c + 20 z), clipped to [-128, 127]
+  f32 : centres = normalize(N(0, I)), x = normalize(c + 0.1 z), in fp64, cast
+Seeds: base 1000 + c, queries 2000 + c for workload c; the centres come from
+the base seed's first draws so that base and queries share them.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+
+@dataclasses.dataclass(frozen=True)
+class WorkloadConfig:
+    cid: int
+    name: str
+    n: int
+    d: int
+    dtype: str          # "u8" | "i8" | "f32"
+    components: int
+    R: int
+    slot: int           # record slot bytes
+    tier: str           # "hbm" | "host" | "nvme"
+    nq: int
+    k: int
+    L: tuple
+
+    @property
+    def np_dtype(self):
+        return {"u8": np.uint8, "i8": np.int8, "f32": np.float32}[self.dtype]
+
+
+CONFIGS = {
+    1: WorkloadConfig(1, "strict in-HBM, 10k u8/128", 10_000, 128, "u8", 16, 32, 256, "hbm",
+                      100, 10, (64,)),
+    2: WorkloadConfig(2, "1M u8/128 records in pinned host DRAM", 1_000_000, 128, "u8", 256, 64,
+                      512, "host", 10_000, 10, (32, 48, 64, 96, 128, 192, 256)),
+    3: WorkloadConfig(3, "10M f32/96 records on NVMe", 10_000_000, 96, "f32", 1024, 64, 4096,
+                      "nvme", 10_000, 10, (128,)),
+    4: WorkloadConfig(4, "100M i8/100 batched, uneven L", 100_000_000, 100, "i8", 4096, 48, 512,
+                      "nvme", 100_000, 10, (32, 64, 128, 256)),
+    5: WorkloadConfig(5, "100M u8/128 serving", 100_000_000, 128, "u8", 4096, 64, 512, "nvme",
+                      100_000, 10, (32, 64, 128, 256)),
+}
+
+
+def _centres(rng: np.random.Generator, m: int, d: int, dtype: str) -> np.ndarray:
+    if dtype == "u8":
+        return rng.uniform(40.0, 215.0, size=(m, d))
+    if dtype == "i8":
+        return rng.uniform(-88.0, 87.0, size=(m, d))
+    c = rng.standard_normal(size=(m, d))
+    return c / np.linalg.norm(c, axis=1, keepdims=True)
+
+
+def _points(rng: np.random.Generator, centres: np.ndarray, n: int, dtype: str,
+            chunk: int = 1 << 20) -> np.ndarray:
+    m, d = centres.shape
+    out = np.empty((n, d), dtype={"u8": np.uint8, "i8": np.int8, "f32": np.float32}[dtype])
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        comp = rng.integers(0, m, size=e - s)
+        if dtype == "f32":
+            x = centres[comp] + 0.1 * rng.standard_normal(size=(e - s, d))
+            x /= np.linalg.norm(x, axis=1, keepdims=True)
+            out[s:e] = x.astype(np.float32)
+        else:
+            x = np.rint(centres[comp] + 20.0 * rng.standard_normal(size=(e - s, d)))
+            lo, hi = (0, 255) if dtype == "u8" else (-128, 127)
+            out[s:e] = np.clip(x, lo, hi).astype(out.dtype)
+    return out
+
+
+def make_base(n: int, d: int, dtype: str, components: int, seed: int) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    centres = _centres(rng, components, d, dtype)
+    return _points(rng, centres, n, dtype)
+
+
+def make_queries(nq: int, d: int, dtype: str, components: int, base_seed: int,
+                 query_seed: int) -> np.ndarray:
+    centres = _centres(np.random.Generator(np.random.PCG64(base_seed)), components, d, dtype)
+    return _points(np.random.Generator(np.random.PCG64(query_seed)), centres, nq, dtype)
+
+
+def make_dataset(cfg: WorkloadConfig, n: int | None = None, nq: int | None = None):
+    """Base vectors and queries of workload ``cfg`` (optionally truncated sizes)."""
+    n = cfg.n if n is None else n
+    nq = cfg.nq if nq is None else nq
+    base = make_base(n, cfg.d, cfg.dtype, cfg.components, 1000 + cfg.cid)
+    queries = make_queries(nq, cfg.d, cfg.dtype, cfg.components, 1000 + cfg.cid, 2000 + cfg.cid)
+    return base, queries
