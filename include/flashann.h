@@ -1,0 +1,131 @@
+/*
+ * flashann.h -- C ABI of the MI355X (gfx950) out-of-core graph search library.
+ *
+ * The method is the search hot path of FlashANNS (arXiv 2507.10070): batched
+ * best-first search over a fixed-degree proximity graph in which every
+ * expansion fetches one node record (full-precision vector plus neighbour
+ * ids) from a storage tier and scores the neighbours by squared L2 distance
+ * (paper section 4.1.1), optionally with the dependency-relaxed schedule that
+ * issues the next record fetch before the current distances are done
+ * (section 4.1.2).  The problem statement is top-k by L2 (section 1); recall
+ * is controlled by the candidate-list size L (section 5.1).
+ *
+ * Conventions
+ *   - Every function returns ANN_OK (0) or a negative errno-style code and
+ *     leaves a message for ann_last_error() on failure.
+ *   - Pointers documented "device" must be device-accessible (hipMalloc or
+ *     PyTorch CUDA tensors); "host" pointers are plain host memory.  The
+ *     caller owns every pointer it passes; the library keeps none of them
+ *     after a call returns (ann_search: after the stream work completes).
+ *   - The library owns the index handle and everything inside it: the HBM
+ *     navigation copy, the record store of the chosen tier, staging buffers.
+ *   - Distances are squared L2 (no square root): exact uint32 for u8/i8
+ *     vectors, fp32 for f32 vectors.
+ *   - Vectors are row-major, d elements per row, no padding.
+ */
+#ifndef FLASHANN_H
+#define FLASHANN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ANN_OK = 0,
+  ANN_EIO = -5,
+  ANN_ENOMEM = -12,
+  ANN_EBUSY = -16,
+  ANN_ENODEV = -19,
+  ANN_EINVAL = -22,
+  ANN_ENOTSUP = -95,
+  ANN_ETIMEDOUT = -110
+};
+
+typedef enum { ANN_U8 = 1, ANN_I8 = 2, ANN_F32 = 3 } ann_dtype;
+
+/* Where node records live (section 4.2 places them on SSD; this build offers
+ * HBM, pinned host DRAM read by the GPU over the host link, and a file). */
+typedef enum { ANN_TIER_HBM = 0, ANN_TIER_HOST = 1, ANN_TIER_FILE = 2 } ann_tier;
+
+typedef struct ann_index ann_index; /* opaque, owned by the library */
+
+typedef struct {
+  int64_t n;          /* base vectors */
+  int32_t d;          /* dimension */
+  int32_t dtype;      /* ann_dtype */
+  int32_t R;          /* neighbour ids per record */
+  int32_t entry;      /* entrance node of every search */
+  int32_t slot_bytes; /* record slot size */
+  int32_t tier;       /* ann_tier */
+  int32_t nav_stride; /* bytes per row of the HBM navigation copy */
+  int32_t rec_bytes;  /* bytes of each record fetched per step */
+  int64_t hbm_bytes;  /* device memory held by the index */
+} ann_index_info;
+
+/* Search options; a NULL pointer means {delay = 1, beam_width = 1, defaults}. */
+typedef struct {
+  int32_t delay;           /* staleness: 0 = strict best-first, 1 = relaxed (section 4.1.4 default) */
+  int32_t beam_width;      /* nodes selected per iteration; only 1 is implemented */
+  int32_t hash_bits;       /* log2 of the per-query visited-hash slots (0 = default 10) */
+  int32_t waves_per_block; /* queries per workgroup, 1..4 (0 = default 4) */
+  unsigned long long *d_stats; /* optional device counters, 3 x u64, accumulated:
+                                  [0] expansions [1] neighbour distances computed
+                                  [2] records whose own vector disagreed with the
+                                  navigation copy (always 0 for a valid index) */
+  int32_t *d_trace;        /* optional device buffer, nq x trace_cap int32: the
+                              expanded node ids of each query in expansion order
+                              (entries past the query's steps are left untouched) */
+  int32_t trace_cap;
+} ann_search_opts;
+
+/*
+ * ann_index_create -- build a searchable index from host arrays.
+ *   vectors    host, n x d elements of `dtype`
+ *   adjacency  host, n x R int32 neighbour ids; ids outside [0, n) are
+ *              padding and are skipped by the search
+ *   entry      entrance node (e.g. the medoid), 0 <= entry < n
+ *   slot_bytes record slot size; a record is the vector (padded to 16 B)
+ *              followed by the R ids, so slot_bytes >= round_up(d*b,16) + 4R
+ *              and a multiple of 16; the fetched part must be <= 1024 B
+ *   tier       ANN_TIER_HBM or ANN_TIER_HOST (pinned host DRAM)
+ * Layout follows the paper's node record: the vector then its neighbour ids
+ * (section 3, challenge C3: 128 B of u8 vector + 64 x 4 B ids = 384 B).
+ * Errors: ANN_EINVAL (bad sizes), ANN_ENOMEM, ANN_ENODEV (no GPU).
+ */
+int ann_index_create(const void *vectors, const int32_t *adjacency, int64_t n, int32_t d,
+                     int32_t dtype, int32_t R, int32_t entry, int32_t slot_bytes, int32_t tier,
+                     ann_index **out);
+
+/* ann_index_info -- sizes and layout of an index (host struct, caller-owned). */
+int ann_index_info_get(const ann_index *ix, ann_index_info *out);
+
+/*
+ * ann_search -- batched top-k search, stream-ordered on `hip_stream` (a
+ * hipStream_t; NULL = default stream).  One GPU wavefront runs each query.
+ *   d_queries  device, nq x d elements of the index dtype
+ *   k, L       results per query and candidate-list size, 1 <= k <= L <= 1024
+ *   R          neighbours used per expansion, 1 <= R <= index R (0 = index R)
+ *   d_ids      device, nq x k int32, padded with -1 when fewer than k found
+ *   d_dists    device, nq x k: uint32 (u8/i8, padding 0xFFFFFFFF) or float
+ *              (f32, padding +inf)
+ *   d_steps    device, nq uint32 expansions per query, optional (NULL)
+ * Returns after the launch; buffers must stay valid until the stream syncs.
+ * Errors: ANN_EINVAL before any device work; ANN_ENOTSUP for beam_width > 1.
+ */
+int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int32_t L, int32_t R,
+               const ann_search_opts *opts, int32_t *d_ids, void *d_dists, uint32_t *d_steps,
+               void *hip_stream);
+
+/* ann_index_free -- release everything the index holds (NULL is a no-op). */
+int ann_index_free(ann_index *ix);
+
+/* Thread-local message describing the last failure of this thread. */
+const char *ann_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FLASHANN_H */

@@ -1,0 +1,9 @@
+"""MI355X (gfx950) search hot path of FlashANNS (arXiv 2507.10070).
+
+The compute path is the HIP library ``libflashann.so`` (C ABI declared in
+``include/flashann.h``); this package is a thin ctypes binding around it.
+Importing the package does not load the library; the first call does, and it
+raises if the library has not been built.
+"""
+from .flashann import (ANN_ERRORS, Index, SearchOptions, load_library, search,  # noqa: F401
+                       DTYPE_CODES, TIER_HBM, TIER_HOST, TIER_FILE)

@@ -1,0 +1,564 @@
+// search_kernel.hip -- batched best-first graph search on gfx950 (CDNA4),
+// strict or with the dependency-relaxed fetch schedule of FlashANNS
+// (arXiv 2507.10070, section 4.1).
+//
+// One wavefront (64 lanes) runs one query.  Per wave, LDS holds
+//   cand[Lcap]  the candidate list: u64 keys (distance << 32 | id), sorted
+//               ascending; bit 31 of the id word is the "expanded" flag
+//   nk[64]      sorted keys of the batch being merged
+//   stage[64]   the record being processed (16 B per lane)
+//   qbuf        the query, zero-padded to the navigation row stride
+//   ids/dsc     per-batch neighbour ids and their distances
+//   hash[H]     visited set: exact ids, linear probing, may forget
+// Forgetting is harmless: a forgotten node is either still in the list (its
+// recomputed key is identical and is dropped as a duplicate) or its key is
+// above the current L-th key, which never increases, so it is rejected again.
+//
+// A search step (section 4.1.1): select the first unexpanded candidate, fetch
+// its record (full vector + R neighbour ids), score the unvisited neighbours
+// with exact squared L2 against the HBM navigation copy, merge them into the
+// list.  With DELAY = 1 the node selected in iteration t is processed in
+// iteration t+1, so its record fetch overlaps the gathers, distances and
+// merge of the previous node (section 4.1.2).  Selection always happens before
+// the previous node's merge, i.e. on the list as of one step earlier.
+//
+// Distances: u8/i8 exactly as |q|^2 + |x|^2 - 2 q.x with 4-byte dot products
+// (v_dot4), f32 as a sum of squared differences in fp32.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "search_kernel.h"
+
+namespace fa {
+
+constexpr uint32_t kFlag = 0x80000000u;
+constexpr uint64_t kNoKey = 0xFFFFFFFFFFFFFFFFull;
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint64_t kmask(uint64_t e) { return e & ~(uint64_t)kFlag; }
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Sum over each aligned group of 8 lanes; every lane of the group gets it.
+__device__ __forceinline__ int group8_sum(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  return v;
+}
+__device__ __forceinline__ float group8_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
+  return v;
+}
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t x, int m) {
+  const int addr = ((lane_id() ^ m) << 2);
+  uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)x);
+  uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Ascending bitonic sort of one u64 per lane across the wave.
+__device__ __forceinline__ uint64_t wave_sort64(uint64_t x) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint64_t o = shfl_xor64(x, j);
+      const bool up = (lane & k) == 0;
+      const bool lower = (lane & j) == 0;
+      const bool take_min = (lower == up);
+      x = take_min ? (o < x ? o : x) : (o > x ? o : x);
+    }
+  }
+  return x;
+}
+
+__device__ __forceinline__ uint32_t mbcnt(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Number of entries of a[0..cnt) whose masked key is below `key`.
+__device__ __forceinline__ int lower_bound(const uint64_t *a, int cnt, uint64_t key) {
+  int lo = 0, hi = cnt;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (kmask(a[mid]) < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Visited set probe: true if x was not recorded (and is recorded now).
+__device__ __forceinline__ bool hash_insert(uint32_t *tab, int bits, uint32_t x) {
+  const uint32_t mask = (1u << bits) - 1u;
+  const uint32_t h = (x * 2654435761u) >> (32 - bits);
+#pragma unroll 1
+  for (int p = 0; p < 8; p++) {
+    const uint32_t s = (h + (uint32_t)p) & mask;
+    uint32_t cur = tab[s];
+    if (cur == x) return false;
+    if (cur == kEmpty) {
+      cur = atomicCAS(&tab[s], kEmpty, x);
+      if (cur == kEmpty) return true;
+      if (cur == x) return false;
+    }
+  }
+  atomicExch(&tab[h & mask], x);  // neighbourhood full: forget one id
+  return true;
+}
+
+// ---------------------------------------------------------------- dtypes
+
+template <int DT>
+struct Dist;
+
+template <>
+struct Dist<DT_U8> {
+  // partial = |x|^2 - 2 q.x over this lane's chunks
+  __device__ __forceinline__ static int partial(const uint4 q, const uint4 r, int acc) {
+    uint32_t qx = 0, xx = 0;
+    qx = __builtin_amdgcn_udot4(q.x, r.x, qx, false);
+    qx = __builtin_amdgcn_udot4(q.y, r.y, qx, false);
+    qx = __builtin_amdgcn_udot4(q.z, r.z, qx, false);
+    qx = __builtin_amdgcn_udot4(q.w, r.w, qx, false);
+    xx = __builtin_amdgcn_udot4(r.x, r.x, xx, false);
+    xx = __builtin_amdgcn_udot4(r.y, r.y, xx, false);
+    xx = __builtin_amdgcn_udot4(r.z, r.z, xx, false);
+    xx = __builtin_amdgcn_udot4(r.w, r.w, xx, false);
+    return acc + (int)xx - 2 * (int)qx;
+  }
+  __device__ __forceinline__ static int self(const uint4 q, int acc) {
+    uint32_t s = 0;
+    s = __builtin_amdgcn_udot4(q.x, q.x, s, false);
+    s = __builtin_amdgcn_udot4(q.y, q.y, s, false);
+    s = __builtin_amdgcn_udot4(q.z, q.z, s, false);
+    s = __builtin_amdgcn_udot4(q.w, q.w, s, false);
+    return acc + (int)s;
+  }
+  using Acc = int;
+  __device__ __forceinline__ static uint32_t finish(int qq, int sum) { return (uint32_t)(qq + sum); }
+};
+
+template <>
+struct Dist<DT_I8> {
+  __device__ __forceinline__ static int partial(const uint4 q, const uint4 r, int acc) {
+    int qx = 0, xx = 0;
+    qx = __builtin_amdgcn_sdot4((int)q.x, (int)r.x, qx, false);
+    qx = __builtin_amdgcn_sdot4((int)q.y, (int)r.y, qx, false);
+    qx = __builtin_amdgcn_sdot4((int)q.z, (int)r.z, qx, false);
+    qx = __builtin_amdgcn_sdot4((int)q.w, (int)r.w, qx, false);
+    xx = __builtin_amdgcn_sdot4((int)r.x, (int)r.x, xx, false);
+    xx = __builtin_amdgcn_sdot4((int)r.y, (int)r.y, xx, false);
+    xx = __builtin_amdgcn_sdot4((int)r.z, (int)r.z, xx, false);
+    xx = __builtin_amdgcn_sdot4((int)r.w, (int)r.w, xx, false);
+    return acc + xx - 2 * qx;
+  }
+  __device__ __forceinline__ static int self(const uint4 q, int acc) {
+    int s = 0;
+    s = __builtin_amdgcn_sdot4((int)q.x, (int)q.x, s, false);
+    s = __builtin_amdgcn_sdot4((int)q.y, (int)q.y, s, false);
+    s = __builtin_amdgcn_sdot4((int)q.z, (int)q.z, s, false);
+    s = __builtin_amdgcn_sdot4((int)q.w, (int)q.w, s, false);
+    return acc + s;
+  }
+  using Acc = int;
+  __device__ __forceinline__ static uint32_t finish(int qq, int sum) { return (uint32_t)(qq + sum); }
+};
+
+template <>
+struct Dist<DT_F32> {
+  __device__ __forceinline__ static float partial(const uint4 q, const uint4 r, float acc) {
+    float t;
+    t = __uint_as_float(q.x) - __uint_as_float(r.x); acc = fmaf(t, t, acc);
+    t = __uint_as_float(q.y) - __uint_as_float(r.y); acc = fmaf(t, t, acc);
+    t = __uint_as_float(q.z) - __uint_as_float(r.z); acc = fmaf(t, t, acc);
+    t = __uint_as_float(q.w) - __uint_as_float(r.w); acc = fmaf(t, t, acc);
+    return acc;
+  }
+  __device__ __forceinline__ static float self(const uint4, float acc) { return acc; }
+  using Acc = float;
+  __device__ __forceinline__ static uint32_t finish(float, float sum) { return __float_as_uint(sum); }
+};
+
+// ---------------------------------------------------------------- per wave
+
+struct WaveLds {
+  uint64_t *cand;
+  uint64_t *nk;
+  uint4 *stage;
+  uint8_t *qbuf;
+  uint32_t *ids;
+  uint32_t *dsc;
+  uint32_t *hash;
+};
+
+__host__ __device__ inline LdsLayout lds_layout(int Lcap, int nav_stride, int hash_bits) {
+  LdsLayout o;
+  uint32_t off = 0;
+  o.cand = off; off += 8u * (uint32_t)Lcap;
+  o.nk = off; off += 8u * 64u;
+  o.stage = off; off += 16u * 64u;
+  o.qbuf = off; off += (uint32_t)nav_stride;
+  o.ids = off; off += 4u * 64u;
+  o.dsc = off; off += 4u * 64u;
+  o.hash = off; off += 4u << hash_bits;
+  o.bytes = (off + 15u) & ~15u;
+  return o;
+}
+
+template <int DT, int CPL>
+struct Searcher {
+  using D = Dist<DT>;
+  using Acc = typename D::Acc;
+
+  const SearchArgs &A;
+  WaveLds S;
+  int lane, sub, grp;
+  uint4 qv[CPL];
+  Acc qq;
+  int nc;
+  int64_t qi;
+  uint32_t steps, rows, mismatches;
+
+  __device__ Searcher(const SearchArgs &args, uint8_t *base, int64_t query) : A(args), qi(query) {
+    lane = lane_id();
+    sub = lane & 7;
+    grp = lane >> 3;
+    const LdsLayout lay = lds_layout(A.Lcap, A.nav_stride, A.hash_bits);
+    S.cand = (uint64_t *)(base + lay.cand);
+    S.nk = (uint64_t *)(base + lay.nk);
+    S.stage = (uint4 *)(base + lay.stage);
+    S.qbuf = base + lay.qbuf;
+    S.ids = (uint32_t *)(base + lay.ids);
+    S.dsc = (uint32_t *)(base + lay.dsc);
+    S.hash = (uint32_t *)(base + lay.hash);
+    // query -> LDS, zero padded to the row stride
+    const uint8_t *q = A.queries + qi * (int64_t)A.qbytes;
+    for (int b = lane; b < A.nav_stride; b += 64) S.qbuf[b] = b < A.qbytes ? q[b] : (uint8_t)0;
+    for (int s = lane; s < (1 << A.hash_bits); s += 64) S.hash[s] = kEmpty;
+    __builtin_amdgcn_wave_barrier();
+    Acc a = Acc(0);
+#pragma unroll
+    for (int c = 0; c < CPL; c++) {
+      qv[c] = *(const uint4 *)(S.qbuf + 16 * (sub + 8 * c));
+      a = D::self(qv[c], a);
+    }
+    qq = group8_sum(a);
+    steps = rows = mismatches = 0;
+  }
+
+  // Distance of the query to the row at `p` (all 8 lanes of a group call).
+  __device__ __forceinline__ uint32_t row_dist(const uint8_t *p) const {
+    Acc a = Acc(0);
+#pragma unroll
+    for (int c = 0; c < CPL; c++) {
+      const uint4 r = *(const uint4 *)(p + 16 * (sub + 8 * c));
+      a = D::partial(qv[c], r, a);
+    }
+    return D::finish(qq, group8_sum(a));
+  }
+
+  __device__ void init_entry() {
+    const uint32_t e = (uint32_t)A.entry;
+    uint32_t dist = row_dist(A.nav + (int64_t)e * A.nav_stride);
+    if (lane == 0) {
+      S.cand[0] = ((uint64_t)dist << 32) | e;
+      hash_insert(S.hash, A.hash_bits, e);
+    }
+    nc = 1;
+    __builtin_amdgcn_wave_barrier();
+  }
+
+  // First unexpanded candidate: marks it and returns its key (kNoKey if none).
+  // A correct search expands each node at most once; the cap at n expansions
+  // guarantees termination regardless.
+  __device__ uint64_t select() {
+    if ((int64_t)steps >= A.n) return kNoKey;
+    for (int base = 0; base < nc; base += 64) {
+      const int i = base + lane;
+      const bool un = i < nc && !((uint32_t)S.cand[i] & kFlag);
+      const uint64_t b = __ballot(un);
+      if (b) {
+        const int idx = base + __ffsll((unsigned long long)b) - 1;
+        const uint64_t key = S.cand[idx];
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) {
+          S.cand[idx] = key | kFlag;
+          if (A.trace && steps < (uint32_t)A.trace_cap)
+            A.trace[qi * A.trace_cap + steps] = (int32_t)((uint32_t)key & ~kFlag);
+        }
+        __builtin_amdgcn_wave_barrier();
+        steps++;
+        return key;
+      }
+    }
+    return kNoKey;
+  }
+
+  // Record fetch: lane i loads bytes [16i, 16i+16) of the record.  Lanes past
+  // the record re-read its last chunk, so the load has no branch around it
+  // and the compiler can count it exactly when it places its waits.
+  __device__ __forceinline__ uint4 fetch(uint32_t v) const {
+    const int c = lane < A.rec_chunks ? lane : A.rec_chunks - 1;
+    return *(const uint4 *)(A.records + (int64_t)v * A.slot + 16 * c);
+  }
+
+  // Part 1 of processing node u: stage its record, filter the first batch.
+  __device__ __forceinline__ void stage(uint4 rec) {
+    if (lane < A.rec_chunks) S.stage[lane] = rec;
+    __builtin_amdgcn_wave_barrier();
+  }
+
+  // Neighbours [b0, b0+64) of the staged record: visited filter and
+  // compaction.  Returns the number of new ids (written to S.ids).
+  __device__ __forceinline__ int filter(int b0) {
+    const int j = b0 + lane;
+    int32_t x = -1;
+    if (j < A.R) x = ((const int32_t *)((const uint8_t *)S.stage + A.ids_off))[j];
+    bool fresh = false;
+    if (x >= 0 && (int64_t)x < A.n) fresh = hash_insert(S.hash, A.hash_bits, (uint32_t)x);
+    const uint64_t m = __ballot(fresh);
+    if (fresh) S.ids[mbcnt(m)] = (uint32_t)x;
+    __builtin_amdgcn_wave_barrier();
+    return __popcll((unsigned long long)m);
+  }
+
+  // Gather + distances of rows [p0, p0 + 8*PB) of S.ids[0..m): 8 rows per
+  // pass, 8 lanes per row, the loads of all PB passes issued before the
+  // first reduction.  Rows past m re-read row 0 so that no load sits under a
+  // branch.  WITH_FETCH issues the record fetch of `fid` into `frec` right
+  // after the gathers, in straight-line code, so the compiler's wait before
+  // each pass leaves that fetch in flight.
+  static constexpr int PB = (8 / CPL) > 0 ? (8 / CPL) : 1;
+
+  template <bool WITH_FETCH>
+  __device__ __forceinline__ void gather_block(int m, int p0, uint32_t fid, uint4 &frec) {
+    uint4 r[PB][CPL];
+#pragma unroll
+    for (int pb = 0; pb < PB; pb++) {
+      const int row = p0 + 8 * pb + grp;
+      const uint8_t *p = A.nav + (int64_t)S.ids[row < m ? row : 0] * A.nav_stride;
+#pragma unroll
+      for (int c = 0; c < CPL; c++) r[pb][c] = *(const uint4 *)(p + 16 * (sub + 8 * c));
+    }
+    if (WITH_FETCH) frec = fetch(fid);
+#pragma unroll
+    for (int pb = 0; pb < PB; pb++) {
+      const int row = p0 + 8 * pb + grp;
+      Acc a = Acc(0);
+#pragma unroll
+      for (int c = 0; c < CPL; c++) a = D::partial(qv[c], r[pb][c], a);
+      const uint32_t dist = D::finish(qq, group8_sum(a));
+      if (row < m && sub == 0) S.dsc[row] = dist;
+    }
+  }
+
+  // Merge the m scored ids into the candidate list (first L of the union).
+  __device__ __forceinline__ void merge(int m) {
+    uint64_t key = kNoKey;
+    if (lane < m) key = ((uint64_t)S.dsc[lane] << 32) | S.ids[lane];
+    if (key != kNoKey) {
+      const int r = lower_bound(S.cand, nc, key);
+      const bool dup = r < nc && kmask(S.cand[r]) == key;
+      if (dup || r >= A.L) key = kNoKey;
+    }
+    if (__ballot(key != kNoKey) == 0) return;
+    key = wave_sort64(key);
+    // Equal keys in one batch are possible only when the hash forgot an id
+    // that occurs twice in one neighbour list: keep the first.
+    {
+      const int addr = ((lane - 1) & 63) << 2;
+      const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)key);
+      const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(key >> 32));
+      const uint64_t left = ((uint64_t)hi << 32) | lo;
+      const bool dupl = lane > 0 && key != kNoKey && left == key;
+      if (__ballot(dupl)) {
+        if (dupl) key = kNoKey;
+        key = wave_sort64(key);
+      }
+    }
+    const int m2 = __popcll((unsigned long long)__ballot(key != kNoKey));
+    int rnew = 0;
+    if (lane < m2) rnew = lower_bound(S.cand, nc, key);
+    S.nk[lane] = key;
+    __builtin_amdgcn_wave_barrier();
+    // old entries move right by the number of smaller new keys; walk chunks
+    // from the top so that no unread entry is overwritten
+    const int nchunks = (nc + 63) >> 6;
+    for (int t = nchunks - 1; t >= 0; t--) {
+      const int i = 64 * t + lane;
+      uint64_t e = 0;
+      int pos = A.L;
+      if (i < nc) {
+        e = S.cand[i];
+        pos = i + lower_bound(S.nk, m2, kmask(e));
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (i < nc && pos < A.L) S.cand[pos] = e;
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (lane < m2 && lane + rnew < A.L) S.cand[lane + rnew] = key;
+    nc = nc + m2 < A.L ? nc + m2 : A.L;
+    __builtin_amdgcn_wave_barrier();
+  }
+
+  // Optional check: the record's own vector gives the same distance as the
+  // node's key (the record holds the full-precision vector).
+  __device__ __forceinline__ void check_record(uint64_t key) {
+    Acc a = Acc(0);
+    if (grp == 0) {
+#pragma unroll
+      for (int c = 0; c < CPL; c++) {
+        const int chunk = sub + 8 * c;
+        uint4 r = make_uint4(0, 0, 0, 0);
+        if (16 * chunk < A.vec_pad) r = S.stage[chunk];
+        a = D::partial(qv[c], r, a);
+      }
+    }
+    const uint32_t dist = D::finish(qq, group8_sum(a));
+    if (dist != (uint32_t)(key >> 32)) mismatches++;
+  }
+
+  // Score and merge neighbours [b0, b0 + 64) of the staged record, starting
+  // at gather block p_start (earlier blocks were done by the caller).
+  __device__ __forceinline__ void finish_batch(int m, int p_start) {
+    uint4 unused;
+    for (int p0 = p_start; p0 < m; p0 += 8 * PB) gather_block<false>(m, p0, 0u, unused);
+    __builtin_amdgcn_wave_barrier();
+    rows += (uint32_t)m;
+    merge(m);
+  }
+
+  // Process node u whose record is `rec`: stage, filter, gather, merge.
+  // RELAXED: exactly one record fetch (of `fid`, into `frec`) is issued,
+  // right after the first block of gathers (straight-line code, so the waits
+  // before the distance passes leave it in flight), or at once if the first
+  // batch has no new neighbour.
+  template <bool RELAXED>
+  __device__ __forceinline__ void process(uint64_t ukey, uint4 rec, uint32_t fid, uint4 &frec) {
+    stage(rec);
+    if (A.stats) check_record(ukey);
+    const int m = filter(0);
+    if (m > 0) {
+      gather_block<RELAXED>(m, 0, fid, frec);
+      finish_batch(m, 8 * PB);
+    } else if (RELAXED) {
+      frec = fetch(fid);
+    }
+    for (int b0 = 64; b0 < A.R; b0 += 64) {
+      const int mb = filter(b0);
+      if (mb > 0) finish_batch(mb, 0);
+    }
+  }
+
+  __device__ void finish_query(int64_t qi) {
+    for (int j = lane; j < A.k; j += 64) {
+      int32_t id = -1;
+      uint32_t dist = DT == DT_F32 ? 0x7F800000u : 0xFFFFFFFFu;
+      if (j < nc) {
+        const uint64_t e = S.cand[j];
+        id = (int32_t)((uint32_t)e & ~kFlag);
+        dist = (uint32_t)(e >> 32);
+      }
+      A.out_ids[qi * A.k + j] = id;
+      ((uint32_t *)A.out_dists)[qi * A.k + j] = dist;
+    }
+    if (lane == 0) {
+      if (A.out_steps) A.out_steps[qi] = steps;
+      if (A.stats) {
+        atomicAdd(&A.stats[0], (unsigned long long)steps);
+        atomicAdd(&A.stats[1], (unsigned long long)rows);
+        atomicAdd(&A.stats[2], (unsigned long long)mismatches);
+      }
+    }
+  }
+};
+
+// Strict and relaxed drivers.  The relaxed loop is unrolled twice so the two
+// in-flight record registers have static names; a slot whose id word holds
+// kNoKey is an empty pipeline slot.
+template <int DT, int CPL, int DELAY>
+__global__ void __launch_bounds__(256) search_kernel(SearchArgs A) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int wave = threadIdx.x >> 6;
+  const int64_t qi = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  if (qi >= A.nq) return;
+  Searcher<DT, CPL> s(A, smem + (size_t)wave * A.lds_per_wave, qi);
+  s.init_entry();
+  if (DELAY == 0) {
+    uint4 unused = make_uint4(0, 0, 0, 0);
+    for (;;) {
+      const uint64_t v = s.select();
+      if (v == kNoKey) break;
+      const uint4 rec = s.fetch((uint32_t)v & ~kFlag);
+      s.template process<false>(v, rec, 0u, unused);
+    }
+  } else {
+    // Two pipeline slots.  An empty slot (key kNoKey) is filled with a fetch
+    // of the entry record so that every processing issues exactly one fetch.
+    const uint32_t dummy = (uint32_t)A.entry;
+    uint64_t k0 = kNoKey, k1 = kNoKey;
+    uint4 r0 = make_uint4(0, 0, 0, 0), r1 = make_uint4(0, 0, 0, 0);
+    for (;;) {
+      // slot 0 receives the new selection while slot 1 (the previous
+      // selection) is processed; then the roles swap
+      k0 = s.select();
+      if (k0 == kNoKey && k1 == kNoKey) break;
+      const uint32_t f0 = k0 != kNoKey ? ((uint32_t)k0 & ~kFlag) : dummy;
+      if (k1 != kNoKey) s.template process<true>(k1, r1, f0, r0);
+      else r0 = s.fetch(f0);
+      k1 = s.select();
+      if (k1 == kNoKey && k0 == kNoKey) break;
+      const uint32_t f1 = k1 != kNoKey ? ((uint32_t)k1 & ~kFlag) : dummy;
+      if (k0 != kNoKey) s.template process<true>(k0, r0, f1, r1);
+      else r1 = s.fetch(f1);
+    }
+  }
+  s.finish_query(qi);
+}
+
+template <int DT, int CPL, int DELAY>
+static hipError_t launch_t(const SearchArgs &a, int waves_per_block, hipStream_t st) {
+  const int64_t blocks = (a.nq + waves_per_block - 1) / waves_per_block;
+  const size_t lds = (size_t)a.lds_per_wave * waves_per_block;
+  hipLaunchKernelGGL((search_kernel<DT, CPL, DELAY>), dim3((unsigned)blocks),
+                     dim3(64 * waves_per_block), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int DT, int CPL>
+static hipError_t launch_d(const SearchArgs &a, int delay, int wpb, hipStream_t st) {
+  return delay == 0 ? launch_t<DT, CPL, 0>(a, wpb, st) : launch_t<DT, CPL, 1>(a, wpb, st);
+}
+
+template <int DT>
+static hipError_t launch_c(const SearchArgs &a, int cpl, int delay, int wpb, hipStream_t st) {
+  switch (cpl) {
+    case 1: return launch_d<DT, 1>(a, delay, wpb, st);
+    case 2: return launch_d<DT, 2>(a, delay, wpb, st);
+    case 3: return launch_d<DT, 3>(a, delay, wpb, st);
+    case 4: return launch_d<DT, 4>(a, delay, wpb, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+uint32_t search_lds_bytes(int Lcap, int nav_stride, int hash_bits) {
+  return lds_layout(Lcap, nav_stride, hash_bits).bytes;
+}
+
+hipError_t launch_search(const SearchArgs &a, int dtype, int delay, int waves_per_block,
+                         hipStream_t st) {
+  const int cpl = a.nav_stride / 128;
+  switch (dtype) {
+    case DT_U8: return launch_c<DT_U8>(a, cpl, delay, waves_per_block, st);
+    case DT_I8: return launch_c<DT_I8>(a, cpl, delay, waves_per_block, st);
+    case DT_F32: return launch_c<DT_F32>(a, cpl, delay, waves_per_block, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace fa

@@ -1,0 +1,161 @@
+"""ctypes binding of ``libflashann.so`` (C ABI in ``include/flashann.h``).
+
+Argument marshalling only: every step of the search runs in the HIP
+kernels.  PyTorch provides device memory and the current stream.  If the
+library is missing, every entry point raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libflashann.so")
+
+ANN_ERRORS = {0: "ANN_OK", -5: "ANN_EIO", -12: "ANN_ENOMEM", -16: "ANN_EBUSY",
+              -19: "ANN_ENODEV", -22: "ANN_EINVAL", -95: "ANN_ENOTSUP", -110: "ANN_ETIMEDOUT"}
+DTYPE_CODES = {np.dtype(np.uint8): 1, np.dtype(np.int8): 2, np.dtype(np.float32): 3}
+TIER_HBM, TIER_HOST, TIER_FILE = 0, 1, 2
+
+EXPORTED = ["ann_index_create", "ann_index_info_get", "ann_search", "ann_index_free",
+            "ann_last_error"]
+
+
+class AnnError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__("%s (%d): %s" % (ANN_ERRORS.get(code, "?"), code, message))
+        self.code = code
+
+
+class SearchOptions(ctypes.Structure):
+    _fields_ = [("delay", ctypes.c_int32), ("beam_width", ctypes.c_int32),
+                ("hash_bits", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
+                ("d_stats", ctypes.c_void_p), ("d_trace", ctypes.c_void_p),
+                ("trace_cap", ctypes.c_int32)]
+
+
+class IndexInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("R", ctypes.c_int32), ("entry", ctypes.c_int32), ("slot_bytes", ctypes.c_int32),
+                ("tier", ctypes.c_int32), ("nav_stride", ctypes.c_int32),
+                ("rec_bytes", ctypes.c_int32), ("hbm_bytes", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("%s is not built: run __graft_entry__.build() first" % path)
+    lib = ctypes.CDLL(path)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    lib.ann_index_create.argtypes = [vp, vp, i64, i32, i32, i32, i32, i32, i32,
+                                     ctypes.POINTER(vp)]
+    lib.ann_index_create.restype = ctypes.c_int
+    lib.ann_index_info_get.argtypes = [vp, ctypes.POINTER(IndexInfo)]
+    lib.ann_index_info_get.restype = ctypes.c_int
+    lib.ann_search.argtypes = [vp, vp, i64, i32, i32, i32, ctypes.POINTER(SearchOptions),
+                               vp, vp, vp, vp]
+    lib.ann_search.restype = ctypes.c_int
+    lib.ann_index_free.argtypes = [vp]
+    lib.ann_index_free.restype = ctypes.c_int
+    lib.ann_last_error.argtypes = []
+    lib.ann_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise AnnError(rc, load_library().ann_last_error().decode(errors="replace"))
+
+
+class Index:
+    """A searchable index: navigation copy in HBM plus records in a tier."""
+
+    def __init__(self, vectors: np.ndarray, adjacency: np.ndarray, entry: int,
+                 slot_bytes: int, tier: int = TIER_HBM):
+        lib = load_library()
+        vectors = np.ascontiguousarray(vectors)
+        adjacency = np.ascontiguousarray(adjacency, dtype=np.int32)
+        if vectors.dtype not in DTYPE_CODES or vectors.ndim != 2:
+            raise ValueError("vectors must be a 2-D uint8, int8 or float32 array")
+        if adjacency.ndim != 2 or adjacency.shape[0] != vectors.shape[0]:
+            raise ValueError("adjacency must be [n, R] int32")
+        self.dtype = vectors.dtype
+        self.d = vectors.shape[1]
+        h = ctypes.c_void_p()
+        _check(lib.ann_index_create(vectors.ctypes.data, adjacency.ctypes.data,
+                                    vectors.shape[0], vectors.shape[1], DTYPE_CODES[vectors.dtype],
+                                    adjacency.shape[1], int(entry), int(slot_bytes), int(tier),
+                                    ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("index is closed")
+        return self._h
+
+    def info(self) -> dict:
+        out = IndexInfo()
+        _check(load_library().ann_index_info_get(self.handle, ctypes.byref(out)))
+        return {f: getattr(out, f) for f, _ in IndexInfo._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load_library().ann_index_free(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
+           beam_width: int = 1, hash_bits: int = 0, waves_per_block: int = 0, stats=None,
+           trace=None, stream=None, out=None):
+    """ann_search on torch CUDA tensors.
+
+    queries: [nq, d] device tensor of the index dtype (uint8/int8/float32).
+    stats: optional int64 device tensor of 3 counters (accumulated);
+    trace: optional int32 device tensor [nq, cap] receiving expanded ids.
+    Returns (ids int32 [nq,k], dists [nq,k] int32-viewed uint32 or float32,
+    steps int32-viewed uint32 [nq]), all on the device.
+    """
+    import torch
+
+    if queries.dim() != 2 or queries.shape[1] != index.d:
+        raise ValueError("queries must be [nq, %d]" % index.d)
+    want = {np.dtype(np.uint8): torch.uint8, np.dtype(np.int8): torch.int8,
+            np.dtype(np.float32): torch.float32}[index.dtype]
+    if queries.dtype != want or not queries.is_cuda or not queries.is_contiguous():
+        raise ValueError("queries must be a contiguous CUDA %s tensor" % want)
+    nq = queries.shape[0]
+    dev = queries.device
+    if out is None:
+        ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+        dists = torch.empty((nq, k), dtype=torch.float32 if index.dtype == np.float32
+                            else torch.int32, device=dev)
+        steps = torch.empty((nq,), dtype=torch.int32, device=dev)
+    else:
+        ids, dists, steps = out
+    opts = SearchOptions(delay, beam_width, hash_bits, waves_per_block,
+                         stats.data_ptr() if stats is not None else None,
+                         trace.data_ptr() if trace is not None else None,
+                         trace.shape[1] if trace is not None else 0)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    _check(load_library().ann_search(index.handle, queries.data_ptr(), nq, k, L, R,
+                                     ctypes.byref(opts), ids.data_ptr(), dists.data_ptr(),
+                                     steps.data_ptr() if steps is not None else None,
+                                     st.cuda_stream))
+    return ids, dists, steps
