@@ -79,6 +79,9 @@ typedef struct {
                               expanded node ids of each query in expansion order
                               (entries past the query's steps are left untouched) */
   int32_t trace_cap;
+  unsigned long long *d_times; /* optional device buffer, nq x 2 u64: wall-clock
+                                  stamps when each query's search starts and ends,
+                                  in ticks of ann_device_clock_khz() kHz */
 } ann_search_opts;
 
 /*
@@ -118,6 +121,10 @@ int ann_index_info_get(const ann_index *ix, ann_index_info *out);
 int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int32_t L, int32_t R,
                const ann_search_opts *opts, int32_t *d_ids, void *d_dists, uint32_t *d_steps,
                void *hip_stream);
+
+/* ann_device_clock_khz -- frequency of the device wall clock used by
+ * ann_search_opts.d_times on the current device (host int, caller-owned). */
+int ann_device_clock_khz(int32_t *khz);
 
 /* ann_index_free -- release everything the index holds (NULL is a no-op). */
 int ann_index_free(ann_index *ix);

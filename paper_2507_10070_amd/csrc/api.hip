@@ -205,7 +205,7 @@ int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int3
   if (L < k || L > 1024) return fail(ANN_EINVAL, "L=%d must satisfy k <= L <= 1024", L);
   if (R == 0) R = ix->R;
   if (R < 1 || R > ix->R) return fail(ANN_EINVAL, "R=%d must be in [1, %d]", R, ix->R);
-  ann_search_opts o = {1, 1, 10, 4, nullptr, nullptr, 0};
+  ann_search_opts o = {1, 1, 10, 4, nullptr, nullptr, 0, nullptr};
   if (opts) {
     o = *opts;
     if (o.hash_bits == 0) o.hash_bits = 10;
@@ -232,6 +232,7 @@ int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int3
   a.stats = o.d_stats;
   a.trace = o.d_trace;
   a.trace_cap = o.d_trace ? o.trace_cap : 0;
+  a.times = o.d_times;
   a.nq = nq; a.n = ix->n; a.slot = ix->slot;
   a.nav_stride = ix->nav_stride; a.qbytes = ix->vec_bytes; a.vec_pad = ix->vec_pad;
   a.ids_off = ix->vec_pad; a.rec_chunks = ix->rec_chunks;
@@ -243,6 +244,16 @@ int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int3
                 o.waves_per_block);
   hipError_t e = fa::launch_search(a, ix->dtype, o.delay, o.waves_per_block, (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e, "search launch");
+  return ANN_OK;
+}
+
+int ann_device_clock_khz(int32_t *khz) {
+  if (!khz) return fail(ANN_EINVAL, "khz is NULL");
+  int dev = 0, v = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, dev);
+  if (e != hipSuccess) return hip_fail(e, "wall clock rate");
+  *khz = v;
   return ANN_OK;
 }
 

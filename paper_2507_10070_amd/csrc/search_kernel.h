@@ -22,6 +22,7 @@ struct SearchArgs {
   uint32_t *out_steps;     // nq, optional
   unsigned long long *stats;  // optional: [0] steps [1] rows scored [2] record mismatches
   int32_t *trace;          // optional: nq x trace_cap selected ids, in order
+  unsigned long long *times;  // optional: nq x 2 wall-clock stamps (start, end)
   int32_t trace_cap;
   int64_t nq, n, slot;
   int32_t nav_stride, qbytes, vec_pad, ids_off, rec_chunks;

@@ -487,6 +487,7 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs A) {
   const int wave = threadIdx.x >> 6;
   const int64_t qi = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
   if (qi >= A.nq) return;
+  const unsigned long long t_start = A.times ? __builtin_amdgcn_s_memrealtime() : 0ull;
   Searcher<DT, CPL> s(A, smem + (size_t)wave * A.lds_per_wave, qi);
   s.init_entry();
   if (DELAY == 0) {
@@ -519,6 +520,10 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs A) {
     }
   }
   s.finish_query(qi);
+  if (A.times && s.lane == 0) {
+    A.times[2 * qi] = t_start;
+    A.times[2 * qi + 1] = __builtin_amdgcn_s_memrealtime();
+  }
 }
 
 template <int DT, int CPL, int DELAY>

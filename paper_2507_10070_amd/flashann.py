@@ -19,7 +19,7 @@ DTYPE_CODES = {np.dtype(np.uint8): 1, np.dtype(np.int8): 2, np.dtype(np.float32)
 TIER_HBM, TIER_HOST, TIER_FILE = 0, 1, 2
 
 EXPORTED = ["ann_index_create", "ann_index_info_get", "ann_search", "ann_index_free",
-            "ann_last_error"]
+            "ann_last_error", "ann_device_clock_khz"]
 
 
 class AnnError(RuntimeError):
@@ -32,7 +32,7 @@ class SearchOptions(ctypes.Structure):
     _fields_ = [("delay", ctypes.c_int32), ("beam_width", ctypes.c_int32),
                 ("hash_bits", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
                 ("d_stats", ctypes.c_void_p), ("d_trace", ctypes.c_void_p),
-                ("trace_cap", ctypes.c_int32)]
+                ("trace_cap", ctypes.c_int32), ("d_times", ctypes.c_void_p)]
 
 
 class IndexInfo(ctypes.Structure):
@@ -64,6 +64,8 @@ def load_library(path: str = LIB_PATH):
     lib.ann_search.restype = ctypes.c_int
     lib.ann_index_free.argtypes = [vp]
     lib.ann_index_free.restype = ctypes.c_int
+    lib.ann_device_clock_khz.argtypes = [ctypes.POINTER(ctypes.c_int32)]
+    lib.ann_device_clock_khz.restype = ctypes.c_int
     lib.ann_last_error.argtypes = []
     lib.ann_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -73,6 +75,13 @@ def load_library(path: str = LIB_PATH):
 def _check(rc):
     if rc != 0:
         raise AnnError(rc, load_library().ann_last_error().decode(errors="replace"))
+
+
+def device_clock_khz() -> int:
+    """Frequency of the device wall clock that stamps per-query times."""
+    v = ctypes.c_int32()
+    _check(load_library().ann_device_clock_khz(ctypes.byref(v)))
+    return v.value
 
 
 class Index:
@@ -123,12 +132,13 @@ class Index:
 
 def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
            beam_width: int = 1, hash_bits: int = 0, waves_per_block: int = 0, stats=None,
-           trace=None, stream=None, out=None):
+           trace=None, times=None, stream=None, out=None):
     """ann_search on torch CUDA tensors.
 
     queries: [nq, d] device tensor of the index dtype (uint8/int8/float32).
     stats: optional int64 device tensor of 3 counters (accumulated);
-    trace: optional int32 device tensor [nq, cap] receiving expanded ids.
+    trace: optional int32 device tensor [nq, cap] receiving expanded ids;
+    times: optional int64 device tensor [nq, 2] receiving start/end stamps.
     Returns (ids int32 [nq,k], dists [nq,k] int32-viewed uint32 or float32,
     steps int32-viewed uint32 [nq]), all on the device.
     """
@@ -152,7 +162,8 @@ def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
     opts = SearchOptions(delay, beam_width, hash_bits, waves_per_block,
                          stats.data_ptr() if stats is not None else None,
                          trace.data_ptr() if trace is not None else None,
-                         trace.shape[1] if trace is not None else 0)
+                         trace.shape[1] if trace is not None else 0,
+                         times.data_ptr() if times is not None else None)
     st = stream if stream is not None else torch.cuda.current_stream(dev)
     _check(load_library().ann_search(index.handle, queries.data_ptr(), nq, k, L, R,
                                      ctypes.byref(opts), ids.data_ptr(), dists.data_ptr(),
