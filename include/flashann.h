@@ -50,6 +50,19 @@ typedef enum { ANN_U8 = 1, ANN_I8 = 2, ANN_F32 = 3 } ann_dtype;
  * HBM, pinned host DRAM read by the GPU over the host link, and a file). */
 typedef enum { ANN_TIER_HBM = 0, ANN_TIER_HOST = 1, ANN_TIER_FILE = 2 } ann_tier;
 
+/* How a GPU wave obtains a record.  DIRECT: the wave loads it itself (HBM, or
+ * pinned host DRAM over the host link).  AGENT: the query-grained transport of
+ * section 4.2 -- the wave writes a request into its own slot in host memory and
+ * continues; a host agent thread reads the record (memory copy or file read)
+ * into the query's staging slot and posts a per-query completion word, which
+ * the wave checks when it needs the record.  AUTO: AGENT for ANN_TIER_FILE,
+ * DIRECT otherwise. */
+typedef enum {
+  ANN_TRANSPORT_AUTO = 0,
+  ANN_TRANSPORT_DIRECT = 1,
+  ANN_TRANSPORT_AGENT = 2
+} ann_transport;
+
 typedef struct ann_index ann_index; /* opaque, owned by the library */
 
 typedef struct {
@@ -63,6 +76,7 @@ typedef struct {
   int32_t nav_stride; /* bytes per row of the HBM navigation copy */
   int32_t rec_bytes;  /* bytes of each record fetched per step */
   int64_t hbm_bytes;  /* device memory held by the index */
+  int32_t direct_io;  /* ANN_TIER_FILE: 1 if the file is read with O_DIRECT */
 } ann_index_info;
 
 /* Search options; a NULL pointer means {delay = 1, beam_width = 1, defaults}. */
@@ -82,6 +96,9 @@ typedef struct {
   unsigned long long *d_times; /* optional device buffer, nq x 2 u64: wall-clock
                                   stamps when each query's search starts and ends,
                                   in ticks of ann_device_clock_khz() kHz */
+  int32_t transport;       /* ann_transport (0 = AUTO) */
+  uint32_t spin_limit;     /* AGENT: polls of a completion word before the query
+                              gives up with ANN_ETIMEDOUT (0 = default 2^24) */
 } ann_search_opts;
 
 /*
@@ -102,12 +119,59 @@ int ann_index_create(const void *vectors, const int32_t *adjacency, int64_t n, i
                      int32_t dtype, int32_t R, int32_t entry, int32_t slot_bytes, int32_t tier,
                      ann_index **out);
 
+/*
+ * ann_save_index -- write an index directory: meta.json (n, d, dtype, R,
+ * entry, slot_bytes), vectors.bin (n x d raw elements) and records.bin (n
+ * records of slot_bytes, the layout of ann_index_create).  Host pointers;
+ * `dir` is created if missing.  Errors: ANN_EINVAL, ANN_EIO.
+ */
+int ann_save_index(const char *dir, const void *vectors, const int32_t *adjacency, int64_t n,
+                   int32_t d, int32_t dtype, int32_t R, int32_t entry, int32_t slot_bytes);
+
+/*
+ * ann_build_index -- construct a degree-R proximity graph over `vectors`
+ * (host, n x d; deterministic for a given seed: kNN pools, alpha = 1.2
+ * pruning, reverse and long-range hub edges, connectivity repair, medoid
+ * entry) and write the index directory as ann_save_index does.  The paper
+ * inherits its graphs and does not describe their construction; this is
+ * offline and not on the search path.  Errors: ANN_EINVAL, ANN_ENOMEM, ANN_EIO.
+ */
+int ann_build_index(const void *vectors, int64_t n, int32_t d, int32_t dtype, int32_t R,
+                    int32_t slot_bytes, uint64_t seed, const char *out_dir);
+
+/*
+ * ann_load_records -- open an index directory on the GPU: the navigation copy
+ * goes to HBM; records go to HBM or pinned host DRAM (tiers HBM, HOST), or
+ * stay in the file for ANN_TIER_FILE (read per request by the agent, with
+ * O_DIRECT when slot_bytes is a multiple of 512 and the file system allows).
+ * `records_path` overrides <dir>/records.bin (NULL = default).
+ * Errors: ANN_EINVAL, ANN_EIO, ANN_ENOMEM, ANN_ENODEV.
+ */
+int ann_load_records(const char *dir, int32_t tier, const char *records_path, ann_index **out);
+
+/*
+ * ann_agent_configure -- settings of the host agent used by the AGENT
+ * transport: `threads` (0 = hardware threads - 2, at most 32).  The other
+ * arguments inject faults for tests, -1 = off: requests for `delay_node`
+ * complete after `delay_us` microseconds (a straggler), requests for
+ * `fail_node` complete with a read error (ANN_EIO for that query), requests
+ * for `drop_node` never complete (ANN_ETIMEDOUT after spin_limit polls).
+ */
+int ann_agent_configure(ann_index *ix, int32_t threads, int32_t delay_node, int32_t delay_us,
+                        int32_t fail_node, int32_t drop_node);
+
+/* ann_agent_stats -- cumulative agent counters: requests served, bytes copied
+ * or read, failed reads (host integers, caller-owned). */
+int ann_agent_stats(const ann_index *ix, uint64_t *requests, uint64_t *bytes, uint64_t *errors);
+
 /* ann_index_info -- sizes and layout of an index (host struct, caller-owned). */
 int ann_index_info_get(const ann_index *ix, ann_index_info *out);
 
 /*
- * ann_search -- batched top-k search, stream-ordered on `hip_stream` (a
- * hipStream_t; NULL = default stream).  One GPU wavefront runs each query.
+ * ann_search -- batched top-k search on `hip_stream` (a hipStream_t; NULL =
+ * default stream).  One GPU wavefront runs each query.  DIRECT transport:
+ * stream-ordered, returns after the launch.  AGENT transport: returns after
+ * the search has completed (the agent serves the kernel while it runs).
  *   d_queries  device, nq x d elements of the index dtype
  *   k, L       results per query and candidate-list size, 1 <= k <= L <= 1024
  *   R          neighbours used per expansion, 1 <= R <= index R (0 = index R)
@@ -115,8 +179,10 @@ int ann_index_info_get(const ann_index *ix, ann_index_info *out);
  *   d_dists    device, nq x k: uint32 (u8/i8, padding 0xFFFFFFFF) or float
  *              (f32, padding +inf)
  *   d_steps    device, nq uint32 expansions per query, optional (NULL)
- * Returns after the launch; buffers must stay valid until the stream syncs.
- * Errors: ANN_EINVAL before any device work; ANN_ENOTSUP for beam_width > 1.
+ * Buffers must stay valid until the stream syncs.
+ * Errors: ANN_EINVAL before any device work; ANN_ENOTSUP for delay > 1 or
+ * beam_width > 1; AGENT: ANN_EIO / ANN_ETIMEDOUT when a record read failed or
+ * never completed (those queries return ids -1; the others are valid).
  */
 int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int32_t L, int32_t R,
                const ann_search_opts *opts, int32_t *d_ids, void *d_dists, uint32_t *d_steps,

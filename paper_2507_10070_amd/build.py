@@ -7,7 +7,9 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libflashann.so")
-SOURCES = ["search_kernel.hip", "api.hip"]
+SOURCES = ["search_kernel.hip", "api.hip", "agent.cpp",
+           # the graph builder of the input generators, for ann_build_index
+           os.path.join("..", "..", "synth", "csrc", "graph_build.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          # no packed fp32 instructions in device code

@@ -1,0 +1,90 @@
+// agent.h -- host side of the query-grained record transport (FlashANNS
+// section 4.2): each query owns a request slot that its GPU wave writes and a
+// completion word that a host agent thread writes; no query ever waits for
+// another query's reads.
+//
+// Plain C++ (no HIP): the memory it works on is handed in by the caller, so
+// the protocol can be exercised on the CPU with a thread standing in for the
+// GPU.
+#pragma once
+#include <stdint.h>
+
+#include <atomic>
+#include <thread>
+#include <vector>
+
+namespace fa {
+
+// One query's request slots, written by its GPU wave: request s is the
+// 64-bit word slot[s & 1] = (node << 32) | s, stored in one piece, so the
+// agent never sees a sequence number without its node.  At most two requests
+// of a query are outstanding (strict or one-step-stale schedule), and a wave
+// reuses a slot only after consuming the request that held it.
+struct alignas(16) AgentRequest {
+  uint64_t slot[2];
+};
+
+// Completion words: two per query, cpl[2q + (s & 1)] = s when request s has
+// been staged, s | kCplError when its read failed.  One word per in-flight
+// slot keeps each request's status until its wave has consumed it.
+constexpr uint32_t kCplError = 0x80000000u;
+
+// Fault injection for tests (host-forced conditions only).
+struct AgentFaults {
+  int32_t delay_node = -1;   // requests for this node complete after delay_us
+  int32_t delay_us = 0;
+  int32_t fail_node = -1;    // requests for this node complete with kCplError
+  int32_t drop_node = -1;    // requests for this node never complete
+};
+
+struct AgentStats {
+  std::atomic<uint64_t> requests{0};
+  std::atomic<uint64_t> bytes{0};
+  std::atomic<uint64_t> errors{0};
+  std::atomic<int> last_errno{0};
+};
+
+class Agent {
+ public:
+  // Record source: `mem` (slot-strided records in host memory) or `fd`
+  // (a file of slot-strided records; `direct` if opened with O_DIRECT).
+  // Each request copies `copy_bytes` (the useful record prefix); file reads
+  // are `io_bytes` long (copy_bytes rounded up to the device block).
+  Agent(const uint8_t *mem, int fd, bool direct, int64_t slot, int32_t copy_bytes,
+        int32_t io_bytes, int threads);
+  ~Agent();
+
+  // Serve the requests of `nq` queries until disarm().  `cpl` holds 2 x nq
+  // completion words and `stage` two staging slots of `stage_stride` bytes
+  // per query (slot s & 1 for request s).  The caller zeroes req/cpl.
+  void arm(AgentRequest *req, uint32_t *cpl, uint8_t *stage, int64_t nq, int64_t stage_stride);
+  // Stop serving; returns once no agent thread touches the arrays any more.
+  void disarm();
+
+  AgentFaults faults;  // set while disarmed
+  AgentStats stats;
+  int threads() const { return (int)workers_.size(); }
+
+ private:
+  void run(int t);
+  bool serve(int64_t q, uint32_t seq, uint32_t node, uint8_t *bounce);
+
+  const uint8_t *mem_;
+  int fd_;
+  bool direct_;
+  int64_t slot_;
+  int32_t copy_bytes_, io_bytes_;
+
+  int nthreads_ = 1;
+  std::vector<std::thread> workers_;
+  std::atomic<bool> quit_{false};
+  std::atomic<bool> armed_{false};
+  std::atomic<int> busy_{0};            // workers inside a serving pass
+  AgentRequest *req_ = nullptr;
+  uint32_t *cpl_ = nullptr;
+  uint8_t *stage_ = nullptr;
+  int64_t nq_ = 0, stage_stride_ = 0;
+  std::vector<uint32_t> done_;          // per query: last request served
+};
+
+}  // namespace fa

@@ -1,28 +1,56 @@
-// api.hip -- C ABI of the search library: index construction in device and
-// pinned host memory, argument validation and kernel dispatch.
+// api.hip -- C ABI of the search library: index construction (HBM navigation
+// copy + record store in HBM, pinned host DRAM or a file), the on-disk index
+// format, the host agent of the query-grained transport, argument validation
+// and kernel dispatch.
+#include <fcntl.h>
 #include <hip/hip_runtime.h>
+#include <sys/stat.h>
+#include <unistd.h>
 
+#include <algorithm>
+#include <cerrno>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/flashann.h"
+#include "agent.h"
 #include "search_kernel.h"
+
+extern "C" int synth_build_graph(const void *base, int64_t n, int32_t d, int32_t dtype, int32_t R,
+                                 uint64_t seed, int32_t threads, int32_t pool, float alpha,
+                                 int32_t n_hubs, int64_t exact_limit, int32_t *adj,
+                                 int32_t *entry_out);
+
+static_assert(sizeof(fa::AgentRequest) == 16, "request slot layout shared with the kernel");
 
 struct ann_index {
   int64_t n = 0;
   int32_t d = 0, dtype = 0, R = 0, entry = 0, slot = 0, tier = 0;
   int32_t elem = 1, vec_bytes = 0, vec_pad = 0, nav_stride = 0, rec_bytes = 0, rec_chunks = 0;
   uint8_t *nav = nullptr;       // device, n x nav_stride
-  uint8_t *rec_dev = nullptr;   // device-visible record base
+  uint8_t *rec_dev = nullptr;   // device-visible record base (HBM / HOST tiers)
   uint8_t *rec_hbm = nullptr;   // hipMalloc'd records (tier HBM)
   void *rec_host = nullptr;     // hipHostMalloc'd records (tier HOST)
+  int fd = -1;                  // record file (tier FILE)
+  bool direct_io = false;
   int device = 0;
   int64_t hbm_bytes = 0;
+  // query-grained transport
+  int agent_threads = 0;
+  fa::AgentFaults faults;
+  std::unique_ptr<fa::Agent> agent;
+  fa::AgentRequest *req = nullptr;  // fine-grained pinned host
+  uint32_t *cpl = nullptr;          // fine-grained pinned host
+  uint8_t *stage = nullptr;         // fine-grained pinned host
+  int32_t *d_status = nullptr;      // device
+  int64_t tcap = 0, stage_stride = 0;
 };
 
 namespace {
@@ -50,24 +78,217 @@ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 int elem_bytes(int32_t dt) { return dt == ANN_F32 ? 4 : 1; }
 
+void free_transport(ann_index *ix) {
+  ix->agent.reset();
+  if (ix->req) (void)hipHostFree(ix->req);
+  if (ix->cpl) (void)hipHostFree(ix->cpl);
+  if (ix->stage) (void)hipHostFree(ix->stage);
+  if (ix->d_status) (void)hipFree(ix->d_status);
+  ix->req = nullptr;
+  ix->cpl = nullptr;
+  ix->stage = nullptr;
+  ix->d_status = nullptr;
+  ix->tcap = 0;
+}
+
 void release(ann_index *ix) {
   if (!ix) return;
+  free_transport(ix);
   if (ix->nav) (void)hipFree(ix->nav);
   if (ix->rec_hbm) (void)hipFree(ix->rec_hbm);
   if (ix->rec_host) (void)hipHostFree(ix->rec_host);
+  if (ix->fd >= 0) close(ix->fd);
   delete ix;
 }
 
-// Pack records [i0, i1) into `dst` (slot bytes each): vector, zero pad to
-// 16 B, R int32 ids, zero pad to the slot.
-void pack_records(const ann_index *ix, const uint8_t *vecs, const int32_t *adj, int64_t i0,
-                  int64_t i1, uint8_t *dst) {
-  for (int64_t i = i0; i < i1; i++) {
-    uint8_t *r = dst + (i - i0) * ix->slot;
-    std::memcpy(r, vecs + i * ix->vec_bytes, ix->vec_bytes);
-    std::memset(r + ix->vec_bytes, 0, ix->slot - ix->vec_bytes);
-    std::memcpy(r + ix->vec_pad, adj + i * ix->R, 4 * (size_t)ix->R);
+// Sizes derived from (n, d, dtype, R, slot); validates them.
+int init_layout(ann_index *ix, int64_t n, int32_t d, int32_t dtype, int32_t R, int32_t entry,
+                int32_t slot_bytes) {
+  if (n < 1 || n > 0x7FFFFFFFll) return fail(ANN_EINVAL, "n=%lld out of range", (long long)n);
+  if (d < 1) return fail(ANN_EINVAL, "d=%d", d);
+  if (dtype != ANN_U8 && dtype != ANN_I8 && dtype != ANN_F32)
+    return fail(ANN_EINVAL, "dtype=%d", dtype);
+  if (R < 1) return fail(ANN_EINVAL, "R=%d", R);
+  if (entry < 0 || entry >= n) return fail(ANN_EINVAL, "entry=%d not in [0,n)", entry);
+  ix->n = n; ix->d = d; ix->dtype = dtype; ix->R = R; ix->entry = entry; ix->slot = slot_bytes;
+  ix->elem = elem_bytes(dtype);
+  ix->vec_bytes = d * ix->elem;
+  ix->vec_pad = (int32_t)round_up(ix->vec_bytes, 16);
+  ix->nav_stride = (int32_t)round_up(ix->vec_bytes, 128);
+  ix->rec_bytes = (int32_t)round_up(ix->vec_pad + 4 * (int64_t)R, 16);
+  ix->rec_chunks = ix->rec_bytes / 16;
+  if (ix->nav_stride > 512)
+    return fail(ANN_ENOTSUP, "vector of %d B exceeds the 512 B row limit", ix->vec_bytes);
+  if (ix->rec_bytes > 1024)
+    return fail(ANN_ENOTSUP, "record of %d B exceeds the 1024 B fetch limit", ix->rec_bytes);
+  if (slot_bytes < ix->vec_pad + 4 * R || slot_bytes % 16 != 0)
+    return fail(ANN_EINVAL, "slot_bytes=%d must be a multiple of 16 and >= %d", slot_bytes,
+                ix->vec_pad + 4 * R);
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(ANN_ENODEV, "no GPU visible");
+  (void)hipGetDevice(&ix->device);
+  return ANN_OK;
+}
+
+// Navigation copy in HBM: rows zero-padded to nav_stride.
+int build_nav(ann_index *ix, const uint8_t *vecs) {
+  const int64_t n = ix->n;
+  const int64_t nav_bytes = n * (int64_t)ix->nav_stride;
+  hipError_t e = hipMalloc(&ix->nav, nav_bytes);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(navigation copy)");
+  ix->hbm_bytes += nav_bytes;
+  const int64_t chunk_rows = std::max<int64_t>(1, (64ll << 20) / ix->nav_stride);
+  std::vector<uint8_t> buf((size_t)(std::min(n, chunk_rows) * ix->nav_stride));
+  for (int64_t i0 = 0; i0 < n; i0 += chunk_rows) {
+    const int64_t i1 = std::min(n, i0 + chunk_rows);
+    std::memset(buf.data(), 0, buf.size());
+    for (int64_t i = i0; i < i1; i++)
+      std::memcpy(buf.data() + (i - i0) * ix->nav_stride, vecs + i * ix->vec_bytes, ix->vec_bytes);
+    e = hipMemcpy(ix->nav + i0 * ix->nav_stride, buf.data(), (i1 - i0) * ix->nav_stride,
+                  hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(navigation copy)");
   }
+  return ANN_OK;
+}
+
+// Record layout: vector, zero pad to 16 B, R int32 ids, zero pad to the slot
+// (paper section 3, C3: the node is its full vector plus its neighbour ids).
+void pack_records(int64_t i0, int64_t i1, int32_t vec_bytes, int32_t vec_pad, int32_t R,
+                  int32_t slot, const uint8_t *vecs, const int32_t *adj, uint8_t *dst) {
+  for (int64_t i = i0; i < i1; i++) {
+    uint8_t *r = dst + (i - i0) * slot;
+    std::memcpy(r, vecs + i * vec_bytes, vec_bytes);
+    std::memset(r + vec_bytes, 0, slot - vec_bytes);
+    std::memcpy(r + vec_pad, adj + i * R, 4 * (size_t)R);
+  }
+}
+
+// Record source for the HBM / HOST tiers: either packed from arrays or read
+// from a records file (fd, already in the layout above).
+struct RecordSource {
+  const uint8_t *vecs = nullptr;
+  const int32_t *adj = nullptr;
+  int fd = -1;
+  int fill(const ann_index *ix, int64_t i0, int64_t i1, uint8_t *dst) const {
+    if (fd < 0) {
+      pack_records(i0, i1, ix->vec_bytes, ix->vec_pad, ix->R, ix->slot, vecs, adj, dst);
+      return ANN_OK;
+    }
+    const int64_t want = (i1 - i0) * ix->slot;
+    int64_t got = 0;
+    while (got < want) {
+      const ssize_t r = pread(fd, dst + got, (size_t)(want - got), (off_t)(i0 * ix->slot + got));
+      if (r <= 0)
+        return fail(ANN_EIO, "records file read failed at %lld", (long long)(i0 * ix->slot + got));
+      got += r;
+    }
+    return ANN_OK;
+  }
+};
+
+int build_records(ann_index *ix, const RecordSource &src) {
+  const int64_t n = ix->n, slot = ix->slot, total = n * slot;
+  hipError_t e;
+  if (ix->tier == ANN_TIER_HBM) {
+    if ((e = hipMalloc(&ix->rec_hbm, total)) != hipSuccess) return hip_fail(e, "hipMalloc(records)");
+    ix->hbm_bytes += total;
+    const int64_t chunk_rows = std::max<int64_t>(1, (64ll << 20) / slot);
+    std::vector<uint8_t> buf((size_t)(std::min(n, chunk_rows) * slot));
+    for (int64_t i0 = 0; i0 < n; i0 += chunk_rows) {
+      const int64_t i1 = std::min(n, i0 + chunk_rows);
+      int rc = src.fill(ix, i0, i1, buf.data());
+      if (rc) return rc;
+      if ((e = hipMemcpy(ix->rec_hbm + i0 * slot, buf.data(), (i1 - i0) * slot,
+                         hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy(records)");
+    }
+    ix->rec_dev = ix->rec_hbm;
+    return ANN_OK;
+  }
+  // Pinned host DRAM mapped into the GPU address space, non-coherent
+  // (coarse-grained): records are immutable while kernels run.
+  if ((e = hipHostMalloc(&ix->rec_host, total, hipHostMallocNonCoherent)) != hipSuccess)
+    return hip_fail(e, "hipHostMalloc(records)");
+  int rc = src.fill(ix, 0, n, (uint8_t *)ix->rec_host);
+  if (rc) return rc;
+  void *dp = nullptr;
+  if ((e = hipHostGetDevicePointer(&dp, ix->rec_host, 0)) != hipSuccess)
+    return hip_fail(e, "hipHostGetDevicePointer(records)");
+  ix->rec_dev = (uint8_t *)dp;
+  return ANN_OK;
+}
+
+int default_agent_threads() {
+  const int hw = (int)std::thread::hardware_concurrency();
+  return std::max(1, std::min(32, hw - 2));
+}
+
+// Transport buffers for nq queries and the agent itself.
+int ensure_transport(ann_index *ix, int64_t nq) {
+  const bool file = ix->tier == ANN_TIER_FILE;
+  const int32_t io = file && ix->direct_io ? (int32_t)round_up(ix->rec_bytes, 512) : ix->rec_bytes;
+  if (!ix->agent) {
+    const int t = ix->agent_threads > 0 ? ix->agent_threads : default_agent_threads();
+    ix->agent.reset(new fa::Agent(file ? nullptr : (const uint8_t *)ix->rec_host, ix->fd,
+                                  ix->direct_io, ix->slot, ix->rec_bytes, io, t));
+  }
+  if (nq <= ix->tcap) return ANN_OK;
+  fa::Agent *keep = ix->agent.release();
+  free_transport(ix);
+  ix->agent.reset(keep);
+  const int64_t cap = std::max<int64_t>(nq, 1024);
+  ix->stage_stride = round_up(io, 512);
+  hipError_t e;
+  const unsigned fl = hipHostMallocCoherent | hipHostMallocMapped;
+  if ((e = hipHostMalloc((void **)&ix->req, sizeof(fa::AgentRequest) * cap, fl)) != hipSuccess ||
+      (e = hipHostMalloc((void **)&ix->cpl, sizeof(uint32_t) * 2 * cap, fl)) != hipSuccess ||
+      (e = hipHostMalloc((void **)&ix->stage, ix->stage_stride * 2 * cap, fl)) != hipSuccess ||
+      (e = hipMalloc(&ix->d_status, sizeof(int32_t) * cap)) != hipSuccess) {
+    free_transport(ix);
+    return hip_fail(e, "transport buffers");
+  }
+  ix->tcap = cap;
+  return ANN_OK;
+}
+
+template <typename T>
+T *dev_ptr(T *host) {
+  void *dp = nullptr;
+  return hipHostGetDevicePointer(&dp, host, 0) == hipSuccess ? (T *)dp : nullptr;
+}
+
+const char *dtype_name(int32_t dt) { return dt == ANN_U8 ? "u8" : dt == ANN_I8 ? "i8" : "f32"; }
+
+// Minimal reader of the flat meta.json written by ann_save_index.
+bool meta_int(const std::string &s, const char *key, int64_t *out) {
+  const std::string k = std::string("\"") + key + "\"";
+  size_t p = s.find(k);
+  if (p == std::string::npos) return false;
+  p = s.find(':', p + k.size());
+  if (p == std::string::npos) return false;
+  char *end = nullptr;
+  const long long v = std::strtoll(s.c_str() + p + 1, &end, 10);
+  if (end == s.c_str() + p + 1) return false;
+  *out = v;
+  return true;
+}
+
+bool meta_dtype(const std::string &s, int32_t *out) {
+  size_t p = s.find("\"dtype\"");
+  if (p == std::string::npos) return false;
+  p = s.find('"', s.find(':', p) + 1);
+  if (p == std::string::npos) return false;
+  const std::string v = s.substr(p + 1, s.find('"', p + 1) - p - 1);
+  *out = v == "u8" ? ANN_U8 : v == "i8" ? ANN_I8 : v == "f32" ? ANN_F32 : 0;
+  return *out != 0;
+}
+
+int write_all(const std::string &path, const void *p, int64_t bytes) {
+  FILE *f = std::fopen(path.c_str(), "wb");
+  if (!f) return fail(ANN_EIO, "cannot create %s: %s", path.c_str(), std::strerror(errno));
+  const bool ok = bytes == 0 || std::fwrite(p, 1, (size_t)bytes, f) == (size_t)bytes;
+  if (std::fclose(f) != 0 || !ok) return fail(ANN_EIO, "write of %s failed", path.c_str());
+  return ANN_OK;
 }
 
 }  // namespace
@@ -82,107 +303,154 @@ int ann_index_create(const void *vectors, const int32_t *adjacency, int64_t n, i
   if (!out) return fail(ANN_EINVAL, "out is NULL");
   *out = nullptr;
   if (!vectors || !adjacency) return fail(ANN_EINVAL, "vectors/adjacency is NULL");
-  if (n < 1 || n > 0x7FFFFFFFll) return fail(ANN_EINVAL, "n=%lld out of range", (long long)n);
-  if (d < 1) return fail(ANN_EINVAL, "d=%d", d);
-  if (dtype != ANN_U8 && dtype != ANN_I8 && dtype != ANN_F32)
-    return fail(ANN_EINVAL, "dtype=%d", dtype);
-  if (R < 1) return fail(ANN_EINVAL, "R=%d", R);
-  if (entry < 0 || entry >= n) return fail(ANN_EINVAL, "entry=%d not in [0,n)", entry);
   if (tier != ANN_TIER_HBM && tier != ANN_TIER_HOST)
-    return fail(ANN_EINVAL, "tier=%d not supported by ann_index_create", tier);
-
+    return fail(ANN_EINVAL, "tier=%d: ann_index_create takes HBM or HOST (files: ann_load_records)",
+                tier);
   ann_index *ix = new (std::nothrow) ann_index();
   if (!ix) return fail(ANN_ENOMEM, "handle");
-  ix->n = n; ix->d = d; ix->dtype = dtype; ix->R = R; ix->entry = entry;
-  ix->slot = slot_bytes; ix->tier = tier;
-  ix->elem = elem_bytes(dtype);
-  ix->vec_bytes = d * ix->elem;
-  ix->vec_pad = (int32_t)round_up(ix->vec_bytes, 16);
-  ix->nav_stride = (int32_t)round_up(ix->vec_bytes, 128);
-  ix->rec_bytes = (int32_t)round_up(ix->vec_pad + 4 * (int64_t)R, 16);
-  ix->rec_chunks = ix->rec_bytes / 16;
-  if (ix->nav_stride > 512) {
-    release(ix);
-    return fail(ANN_ENOTSUP, "vector of %d B exceeds the 512 B row limit", d * elem_bytes(dtype));
+  ix->tier = tier;
+  int rc = init_layout(ix, n, d, dtype, R, entry, slot_bytes);
+  if (!rc) rc = build_nav(ix, (const uint8_t *)vectors);
+  if (!rc) {
+    RecordSource src;
+    src.vecs = (const uint8_t *)vectors;
+    src.adj = adjacency;
+    rc = build_records(ix, src);
   }
-  if (ix->rec_bytes > 1024) {
+  if (rc) {
     release(ix);
-    return fail(ANN_ENOTSUP, "record of %d B exceeds the 1024 B fetch limit", ix->rec_bytes);
+    return rc;
   }
-  if (slot_bytes < ix->vec_pad + 4 * R || slot_bytes % 16 != 0) {
-    release(ix);
-    return fail(ANN_EINVAL, "slot_bytes=%d must be a multiple of 16 and >= %d", slot_bytes,
-                ix->vec_pad + 4 * R);
-  }
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
-    release(ix);
-    return fail(ANN_ENODEV, "no GPU visible");
-  }
-  (void)hipGetDevice(&ix->device);
+  *out = ix;
+  return ANN_OK;
+}
 
-  hipError_t e;
-  // navigation copy: rows zero-padded to nav_stride
-  const int64_t nav_bytes = n * (int64_t)ix->nav_stride;
-  if ((e = hipMalloc(&ix->nav, nav_bytes)) != hipSuccess) {
-    release(ix);
-    return hip_fail(e, "hipMalloc(navigation copy)");
+int ann_save_index(const char *dir, const void *vectors, const int32_t *adjacency, int64_t n,
+                   int32_t d, int32_t dtype, int32_t R, int32_t entry, int32_t slot_bytes) {
+  if (!dir || !vectors || !adjacency) return fail(ANN_EINVAL, "NULL argument");
+  if (n < 1 || d < 1 || R < 1 || entry < 0 || entry >= n ||
+      (dtype != ANN_U8 && dtype != ANN_I8 && dtype != ANN_F32))
+    return fail(ANN_EINVAL, "bad sizes");
+  const int32_t vb = d * elem_bytes(dtype), vp = (int32_t)round_up(vb, 16);
+  if (slot_bytes < vp + 4 * R || slot_bytes % 16 != 0)
+    return fail(ANN_EINVAL, "slot_bytes=%d must be a multiple of 16 and >= %d", slot_bytes, vp + 4 * R);
+  if (mkdir(dir, 0755) != 0 && errno != EEXIST)
+    return fail(ANN_EIO, "cannot create %s: %s", dir, std::strerror(errno));
+  const std::string base(dir);
+  char meta[512];
+  snprintf(meta, sizeof meta,
+           "{\"format\": \"flashann-1\", \"n\": %lld, \"d\": %d, \"dtype\": \"%s\", \"R\": %d, "
+           "\"entry\": %d, \"slot_bytes\": %d}\n",
+           (long long)n, d, dtype_name(dtype), R, entry, slot_bytes);
+  int rc = write_all(base + "/meta.json", meta, (int64_t)strlen(meta));
+  if (!rc) rc = write_all(base + "/vectors.bin", vectors, n * vb);
+  if (rc) return rc;
+  FILE *f = std::fopen((base + "/records.bin").c_str(), "wb");
+  if (!f) return fail(ANN_EIO, "cannot create records.bin: %s", std::strerror(errno));
+  const int64_t chunk = std::max<int64_t>(1, (32ll << 20) / slot_bytes);
+  std::vector<uint8_t> buf((size_t)(std::min(n, chunk) * slot_bytes));
+  bool ok = true;
+  for (int64_t i0 = 0; i0 < n && ok; i0 += chunk) {
+    const int64_t i1 = std::min(n, i0 + chunk);
+    pack_records(i0, i1, vb, vp, R, slot_bytes, (const uint8_t *)vectors, adjacency, buf.data());
+    const size_t bytes = (size_t)((i1 - i0) * slot_bytes);
+    ok = std::fwrite(buf.data(), 1, bytes, f) == bytes;
   }
-  ix->hbm_bytes += nav_bytes;
-  const uint8_t *vecs = (const uint8_t *)vectors;
+  if (std::fclose(f) != 0 || !ok) return fail(ANN_EIO, "write of records.bin failed");
+  return ANN_OK;
+}
+
+int ann_build_index(const void *vectors, int64_t n, int32_t d, int32_t dtype, int32_t R,
+                    int32_t slot_bytes, uint64_t seed, const char *out_dir) {
+  if (!vectors || !out_dir) return fail(ANN_EINVAL, "NULL argument");
+  if (n < 1 || n > 0x7FFFFFFFll || d < 1 || R < 1 ||
+      (dtype != ANN_U8 && dtype != ANN_I8 && dtype != ANN_F32))
+    return fail(ANN_EINVAL, "bad sizes");
+  std::vector<int32_t> adj;
+  try {
+    adj.resize((size_t)(n * R));
+  } catch (...) {
+    return fail(ANN_ENOMEM, "adjacency of %lld x %d", (long long)n, R);
+  }
+  int32_t entry = -1;
+  const int threads = std::max(1, std::min(64, (int)std::thread::hardware_concurrency()));
+  const int64_t hubs = std::min<int64_t>(std::max<int64_t>(64, n / 1000), 4096);
+  const int rc = synth_build_graph(vectors, n, d, dtype, R, seed, threads, std::max(2 * R, 64),
+                                   1.2f, (int32_t)hubs, 20000, adj.data(), &entry);
+  if (rc) return fail(ANN_EINVAL, "graph construction failed (%d)", rc);
+  return ann_save_index(out_dir, vectors, adj.data(), n, d, dtype, R, entry, slot_bytes);
+}
+
+int ann_load_records(const char *dir, int32_t tier, const char *records_path, ann_index **out) {
+  if (!out || !dir) return fail(ANN_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (tier != ANN_TIER_HBM && tier != ANN_TIER_HOST && tier != ANN_TIER_FILE)
+    return fail(ANN_EINVAL, "tier=%d", tier);
+  const std::string base(dir);
+  std::string meta;
   {
-    const int64_t chunk_rows = std::max<int64_t>(1, (64ll << 20) / ix->nav_stride);
-    std::vector<uint8_t> buf((size_t)(std::min(n, chunk_rows) * ix->nav_stride));
-    for (int64_t i0 = 0; i0 < n; i0 += chunk_rows) {
-      const int64_t i1 = std::min(n, i0 + chunk_rows);
-      std::memset(buf.data(), 0, buf.size());
-      for (int64_t i = i0; i < i1; i++)
-        std::memcpy(buf.data() + (i - i0) * ix->nav_stride, vecs + i * ix->vec_bytes,
-                    ix->vec_bytes);
-      e = hipMemcpy(ix->nav + i0 * ix->nav_stride, buf.data(), (i1 - i0) * ix->nav_stride,
-                    hipMemcpyHostToDevice);
-      if (e != hipSuccess) {
-        release(ix);
-        return hip_fail(e, "hipMemcpy(navigation copy)");
+    FILE *f = std::fopen((base + "/meta.json").c_str(), "rb");
+    if (!f) return fail(ANN_EIO, "cannot open %s/meta.json", dir);
+    char buf[1024];
+    const size_t r = std::fread(buf, 1, sizeof buf - 1, f);
+    std::fclose(f);
+    meta.assign(buf, r);
+  }
+  int64_t n, d, R, entry, slot;
+  int32_t dtype;
+  if (!meta_int(meta, "n", &n) || !meta_int(meta, "d", &d) || !meta_int(meta, "R", &R) ||
+      !meta_int(meta, "entry", &entry) || !meta_int(meta, "slot_bytes", &slot) ||
+      !meta_dtype(meta, &dtype))
+    return fail(ANN_EINVAL, "malformed %s/meta.json", dir);
+  ann_index *ix = new (std::nothrow) ann_index();
+  if (!ix) return fail(ANN_ENOMEM, "handle");
+  ix->tier = tier;
+  int rc = init_layout(ix, n, (int32_t)d, dtype, (int32_t)R, (int32_t)entry, (int32_t)slot);
+  std::vector<uint8_t> vecs;
+  if (!rc) {
+    FILE *f = std::fopen((base + "/vectors.bin").c_str(), "rb");
+    if (!f) {
+      rc = fail(ANN_EIO, "cannot open %s/vectors.bin", dir);
+    } else {
+      try {
+        vecs.resize((size_t)(n * ix->vec_bytes));
+      } catch (...) {
+        rc = fail(ANN_ENOMEM, "vectors");
       }
+      if (!rc && std::fread(vecs.data(), 1, vecs.size(), f) != vecs.size())
+        rc = fail(ANN_EIO, "short read of vectors.bin");
+      std::fclose(f);
     }
   }
-  // records
-  const int64_t rec_total = n * (int64_t)slot_bytes;
-  if (tier == ANN_TIER_HBM) {
-    if ((e = hipMalloc(&ix->rec_hbm, rec_total)) != hipSuccess) {
-      release(ix);
-      return hip_fail(e, "hipMalloc(records)");
+  if (!rc) rc = build_nav(ix, vecs.data());
+  vecs.clear();
+  vecs.shrink_to_fit();
+  const std::string rpath = records_path ? std::string(records_path) : base + "/records.bin";
+  if (!rc) {
+    struct stat st;
+    if (stat(rpath.c_str(), &st) != 0 || st.st_size < n * slot)
+      rc = fail(ANN_EIO, "%s missing or shorter than %lld records", rpath.c_str(), (long long)n);
+  }
+  if (!rc && tier == ANN_TIER_FILE) {
+    // O_DIRECT when the slot is a multiple of the 512 B sector and the file
+    // system accepts it; buffered reads otherwise.
+    ix->fd = slot % 512 == 0 ? open(rpath.c_str(), O_RDONLY | O_DIRECT) : -1;
+    ix->direct_io = ix->fd >= 0;
+    if (ix->fd < 0) ix->fd = open(rpath.c_str(), O_RDONLY);
+    if (ix->fd < 0) rc = fail(ANN_EIO, "cannot open %s: %s", rpath.c_str(), std::strerror(errno));
+  } else if (!rc) {
+    RecordSource src;
+    src.fd = open(rpath.c_str(), O_RDONLY);
+    if (src.fd < 0) {
+      rc = fail(ANN_EIO, "cannot open %s", rpath.c_str());
+    } else {
+      rc = build_records(ix, src);
+      close(src.fd);
     }
-    ix->hbm_bytes += rec_total;
-    const int64_t chunk_rows = std::max<int64_t>(1, (64ll << 20) / slot_bytes);
-    std::vector<uint8_t> buf((size_t)(std::min(n, chunk_rows) * slot_bytes));
-    for (int64_t i0 = 0; i0 < n; i0 += chunk_rows) {
-      const int64_t i1 = std::min(n, i0 + chunk_rows);
-      pack_records(ix, vecs, adjacency, i0, i1, buf.data());
-      e = hipMemcpy(ix->rec_hbm + i0 * slot_bytes, buf.data(), (i1 - i0) * slot_bytes,
-                    hipMemcpyHostToDevice);
-      if (e != hipSuccess) {
-        release(ix);
-        return hip_fail(e, "hipMemcpy(records)");
-      }
-    }
-    ix->rec_dev = ix->rec_hbm;
-  } else {
-    // Pinned host DRAM, mapped into the GPU address space.  Non-coherent
-    // (coarse-grained): records are immutable while kernels run, so the GPU
-    // may cache them.
-    if ((e = hipHostMalloc(&ix->rec_host, rec_total, hipHostMallocNonCoherent)) != hipSuccess) {
-      release(ix);
-      return hip_fail(e, "hipHostMalloc(records)");
-    }
-    pack_records(ix, vecs, adjacency, 0, n, (uint8_t *)ix->rec_host);
-    void *dp = nullptr;
-    if ((e = hipHostGetDevicePointer(&dp, ix->rec_host, 0)) != hipSuccess) {
-      release(ix);
-      return hip_fail(e, "hipHostGetDevicePointer(records)");
-    }
-    ix->rec_dev = (uint8_t *)dp;
+  }
+  if (rc) {
+    release(ix);
+    return rc;
   }
   *out = ix;
   return ANN_OK;
@@ -193,6 +461,28 @@ int ann_index_info_get(const ann_index *ix, ann_index_info *out) {
   out->n = ix->n; out->d = ix->d; out->dtype = ix->dtype; out->R = ix->R;
   out->entry = ix->entry; out->slot_bytes = ix->slot; out->tier = ix->tier;
   out->nav_stride = ix->nav_stride; out->rec_bytes = ix->rec_bytes; out->hbm_bytes = ix->hbm_bytes;
+  out->direct_io = ix->direct_io ? 1 : 0;
+  return ANN_OK;
+}
+
+int ann_agent_configure(ann_index *ix, int32_t threads, int32_t delay_node, int32_t delay_us,
+                        int32_t fail_node, int32_t drop_node) {
+  if (!ix) return fail(ANN_EINVAL, "index is NULL");
+  if (threads < 0 || threads > 256 || delay_us < 0) return fail(ANN_EINVAL, "bad agent settings");
+  if (threads != ix->agent_threads) ix->agent.reset();  // recreated on next use
+  ix->agent_threads = threads;
+  ix->faults.delay_node = delay_node;
+  ix->faults.delay_us = delay_us;
+  ix->faults.fail_node = fail_node;
+  ix->faults.drop_node = drop_node;
+  return ANN_OK;
+}
+
+int ann_agent_stats(const ann_index *ix, uint64_t *requests, uint64_t *bytes, uint64_t *errors) {
+  if (!ix || !requests || !bytes || !errors) return fail(ANN_EINVAL, "NULL argument");
+  *requests = ix->agent ? ix->agent->stats.requests.load() : 0;
+  *bytes = ix->agent ? ix->agent->stats.bytes.load() : 0;
+  *errors = ix->agent ? ix->agent->stats.errors.load() : 0;
   return ANN_OK;
 }
 
@@ -205,12 +495,12 @@ int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int3
   if (L < k || L > 1024) return fail(ANN_EINVAL, "L=%d must satisfy k <= L <= 1024", L);
   if (R == 0) R = ix->R;
   if (R < 1 || R > ix->R) return fail(ANN_EINVAL, "R=%d must be in [1, %d]", R, ix->R);
-  ann_search_opts o = {1, 1, 10, 4, nullptr, nullptr, 0, nullptr};
-  if (opts) {
-    o = *opts;
-    if (o.hash_bits == 0) o.hash_bits = 10;
-    if (o.waves_per_block == 0) o.waves_per_block = 4;
-  }
+  ann_search_opts o{};
+  o.delay = 1;
+  o.beam_width = 1;
+  if (opts) o = *opts;
+  if (o.hash_bits == 0) o.hash_bits = 10;
+  if (o.waves_per_block == 0) o.waves_per_block = 4;
   if (o.delay < 0) return fail(ANN_EINVAL, "delay=%d must be >= 0", o.delay);
   if (o.beam_width < 1) return fail(ANN_EINVAL, "beam_width=%d must be >= 1", o.beam_width);
   if (o.delay > 1) return fail(ANN_ENOTSUP, "delay=%d: the GPU kernels implement 0 and 1", o.delay);
@@ -219,6 +509,15 @@ int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int3
   if (o.waves_per_block < 1 || o.waves_per_block > 4)
     return fail(ANN_EINVAL, "waves_per_block=%d not in [1,4]", o.waves_per_block);
   if (o.d_trace && o.trace_cap < 1) return fail(ANN_EINVAL, "trace_cap=%d with a trace buffer", o.trace_cap);
+  int transport = o.transport;
+  if (transport == ANN_TRANSPORT_AUTO)
+    transport = ix->tier == ANN_TIER_FILE ? ANN_TRANSPORT_AGENT : ANN_TRANSPORT_DIRECT;
+  if (transport != ANN_TRANSPORT_DIRECT && transport != ANN_TRANSPORT_AGENT)
+    return fail(ANN_EINVAL, "transport=%d", o.transport);
+  if (transport == ANN_TRANSPORT_DIRECT && ix->tier == ANN_TIER_FILE)
+    return fail(ANN_EINVAL, "a file tier is read through the agent transport only");
+  if (transport == ANN_TRANSPORT_AGENT && ix->tier == ANN_TIER_HBM)
+    return fail(ANN_EINVAL, "HBM records are read directly by the kernel");
   if (nq == 0) return ANN_OK;
   if (!d_queries || !d_ids || !d_dists) return fail(ANN_EINVAL, "NULL query/output pointer");
 
@@ -242,8 +541,58 @@ int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int3
   if ((int64_t)a.lds_per_wave * o.waves_per_block > 160 * 1024)
     return fail(ANN_EINVAL, "LDS need %u B per query x %d exceeds 160 KiB", a.lds_per_wave,
                 o.waves_per_block);
-  hipError_t e = fa::launch_search(a, ix->dtype, o.delay, o.waves_per_block, (hipStream_t)hip_stream);
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (transport == ANN_TRANSPORT_DIRECT) {
+    hipError_t e = fa::launch_search(a, ix->dtype, o.delay, fa::TR_DIRECT, o.waves_per_block, st);
+    if (e != hipSuccess) return hip_fail(e, "search launch");
+    return ANN_OK;
+  }
+
+  // Query-grained transport: arm the agent, run, wait, disarm.  Synchronous
+  // with respect to the host so that the request, completion and staging
+  // arrays are never reused while a kernel may still touch them.
+  int rc = ensure_transport(ix, nq);
+  if (rc) return rc;
+  hipError_t e = hipStreamSynchronize(st);  // earlier work on the stream
+  if (e != hipSuccess) return hip_fail(e, "stream sync");
+  std::memset(ix->req, 0, sizeof(fa::AgentRequest) * nq);
+  std::memset(ix->cpl, 0, sizeof(uint32_t) * 2 * nq);
+  if ((e = hipMemsetAsync(ix->d_status, 0, sizeof(int32_t) * nq, st)) != hipSuccess)
+    return hip_fail(e, "status reset");
+  a.req = dev_ptr((uint64_t *)ix->req);
+  a.cpl = dev_ptr(ix->cpl);
+  a.stage = dev_ptr(ix->stage);
+  a.stage_stride = ix->stage_stride;
+  a.spin_limit = o.spin_limit ? o.spin_limit : (1u << 24);
+  a.status = ix->d_status;
+  if (!a.req || !a.cpl || !a.stage) return fail(ANN_EIO, "transport buffers not mapped");
+  ix->agent->faults = ix->faults;
+  ix->agent->arm(ix->req, ix->cpl, ix->stage, nq, ix->stage_stride);
+  e = fa::launch_search(a, ix->dtype, o.delay, fa::TR_AGENT, o.waves_per_block, st);
+  const hipError_t es = e == hipSuccess ? hipStreamSynchronize(st) : e;
+  ix->agent->disarm();
   if (e != hipSuccess) return hip_fail(e, "search launch");
+  if (es != hipSuccess) return hip_fail(es, "search");
+  std::vector<int32_t> status((size_t)nq);
+  if ((e = hipMemcpy(status.data(), ix->d_status, sizeof(int32_t) * nq, hipMemcpyDeviceToHost)) !=
+      hipSuccess)
+    return hip_fail(e, "status copy");
+  int64_t bad = 0, first = -1;
+  int code = ANN_OK;
+  for (int64_t i = 0; i < nq; i++)
+    if (status[(size_t)i]) {
+      if (first < 0) {
+        first = i;
+        code = status[(size_t)i];
+      }
+      bad++;
+    }
+  if (bad) {
+    const int en = ix->agent->stats.last_errno.load();
+    return fail(code, "%lld queries failed (first: query %lld, %s%s%s); their ids are -1",
+                (long long)bad, (long long)first, code == ANN_ETIMEDOUT ? "timed out" : "read error",
+                en ? ": " : "", en ? std::strerror(en) : "");
+  }
   return ANN_OK;
 }
 

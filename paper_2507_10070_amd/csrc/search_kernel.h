@@ -8,6 +8,11 @@ namespace fa {
 
 enum { DT_U8 = 1, DT_I8 = 2, DT_F32 = 3 };
 
+// How a wave obtains a record: by loading it itself (HBM or host-mapped
+// memory), or by posting a request that a host agent thread serves into a
+// per-query staging slot (query-grained transport).
+enum { TR_DIRECT = 0, TR_AGENT = 1 };
+
 // Byte offsets of one wave's LDS region.
 struct LdsLayout {
   uint32_t cand, nk, stage, qbuf, ids, dsc, hash, bytes;
@@ -23,6 +28,13 @@ struct SearchArgs {
   unsigned long long *stats;  // optional: [0] steps [1] rows scored [2] record mismatches
   int32_t *trace;          // optional: nq x trace_cap selected ids, in order
   unsigned long long *times;  // optional: nq x 2 wall-clock stamps (start, end)
+  // TR_AGENT only (fine-grained host memory except `status`):
+  uint64_t *req;           // nq x 2 request slots: (node << 32) | seq
+  const uint32_t *cpl;     // nq x 2 completion words (seq or seq | 1<<31 on error)
+  const uint8_t *stage;    // nq x 2 staging slots of stage_stride bytes
+  int64_t stage_stride;
+  uint32_t spin_limit;     // polls of a completion word before the query times out
+  int32_t *status;         // nq per-query status, device: 0, -5 (read error), -110 (timeout)
   int32_t trace_cap;
   int64_t nq, n, slot;
   int32_t nav_stride, qbytes, vec_pad, ids_off, rec_chunks;
@@ -31,7 +43,7 @@ struct SearchArgs {
 };
 
 uint32_t search_lds_bytes(int Lcap, int nav_stride, int hash_bits);
-hipError_t launch_search(const SearchArgs &a, int dtype, int delay, int waves_per_block,
-                         hipStream_t st);
+hipError_t launch_search(const SearchArgs &a, int dtype, int delay, int transport,
+                         int waves_per_block, hipStream_t st);
 
 }  // namespace fa

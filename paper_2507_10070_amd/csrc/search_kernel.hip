@@ -34,6 +34,8 @@ namespace fa {
 constexpr uint32_t kFlag = 0x80000000u;
 constexpr uint64_t kNoKey = 0xFFFFFFFFFFFFFFFFull;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+constexpr uint32_t kCplErr = 0x80000000u;   // completion word: read failed
+constexpr uint32_t kTimedOut = 0xFFFFFFFFu;
 
 __device__ __forceinline__ uint64_t kmask(uint64_t e) { return e & ~(uint64_t)kFlag; }
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
@@ -210,7 +212,7 @@ __host__ __device__ inline LdsLayout lds_layout(int Lcap, int nav_stride, int ha
   return o;
 }
 
-template <int DT, int CPL>
+template <int DT, int CPL, int TR>
 struct Searcher {
   using D = Dist<DT>;
   using Acc = typename D::Acc;
@@ -223,6 +225,8 @@ struct Searcher {
   int nc;
   int64_t qi;
   uint32_t steps, rows, mismatches;
+  uint32_t seq;   // TR_AGENT: last request number of this query
+  bool failed;    // TR_AGENT: a record read failed or timed out
 
   __device__ Searcher(const SearchArgs &args, uint8_t *base, int64_t query) : A(args), qi(query) {
     lane = lane_id();
@@ -249,6 +253,8 @@ struct Searcher {
     }
     qq = group8_sum(a);
     steps = rows = mismatches = 0;
+    seq = 0;
+    failed = false;
   }
 
   // Distance of the query to the row at `p` (all 8 lanes of a group call).
@@ -277,7 +283,7 @@ struct Searcher {
   // A correct search expands each node at most once; the cap at n expansions
   // guarantees termination regardless.
   __device__ uint64_t select() {
-    if ((int64_t)steps >= A.n) return kNoKey;
+    if ((int64_t)steps >= A.n || failed) return kNoKey;
     for (int base = 0; base < nc; base += 64) {
       const int i = base + lane;
       const bool un = i < nc && !((uint32_t)S.cand[i] & kFlag);
@@ -307,10 +313,64 @@ struct Searcher {
     return *(const uint4 *)(A.records + (int64_t)v * A.slot + 16 * c);
   }
 
-  // Part 1 of processing node u: stage its record, filter the first batch.
-  __device__ __forceinline__ void stage(uint4 rec) {
+  // Start obtaining the record of v.  TR_DIRECT: the load itself (in flight
+  // until used); `real` is ignored so that the load is unconditional.
+  // TR_AGENT: post request seq+1 for v as one 64-bit system-scope store of
+  // (v << 32 | seq) into the query's request slot seq & 1, then continue;
+  // the returned handle carries the sequence number.  The store needs no
+  // release: the slot's previous request was consumed (its staged bytes
+  // loaded and written to LDS) before this point, so the agent cannot
+  // overwrite data the wave still reads.
+  __device__ __forceinline__ uint4 issue(uint32_t v, bool real) {
+    if (TR == TR_DIRECT) return fetch(v);
+    if (!real || failed) return make_uint4(0, 0, 0, 0);
+    seq++;
+    if (lane == 0)
+      __hip_atomic_store(A.req + 2 * qi + (seq & 1), ((uint64_t)v << 32) | seq, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
+    return make_uint4(seq, 0, 0, 0);
+  }
+
+  // Finish obtaining a record.  TR_AGENT: lane 0 polls the slot's completion
+  // word (system-scope acquire, bounded by spin_limit), then every lane
+  // reads its 16 B of the staging slot.  A failed or timed-out read ends the
+  // query with a status code.
+  __device__ __forceinline__ uint4 consume(uint4 h) {
+    if (TR == TR_DIRECT) return h;
+    const uint32_t s = h.x;
+    if (failed || s == 0) return make_uint4(0, 0, 0, 0);
+    uint32_t c = 0;
+    if (lane == 0) {
+      const uint32_t *w = A.cpl + 2 * qi + (s & 1);
+      uint32_t spins = 0;
+      for (;;) {
+        c = __hip_atomic_load(w, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+        if ((c & ~kCplErr) == s) break;
+        if (++spins > A.spin_limit) {
+          c = kTimedOut;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    c = (uint32_t)__builtin_amdgcn_readfirstlane((int)c);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+    if (c == kTimedOut || (c & kCplErr)) {
+      failed = true;
+      if (lane == 0) A.status[qi] = c == kTimedOut ? -110 : -5;
+      return make_uint4(0, 0, 0, 0);
+    }
+    const int ch = lane < A.rec_chunks ? lane : A.rec_chunks - 1;
+    return *(const uint4 *)(A.stage + (qi * 2 + (s & 1)) * A.stage_stride + 16 * ch);
+  }
+
+  // Part 1 of processing node u: stage its record (false if it failed).
+  __device__ __forceinline__ bool stage(uint4 h) {
+    const uint4 rec = consume(h);
+    if (TR == TR_AGENT && failed) return false;
     if (lane < A.rec_chunks) S.stage[lane] = rec;
     __builtin_amdgcn_wave_barrier();
+    return true;
   }
 
   // Neighbours [b0, b0+64) of the staged record: visited filter and
@@ -336,7 +396,8 @@ struct Searcher {
   static constexpr int PB = (8 / CPL) > 0 ? (8 / CPL) : 1;
 
   template <bool WITH_FETCH>
-  __device__ __forceinline__ void gather_block(int m, int p0, uint32_t fid, uint4 &frec) {
+  __device__ __forceinline__ void gather_block(int m, int p0, uint32_t fid, bool freal,
+                                               uint4 &frec) {
     uint4 r[PB][CPL];
 #pragma unroll
     for (int pb = 0; pb < PB; pb++) {
@@ -345,7 +406,7 @@ struct Searcher {
 #pragma unroll
       for (int c = 0; c < CPL; c++) r[pb][c] = *(const uint4 *)(p + 16 * (sub + 8 * c));
     }
-    if (WITH_FETCH) frec = fetch(fid);
+    if (WITH_FETCH) frec = issue(fid, freal);
 #pragma unroll
     for (int pb = 0; pb < PB; pb++) {
       const int row = p0 + 8 * pb + grp;
@@ -427,27 +488,28 @@ struct Searcher {
   // at gather block p_start (earlier blocks were done by the caller).
   __device__ __forceinline__ void finish_batch(int m, int p_start) {
     uint4 unused;
-    for (int p0 = p_start; p0 < m; p0 += 8 * PB) gather_block<false>(m, p0, 0u, unused);
+    for (int p0 = p_start; p0 < m; p0 += 8 * PB) gather_block<false>(m, p0, 0u, false, unused);
     __builtin_amdgcn_wave_barrier();
     rows += (uint32_t)m;
     merge(m);
   }
 
-  // Process node u whose record is `rec`: stage, filter, gather, merge.
-  // RELAXED: exactly one record fetch (of `fid`, into `frec`) is issued,
-  // right after the first block of gathers (straight-line code, so the waits
-  // before the distance passes leave it in flight), or at once if the first
-  // batch has no new neighbour.
+  // Process node u whose record handle is `rec`: stage, filter, gather,
+  // merge.  RELAXED: exactly one record fetch (of `fid`, into `frec`) is
+  // issued, right after the first block of gathers (straight-line code, so the
+  // waits before the distance passes leave it in flight), or at once if the
+  // first batch has no new neighbour.  `freal` is false for an empty slot.
   template <bool RELAXED>
-  __device__ __forceinline__ void process(uint64_t ukey, uint4 rec, uint32_t fid, uint4 &frec) {
-    stage(rec);
+  __device__ __forceinline__ void process(uint64_t ukey, uint4 rec, uint32_t fid, bool freal,
+                                          uint4 &frec) {
+    if (!stage(rec)) return;
     if (A.stats) check_record(ukey);
     const int m = filter(0);
     if (m > 0) {
-      gather_block<RELAXED>(m, 0, fid, frec);
+      gather_block<RELAXED>(m, 0, fid, freal, frec);
       finish_batch(m, 8 * PB);
     } else if (RELAXED) {
-      frec = fetch(fid);
+      frec = issue(fid, freal);
     }
     for (int b0 = 64; b0 < A.R; b0 += 64) {
       const int mb = filter(b0);
@@ -459,7 +521,7 @@ struct Searcher {
     for (int j = lane; j < A.k; j += 64) {
       int32_t id = -1;
       uint32_t dist = DT == DT_F32 ? 0x7F800000u : 0xFFFFFFFFu;
-      if (j < nc) {
+      if (j < nc && !failed) {
         const uint64_t e = S.cand[j];
         id = (int32_t)((uint32_t)e & ~kFlag);
         dist = (uint32_t)(e >> 32);
@@ -481,26 +543,27 @@ struct Searcher {
 // Strict and relaxed drivers.  The relaxed loop is unrolled twice so the two
 // in-flight record registers have static names; a slot whose id word holds
 // kNoKey is an empty pipeline slot.
-template <int DT, int CPL, int DELAY>
+template <int DT, int CPL, int DELAY, int TR>
 __global__ void __launch_bounds__(256) search_kernel(SearchArgs A) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int wave = threadIdx.x >> 6;
   const int64_t qi = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
   if (qi >= A.nq) return;
   const unsigned long long t_start = A.times ? __builtin_amdgcn_s_memrealtime() : 0ull;
-  Searcher<DT, CPL> s(A, smem + (size_t)wave * A.lds_per_wave, qi);
+  Searcher<DT, CPL, TR> s(A, smem + (size_t)wave * A.lds_per_wave, qi);
   s.init_entry();
   if (DELAY == 0) {
     uint4 unused = make_uint4(0, 0, 0, 0);
     for (;;) {
       const uint64_t v = s.select();
       if (v == kNoKey) break;
-      const uint4 rec = s.fetch((uint32_t)v & ~kFlag);
-      s.template process<false>(v, rec, 0u, unused);
+      const uint4 rec = s.issue((uint32_t)v & ~kFlag, true);
+      s.template process<false>(v, rec, 0u, false, unused);
     }
   } else {
-    // Two pipeline slots.  An empty slot (key kNoKey) is filled with a fetch
-    // of the entry record so that every processing issues exactly one fetch.
+    // Two pipeline slots.  TR_DIRECT fills an empty slot (key kNoKey) with a
+    // load of the entry record so that every processing issues exactly one
+    // load; TR_AGENT posts no request for an empty slot.
     const uint32_t dummy = (uint32_t)A.entry;
     uint64_t k0 = kNoKey, k1 = kNoKey;
     uint4 r0 = make_uint4(0, 0, 0, 0), r1 = make_uint4(0, 0, 0, 0);
@@ -510,13 +573,13 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs A) {
       k0 = s.select();
       if (k0 == kNoKey && k1 == kNoKey) break;
       const uint32_t f0 = k0 != kNoKey ? ((uint32_t)k0 & ~kFlag) : dummy;
-      if (k1 != kNoKey) s.template process<true>(k1, r1, f0, r0);
-      else r0 = s.fetch(f0);
+      if (k1 != kNoKey) s.template process<true>(k1, r1, f0, k0 != kNoKey, r0);
+      else r0 = s.issue(f0, k0 != kNoKey);
       k1 = s.select();
       if (k1 == kNoKey && k0 == kNoKey) break;
       const uint32_t f1 = k1 != kNoKey ? ((uint32_t)k1 & ~kFlag) : dummy;
-      if (k0 != kNoKey) s.template process<true>(k0, r0, f1, r1);
-      else r1 = s.fetch(f1);
+      if (k0 != kNoKey) s.template process<true>(k0, r0, f1, k1 != kNoKey, r1);
+      else r1 = s.issue(f1, k1 != kNoKey);
     }
   }
   s.finish_query(qi);
@@ -526,27 +589,34 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs A) {
   }
 }
 
-template <int DT, int CPL, int DELAY>
+template <int DT, int CPL, int DELAY, int TR>
 static hipError_t launch_t(const SearchArgs &a, int waves_per_block, hipStream_t st) {
   const int64_t blocks = (a.nq + waves_per_block - 1) / waves_per_block;
   const size_t lds = (size_t)a.lds_per_wave * waves_per_block;
-  hipLaunchKernelGGL((search_kernel<DT, CPL, DELAY>), dim3((unsigned)blocks),
+  hipLaunchKernelGGL((search_kernel<DT, CPL, DELAY, TR>), dim3((unsigned)blocks),
                      dim3(64 * waves_per_block), lds, st, a);
   return hipGetLastError();
 }
 
-template <int DT, int CPL>
+template <int DT, int CPL, int TR>
 static hipError_t launch_d(const SearchArgs &a, int delay, int wpb, hipStream_t st) {
-  return delay == 0 ? launch_t<DT, CPL, 0>(a, wpb, st) : launch_t<DT, CPL, 1>(a, wpb, st);
+  return delay == 0 ? launch_t<DT, CPL, 0, TR>(a, wpb, st) : launch_t<DT, CPL, 1, TR>(a, wpb, st);
+}
+
+template <int DT, int CPL>
+static hipError_t launch_tr(const SearchArgs &a, int delay, int tr, int wpb, hipStream_t st) {
+  return tr == TR_DIRECT ? launch_d<DT, CPL, TR_DIRECT>(a, delay, wpb, st)
+                         : launch_d<DT, CPL, TR_AGENT>(a, delay, wpb, st);
 }
 
 template <int DT>
-static hipError_t launch_c(const SearchArgs &a, int cpl, int delay, int wpb, hipStream_t st) {
+static hipError_t launch_c(const SearchArgs &a, int cpl, int delay, int tr, int wpb,
+                           hipStream_t st) {
   switch (cpl) {
-    case 1: return launch_d<DT, 1>(a, delay, wpb, st);
-    case 2: return launch_d<DT, 2>(a, delay, wpb, st);
-    case 3: return launch_d<DT, 3>(a, delay, wpb, st);
-    case 4: return launch_d<DT, 4>(a, delay, wpb, st);
+    case 1: return launch_tr<DT, 1>(a, delay, tr, wpb, st);
+    case 2: return launch_tr<DT, 2>(a, delay, tr, wpb, st);
+    case 3: return launch_tr<DT, 3>(a, delay, tr, wpb, st);
+    case 4: return launch_tr<DT, 4>(a, delay, tr, wpb, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -555,13 +625,13 @@ uint32_t search_lds_bytes(int Lcap, int nav_stride, int hash_bits) {
   return lds_layout(Lcap, nav_stride, hash_bits).bytes;
 }
 
-hipError_t launch_search(const SearchArgs &a, int dtype, int delay, int waves_per_block,
-                         hipStream_t st) {
+hipError_t launch_search(const SearchArgs &a, int dtype, int delay, int transport,
+                         int waves_per_block, hipStream_t st) {
   const int cpl = a.nav_stride / 128;
   switch (dtype) {
-    case DT_U8: return launch_c<DT_U8>(a, cpl, delay, waves_per_block, st);
-    case DT_I8: return launch_c<DT_I8>(a, cpl, delay, waves_per_block, st);
-    case DT_F32: return launch_c<DT_F32>(a, cpl, delay, waves_per_block, st);
+    case DT_U8: return launch_c<DT_U8>(a, cpl, delay, transport, waves_per_block, st);
+    case DT_I8: return launch_c<DT_I8>(a, cpl, delay, transport, waves_per_block, st);
+    case DT_F32: return launch_c<DT_F32>(a, cpl, delay, transport, waves_per_block, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -18,8 +18,11 @@ ANN_ERRORS = {0: "ANN_OK", -5: "ANN_EIO", -12: "ANN_ENOMEM", -16: "ANN_EBUSY",
 DTYPE_CODES = {np.dtype(np.uint8): 1, np.dtype(np.int8): 2, np.dtype(np.float32): 3}
 TIER_HBM, TIER_HOST, TIER_FILE = 0, 1, 2
 
+TRANSPORT_AUTO, TRANSPORT_DIRECT, TRANSPORT_AGENT = 0, 1, 2
+
 EXPORTED = ["ann_index_create", "ann_index_info_get", "ann_search", "ann_index_free",
-            "ann_last_error", "ann_device_clock_khz"]
+            "ann_last_error", "ann_device_clock_khz", "ann_save_index", "ann_build_index",
+            "ann_load_records", "ann_agent_configure", "ann_agent_stats"]
 
 
 class AnnError(RuntimeError):
@@ -32,14 +35,16 @@ class SearchOptions(ctypes.Structure):
     _fields_ = [("delay", ctypes.c_int32), ("beam_width", ctypes.c_int32),
                 ("hash_bits", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
                 ("d_stats", ctypes.c_void_p), ("d_trace", ctypes.c_void_p),
-                ("trace_cap", ctypes.c_int32), ("d_times", ctypes.c_void_p)]
+                ("trace_cap", ctypes.c_int32), ("d_times", ctypes.c_void_p),
+                ("transport", ctypes.c_int32), ("spin_limit", ctypes.c_uint32)]
 
 
 class IndexInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("R", ctypes.c_int32), ("entry", ctypes.c_int32), ("slot_bytes", ctypes.c_int32),
                 ("tier", ctypes.c_int32), ("nav_stride", ctypes.c_int32),
-                ("rec_bytes", ctypes.c_int32), ("hbm_bytes", ctypes.c_int64)]
+                ("rec_bytes", ctypes.c_int32), ("hbm_bytes", ctypes.c_int64),
+                ("direct_io", ctypes.c_int32)]
 
 
 _lib = None
@@ -64,6 +69,17 @@ def load_library(path: str = LIB_PATH):
     lib.ann_search.restype = ctypes.c_int
     lib.ann_index_free.argtypes = [vp]
     lib.ann_index_free.restype = ctypes.c_int
+    cp, u64p = ctypes.c_char_p, ctypes.POINTER(ctypes.c_uint64)
+    lib.ann_save_index.argtypes = [cp, vp, vp, i64, i32, i32, i32, i32, i32]
+    lib.ann_save_index.restype = ctypes.c_int
+    lib.ann_build_index.argtypes = [vp, i64, i32, i32, i32, i32, ctypes.c_uint64, cp]
+    lib.ann_build_index.restype = ctypes.c_int
+    lib.ann_load_records.argtypes = [cp, i32, cp, ctypes.POINTER(vp)]
+    lib.ann_load_records.restype = ctypes.c_int
+    lib.ann_agent_configure.argtypes = [vp, i32, i32, i32, i32, i32]
+    lib.ann_agent_configure.restype = ctypes.c_int
+    lib.ann_agent_stats.argtypes = [vp, u64p, u64p, u64p]
+    lib.ann_agent_stats.restype = ctypes.c_int
     lib.ann_device_clock_khz.argtypes = [ctypes.POINTER(ctypes.c_int32)]
     lib.ann_device_clock_khz.restype = ctypes.c_int
     lib.ann_last_error.argtypes = []
@@ -84,8 +100,56 @@ def device_clock_khz() -> int:
     return v.value
 
 
+def save_index(path: str, vectors: np.ndarray, adjacency: np.ndarray, entry: int,
+               slot_bytes: int) -> None:
+    """ann_save_index: write meta.json, vectors.bin and records.bin."""
+    vectors = np.ascontiguousarray(vectors)
+    adjacency = np.ascontiguousarray(adjacency, dtype=np.int32)
+    _check(load_library().ann_save_index(path.encode(), vectors.ctypes.data, adjacency.ctypes.data,
+                                         vectors.shape[0], vectors.shape[1],
+                                         DTYPE_CODES[vectors.dtype], adjacency.shape[1], int(entry),
+                                         int(slot_bytes)))
+
+
+def build_index(path: str, vectors: np.ndarray, R: int, slot_bytes: int, seed: int) -> None:
+    """ann_build_index: construct the graph and write the index directory."""
+    vectors = np.ascontiguousarray(vectors)
+    _check(load_library().ann_build_index(vectors.ctypes.data, vectors.shape[0], vectors.shape[1],
+                                          DTYPE_CODES[vectors.dtype], int(R), int(slot_bytes),
+                                          int(seed), path.encode()))
+
+
+_CODE_DTYPES = {v: k for k, v in DTYPE_CODES.items()}
+
+
 class Index:
     """A searchable index: navigation copy in HBM plus records in a tier."""
+
+    @classmethod
+    def load(cls, path: str, tier: int = TIER_HBM, records_path: str | None = None) -> "Index":
+        """ann_load_records: open an index directory written by save/build_index."""
+        self = cls.__new__(cls)
+        self._h = None
+        h = ctypes.c_void_p()
+        _check(load_library().ann_load_records(path.encode(), int(tier),
+                                               records_path.encode() if records_path else None,
+                                               ctypes.byref(h)))
+        self._h = h
+        info = self.info()
+        self.dtype = _CODE_DTYPES[info["dtype"]]
+        self.d = info["d"]
+        return self
+
+    def configure_agent(self, threads: int = 0, delay_node: int = -1, delay_us: int = 0,
+                        fail_node: int = -1, drop_node: int = -1) -> None:
+        _check(load_library().ann_agent_configure(self.handle, threads, delay_node, delay_us,
+                                                  fail_node, drop_node))
+
+    def agent_stats(self) -> dict:
+        r, b, e = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(load_library().ann_agent_stats(self.handle, ctypes.byref(r), ctypes.byref(b),
+                                              ctypes.byref(e)))
+        return {"requests": r.value, "bytes": b.value, "errors": e.value}
 
     def __init__(self, vectors: np.ndarray, adjacency: np.ndarray, entry: int,
                  slot_bytes: int, tier: int = TIER_HBM):
@@ -132,7 +196,8 @@ class Index:
 
 def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
            beam_width: int = 1, hash_bits: int = 0, waves_per_block: int = 0, stats=None,
-           trace=None, times=None, stream=None, out=None):
+           trace=None, times=None, transport: int = TRANSPORT_AUTO, spin_limit: int = 0,
+           stream=None, out=None):
     """ann_search on torch CUDA tensors.
 
     queries: [nq, d] device tensor of the index dtype (uint8/int8/float32).
@@ -163,7 +228,8 @@ def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
                          stats.data_ptr() if stats is not None else None,
                          trace.data_ptr() if trace is not None else None,
                          trace.shape[1] if trace is not None else 0,
-                         times.data_ptr() if times is not None else None)
+                         times.data_ptr() if times is not None else None,
+                         transport, spin_limit)
     st = stream if stream is not None else torch.cuda.current_stream(dev)
     _check(load_library().ann_search(index.handle, queries.data_ptr(), nq, k, L, R,
                                      ctypes.byref(opts), ids.data_ptr(), dists.data_ptr(),

@@ -1,0 +1,112 @@
+// CPU exercise of the query-grained record transport: threads play the GPU
+// waves (same structs, same atomics), the real agent serves them.  Built with
+// ThreadSanitizer by tests/test_agent_protocol.py.
+//
+// Each fake wave issues requests in the strict pattern (one outstanding) or
+// the relaxed pattern (a second request issued before the first is consumed),
+// waits on its completion word with acquire loads, and checks the staged bytes
+// against the record store.  Faults: a slow node (straggler) and a failing
+// node (error completion).
+#include <atomic>
+#include <cstdio>
+#include <cstring>
+#include <random>
+#include <thread>
+#include <vector>
+
+#include "../paper_2507_10070_amd/csrc/agent.h"
+
+using fa::AgentRequest;
+
+static int check(bool c, const char *what) {
+  if (!c) std::fprintf(stderr, "FAIL: %s\n", what);
+  return c ? 0 : 1;
+}
+
+int main(int argc, char **argv) {
+  const int64_t n = 5000, slot = 512, copy = 384;
+  const int64_t nq = argc > 1 ? atoll(argv[1]) : 64;
+  const int agents = argc > 2 ? atoi(argv[2]) : 3;
+  const int steps = 200;
+  std::vector<uint8_t> records(n * slot);
+  for (int64_t i = 0; i < n * slot; i++) records[i] = (uint8_t)((i * 2654435761ull) >> 13);
+
+  fa::Agent agent(records.data(), -1, false, slot, (int32_t)copy, (int32_t)copy, agents);
+  agent.faults.delay_node = 7;
+  agent.faults.delay_us = 300;
+  agent.faults.fail_node = 11;
+
+  std::vector<AgentRequest> req(nq);
+  std::vector<uint32_t> cpl(2 * nq, 0);
+  const int64_t stride = 512;
+  std::vector<uint8_t> stage(nq * 2 * stride, 0);
+  std::memset(req.data(), 0, sizeof(AgentRequest) * nq);
+  agent.arm(req.data(), cpl.data(), stage.data(), nq, stride);
+
+  std::atomic<int> errors{0}, failures_seen{0};
+  auto wave = [&](int64_t q) {
+    std::mt19937 rng((unsigned)q * 7919u + 1u);
+    uint32_t seq = 0;
+    auto issue = [&](uint32_t node) {
+      seq++;
+      // release: this thread's reads of the slot's previous staging data are
+      // ordered before the agent may overwrite it (on the GPU the wave has
+      // consumed that data into LDS before it issues the next request)
+      __atomic_store_n(&req[q].slot[seq & 1], ((uint64_t)node << 32) | seq, __ATOMIC_RELEASE);
+      return seq;
+    };
+    auto consume = [&](uint32_t s, uint32_t node) {
+      // wait until this slot's completion word names request s
+      uint32_t c;
+      while (true) {
+        c = __atomic_load_n(&cpl[q * 2 + (s & 1)], __ATOMIC_ACQUIRE);
+        if ((c & ~fa::kCplError) == s) break;
+        std::this_thread::yield();
+      }
+      if (c & fa::kCplError) {
+        if (node != 11) errors++;
+        failures_seen++;
+        return;
+      }
+      const uint8_t *got = &stage[(q * 2 + (s & 1)) * stride];
+      if (std::memcmp(got, &records[(int64_t)node * slot], copy) != 0) errors++;
+    };
+    const bool relaxed = q % 2 == 1;
+    uint32_t prev_node = 0, prev_seq = 0;
+    for (int i = 0; i < steps; i++) {
+      uint32_t node = rng() % n;
+      if (i % 50 == 3) node = 7;    // straggler
+      if (i % 97 == 5) node = 11;   // failing read
+      const uint32_t s = issue(node);
+      if (relaxed) {
+        if (prev_seq) consume(prev_seq, prev_node);
+        prev_seq = s;
+        prev_node = node;
+      } else {
+        consume(s, node);
+      }
+    }
+    if (relaxed && prev_seq) consume(prev_seq, prev_node);
+  };
+  std::vector<std::thread> waves;
+  for (int64_t q = 0; q < nq; q++) waves.emplace_back(wave, q);
+  for (auto &w : waves) w.join();
+  agent.disarm();
+
+  int bad = 0;
+  bad += check(errors.load() == 0, "staged data or completion mismatch");
+  bad += check(failures_seen.load() > 0, "injected failures observed");
+  bad += check(agent.stats.requests.load() == (uint64_t)(nq * steps), "every request served");
+  bad += check(agent.stats.errors.load() == (uint64_t)failures_seen.load(), "error count");
+  // the agent must be reusable after disarm
+  std::memset(req.data(), 0, sizeof(AgentRequest) * nq);
+  std::fill(cpl.begin(), cpl.end(), 0u);
+  agent.arm(req.data(), cpl.data(), stage.data(), nq, stride);
+  __atomic_store_n(&req[0].slot[1], (42ull << 32) | 1u, __ATOMIC_RELEASE);
+  while (__atomic_load_n(&cpl[1], __ATOMIC_ACQUIRE) != 1u) std::this_thread::yield();
+  bad += check(std::memcmp(&stage[1 * stride], &records[42 * slot], copy) == 0, "re-armed serve");
+  agent.disarm();
+  std::printf("%s: %lld queries x %d requests, %d agents, %d injected failures\n",
+              bad ? "FAIL" : "OK", (long long)nq, steps, agents, failures_seen.load());
+  return bad ? 1 : 0;
+}

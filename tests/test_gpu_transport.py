@@ -1,0 +1,147 @@
+"""GPU parity of the query-grained record transport (paper section 4.2) and
+of the index files, through the C ABI.
+
+The agent transport must give bit-exact results (ids, distances, steps,
+traces) for records in pinned host DRAM and in a file; host-forced faults
+must affect exactly the queries that expand the faulty node.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+fa = pytest.importorskip("paper_2507_10070_amd")
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    cfg = synth.CONFIGS[1]
+    base, q = synth.make_dataset(cfg)
+    adj, entry = synth.build_graph(base, cfg.R, 3001, threads=8)
+    return base, q, adj, entry
+
+
+def run(ix, q, k, L, trace_cap=0, **kw):
+    qd = torch.from_numpy(np.ascontiguousarray(q)).to("cuda:0")
+    trace = None
+    if trace_cap:
+        trace = torch.full((q.shape[0], trace_cap), -1, dtype=torch.int32, device="cuda:0")
+    ids, dists, steps = fa.search(ix, qd, k=k, L=L, trace=trace, **kw)
+    torch.cuda.synchronize()
+    out = {"ids": ids.cpu().numpy(), "dists": dists.cpu().numpy().view(np.uint32),
+           "steps": steps.cpu().numpy().view(np.uint32)}
+    if trace is not None:
+        out["trace"] = trace.cpu().numpy()
+    return out
+
+
+def assert_same(g, ref, rows=None):
+    rows = slice(None) if rows is None else rows
+    np.testing.assert_array_equal(g["ids"][rows], ref["ids"][rows])
+    gd = g["dists"][rows].astype(np.float64)
+    gd[g["dists"][rows] == 0xFFFFFFFF] = np.inf
+    np.testing.assert_array_equal(gd, ref["dists"][rows])
+    np.testing.assert_array_equal(g["steps"][rows], ref["steps"][rows])
+
+
+@pytest.mark.parametrize("delay", [0, 1])
+@pytest.mark.parametrize("L", [32, 100])
+def test_agent_transport_host_parity(cfg1, delay, L):
+    base, q, adj, entry = cfg1
+    with fa.Index(base, adj, entry, 256, fa.TIER_HOST) as ix:
+        ix.configure_agent(threads=4)
+        g = run(ix, q, 10, L, delay=delay, transport=fa.TRANSPORT_AGENT, trace_cap=400)
+        st = ix.agent_stats()
+    ref = oracle.search(base, adj, entry, q, 10, L, delay=delay, trace_cap=400)
+    assert_same(g, ref)
+    np.testing.assert_array_equal(g["trace"], ref["trace"])
+    assert st["requests"] == int(ref["steps"].sum())   # one request per expansion
+    assert st["errors"] == 0
+
+
+@pytest.mark.parametrize("slot", [256, 512])
+@pytest.mark.parametrize("tier", ["hbm", "host", "file"])
+def test_index_files_all_tiers(cfg1, tmp_path, slot, tier):
+    base, q, adj, entry = cfg1
+    d = str(tmp_path / "ix")
+    fa.save_index(d, base, adj, entry, slot)
+    t = {"hbm": fa.TIER_HBM, "host": fa.TIER_HOST, "file": fa.TIER_FILE}[tier]
+    ix = fa.Index.load(d, t)
+    try:
+        info = ix.info()
+        assert info["n"] == base.shape[0] and info["R"] == adj.shape[1]
+        assert info["entry"] == entry and info["slot_bytes"] == slot
+        if tier == "file":
+            print("direct_io", info["direct_io"])
+        for delay in (0, 1):
+            g = run(ix, q, 10, 64, delay=delay)
+            ref = oracle.search(base, adj, entry, q, 10, 64, delay=delay)
+            assert_same(g, ref)
+    finally:
+        ix.close()
+
+
+def _node_in_some_traces(ref, want_min=2):
+    """A node expanded by some queries but not all (not the entry)."""
+    tr = ref["trace"]
+    counts = {}
+    for row in tr:
+        for v in set(row[row >= 0].tolist()):
+            counts[v] = counts.get(v, 0) + 1
+    nq = tr.shape[0]
+    cands = sorted((c, v) for v, c in counts.items() if want_min <= c <= nq // 4)
+    return cands[len(cands) // 2][1]
+
+
+@pytest.mark.parametrize("delay", [0, 1])
+def test_agent_faults(cfg1, delay):
+    base, q, adj, entry = cfg1
+    ref = oracle.search(base, adj, entry, q, 10, 64, delay=delay, trace_cap=400)
+    bad_node = _node_in_some_traces(ref)
+    hit = np.array([(row == bad_node).any() for row in ref["trace"]])
+    assert 0 < hit.sum() < len(q)
+    with fa.Index(base, adj, entry, 256, fa.TIER_HOST) as ix:
+        # a straggler changes nothing
+        ix.configure_agent(threads=3, delay_node=bad_node, delay_us=2000)
+        assert_same(run(ix, q, 10, 64, delay=delay, transport=fa.TRANSPORT_AGENT), ref)
+        # a failed read: those queries report ANN_EIO with ids -1, the others are exact
+        ix.configure_agent(threads=3, fail_node=bad_node)
+        qd = torch.from_numpy(q).to("cuda:0")
+        ids = torch.empty((len(q), 10), dtype=torch.int32, device="cuda:0")
+        dists = torch.empty((len(q), 10), dtype=torch.int32, device="cuda:0")
+        steps = torch.empty((len(q),), dtype=torch.int32, device="cuda:0")
+        with pytest.raises(fa.AnnError) as e:
+            fa.search(ix, qd, k=10, L=64, delay=delay, transport=fa.TRANSPORT_AGENT,
+                      out=(ids, dists, steps))
+        assert e.value.code == -5
+        g = {"ids": ids.cpu().numpy(), "dists": dists.cpu().numpy().view(np.uint32),
+             "steps": steps.cpu().numpy().view(np.uint32)}
+        assert (g["ids"][hit] == -1).all()
+        assert_same(g, ref, rows=~hit)
+        # a read that never completes: those queries time out (bounded poll)
+        ix.configure_agent(threads=3, drop_node=bad_node)
+        with pytest.raises(fa.AnnError) as e:
+            fa.search(ix, qd, k=10, L=64, delay=delay, transport=fa.TRANSPORT_AGENT,
+                      spin_limit=2000, out=(ids, dists, steps))
+        assert e.value.code == -110
+        g["ids"] = ids.cpu().numpy()
+        assert (g["ids"][hit] == -1).all()
+        np.testing.assert_array_equal(g["ids"][~hit], ref["ids"][~hit])
+
+
+def test_transport_validation(cfg1):
+    base, q, adj, entry = cfg1
+    qd = torch.from_numpy(q[:4]).to("cuda:0")
+    with fa.Index(base, adj, entry, 256, fa.TIER_HBM) as ix:
+        with pytest.raises(fa.AnnError) as e:
+            fa.search(ix, qd, k=10, L=64, transport=fa.TRANSPORT_AGENT)
+        assert e.value.code == -22
+        with pytest.raises(fa.AnnError) as e:
+            fa.search(ix, qd, k=10, L=64, transport=7)
+        assert e.value.code == -22
