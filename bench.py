@@ -94,6 +94,10 @@ def main():
                     help="queries per oracle pass in the CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="repeat oracle passes until this much CPU time has elapsed")
+    ap.add_argument("--no-transports", action="store_true",
+                    help="skip the agent-transport and file-tier measurements")
+    ap.add_argument("--file-queries", type=int, default=1000,
+                    help="queries of the file-tier measurement (records read with O_DIRECT)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device-to-device copy (scale reference "
                          "for memory counters)")
@@ -225,6 +229,60 @@ def main():
                               "frac": round(link_bytes / sec / 1e9 / link_peak, 4),
                               "bytes_per_launch": link_bytes}}
 
+    # ---- the paper's query-grained I/O stack on the same workload: agent
+    # transport from pinned DRAM (all queries) and from a file (O_DIRECT)
+    transports = None
+    if not args.no_transports:
+        import tempfile
+
+        transports = {}
+
+        def measure(index, qsub, L, delay, reps):
+            outs = (torch.empty((qsub.shape[0], k), dtype=torch.int32, device=dev),
+                    torch.empty((qsub.shape[0], k), dtype=torch.int32, device=dev),
+                    torch.empty((qsub.shape[0],), dtype=torch.int32, device=dev))
+            fa.search(index, qsub, k=k, L=L, delay=delay, transport=fa.TRANSPORT_AGENT, out=outs)
+            times = torch.zeros((qsub.shape[0], 2), dtype=torch.int64, device=dev)
+            fa.search(index, qsub, k=k, L=L, delay=delay, transport=fa.TRANSPORT_AGENT, out=outs,
+                      times=times)
+            tt = times.cpu().numpy()
+            lat = (tt[:, 1] - tt[:, 0]) / khz
+            t = time.perf_counter()
+            for _ in range(reps):
+                fa.search(index, qsub, k=k, L=L, delay=delay, transport=fa.TRANSPORT_AGENT,
+                          out=outs)
+            el = (time.perf_counter() - t) / reps
+            return {"qps": round(qsub.shape[0] / el, 1), "ms_per_step": round(el * 1e3, 3),
+                    "query_latency_ms_p50": float(np.percentile(lat, 50)),
+                    "query_latency_ms_p99": float(np.percentile(lat, 99))}
+
+        if tier == fa.TIER_HOST:
+            reps = max(1, min(args.steps, 5))
+            transports["agent_host"] = {"queries": nq, "L": op[1],
+                                        "relaxed": measure(ix, qd, op[1], 1, reps),
+                                        "strict": measure(ix, qd, op[1], 0, reps)}
+            st = ix.agent_stats()
+            transports["agent_host"]["agent_threads_requests"] = st["requests"]
+            log("agent transport: %s" % transports["agent_host"])
+        tmpd = tempfile.mkdtemp(prefix="flashann_", dir=os.environ.get("TMPDIR", "/tmp"))
+        try:
+            t = time.time()
+            fa.save_index(tmpd, base, adj, entry, cfg.slot)
+            t_save = time.time() - t
+            fix = fa.Index.load(tmpd, fa.TIER_FILE)
+            mq = min(args.file_queries, nq)
+            qsub = qd[:mq].contiguous()
+            transports["file"] = {"queries": mq, "L": op[1], "direct_io": fix.info()["direct_io"],
+                                  "write_s": round(t_save, 1),
+                                  "relaxed": measure(fix, qsub, op[1], 1, 1),
+                                  "strict": measure(fix, qsub, op[1], 0, 1)}
+            fix.close()
+            log("file tier: %s" % transports["file"])
+        finally:
+            import shutil
+
+            shutil.rmtree(tmpd, ignore_errors=True)
+
     # ---- CPU baseline: the oracle on this host's cores, bounded sample
     cpu = None
     if not args.no_cpu_baseline:
@@ -271,6 +329,7 @@ def main():
         "detail": {"strict": detail[0], "relaxed": detail[1]},
         "sweep": {"strict": sweep[0], "relaxed": sweep[1]},
         "roofline": roofline,
+        "transports": transports,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -151,7 +151,8 @@ int ann_load_records(const char *dir, int32_t tier, const char *records_path, an
 
 /*
  * ann_agent_configure -- settings of the host agent used by the AGENT
- * transport: `threads` (0 = hardware threads - 2, at most 32).  The other
+ * transport: `threads` (0 = default: hardware threads - 2, at most 32, for
+ * memory copies; 64 for file reads, which block and set the queue depth).  The other
  * arguments inject faults for tests, -1 = off: requests for `delay_node`
  * complete after `delay_us` microseconds (a straggler), requests for
  * `fail_node` complete with a read error (ANN_EIO for that query), requests

@@ -69,7 +69,7 @@ bool Agent::serve(int64_t q, uint32_t seq, uint32_t node, uint8_t *bounce) {
     if (ok && direct_) std::memcpy(dst, bounce, (size_t)copy_bytes_);
   }
   if ((int32_t)node == faults.fail_node) ok = false;
-  __atomic_store_n(&cpl_[q * 2 + (seq & 1)], ok ? seq : (seq | kCplError), __ATOMIC_RELEASE);
+  __atomic_store_n(&cpl_[q * kCplStride + (seq & 1)], ok ? seq : (seq | kCplError), __ATOMIC_RELEASE);
   stats.requests.fetch_add(1, std::memory_order_relaxed);
   stats.bytes.fetch_add(mem_ ? (uint64_t)copy_bytes_ : (uint64_t)io_bytes_,
                         std::memory_order_relaxed);

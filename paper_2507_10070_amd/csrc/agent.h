@@ -20,13 +20,21 @@ namespace fa {
 // agent never sees a sequence number without its node.  At most two requests
 // of a query are outstanding (strict or one-step-stale schedule), and a wave
 // reuses a slot only after consuming the request that held it.
-struct alignas(16) AgentRequest {
+// Padded to a 64 B line so that no two queries (and no GPU wave and agent
+// thread pair) share a cache line.
+struct alignas(64) AgentRequest {
   uint64_t slot[2];
+  uint64_t pad[6];
 };
 
-// Completion words: two per query, cpl[2q + (s & 1)] = s when request s has
-// been staged, s | kCplError when its read failed.  One word per in-flight
-// slot keeps each request's status until its wave has consumed it.
+// Completion words of query q: cpl[kCplStride * q + (s & 1)], one 64 B line
+// per query.
+constexpr int kCplStride = 16;
+
+// Completion words: two per query, cpl[kCplStride q + (s & 1)] = s when
+// request s has been staged, s | kCplError when its read failed.  One word
+// per in-flight slot keeps each request's status until its wave has
+// consumed it.
 constexpr uint32_t kCplError = 0x80000000u;
 
 // Fault injection for tests (host-forced conditions only).
@@ -54,8 +62,8 @@ class Agent {
         int32_t io_bytes, int threads);
   ~Agent();
 
-  // Serve the requests of `nq` queries until disarm().  `cpl` holds 2 x nq
-  // completion words and `stage` two staging slots of `stage_stride` bytes
+  // Serve the requests of `nq` queries until disarm().  `cpl` holds
+  // kCplStride x nq completion words and `stage` two staging slots of `stage_stride` bytes
   // per query (slot s & 1 for request s).  The caller zeroes req/cpl.
   void arm(AgentRequest *req, uint32_t *cpl, uint8_t *stage, int64_t nq, int64_t stage_stride);
   // Stop serving; returns once no agent thread touches the arrays any more.

@@ -28,7 +28,8 @@ extern "C" int synth_build_graph(const void *base, int64_t n, int32_t d, int32_t
                                  int32_t n_hubs, int64_t exact_limit, int32_t *adj,
                                  int32_t *entry_out);
 
-static_assert(sizeof(fa::AgentRequest) == 16, "request slot layout shared with the kernel");
+static_assert(sizeof(fa::AgentRequest) == 64 && fa::kCplStride == 16,
+              "request/completion layout shared with the kernel");
 
 struct ann_index {
   int64_t n = 0;
@@ -218,9 +219,12 @@ int build_records(ann_index *ix, const RecordSource &src) {
   return ANN_OK;
 }
 
-int default_agent_threads() {
+// Memory copies are CPU-bound: one thread per spare hardware thread.  File
+// reads block in pread, so more threads keep more reads in flight (the queue
+// depth the storage sees).
+int default_agent_threads(bool file) {
   const int hw = (int)std::thread::hardware_concurrency();
-  return std::max(1, std::min(32, hw - 2));
+  return file ? 64 : std::max(1, std::min(32, hw - 2));
 }
 
 // Transport buffers for nq queries and the agent itself.
@@ -228,7 +232,7 @@ int ensure_transport(ann_index *ix, int64_t nq) {
   const bool file = ix->tier == ANN_TIER_FILE;
   const int32_t io = file && ix->direct_io ? (int32_t)round_up(ix->rec_bytes, 512) : ix->rec_bytes;
   if (!ix->agent) {
-    const int t = ix->agent_threads > 0 ? ix->agent_threads : default_agent_threads();
+    const int t = ix->agent_threads > 0 ? ix->agent_threads : default_agent_threads(file);
     ix->agent.reset(new fa::Agent(file ? nullptr : (const uint8_t *)ix->rec_host, ix->fd,
                                   ix->direct_io, ix->slot, ix->rec_bytes, io, t));
   }
@@ -241,7 +245,8 @@ int ensure_transport(ann_index *ix, int64_t nq) {
   hipError_t e;
   const unsigned fl = hipHostMallocCoherent | hipHostMallocMapped;
   if ((e = hipHostMalloc((void **)&ix->req, sizeof(fa::AgentRequest) * cap, fl)) != hipSuccess ||
-      (e = hipHostMalloc((void **)&ix->cpl, sizeof(uint32_t) * 2 * cap, fl)) != hipSuccess ||
+      (e = hipHostMalloc((void **)&ix->cpl, sizeof(uint32_t) * fa::kCplStride * cap, fl)) !=
+          hipSuccess ||
       (e = hipHostMalloc((void **)&ix->stage, ix->stage_stride * 2 * cap, fl)) != hipSuccess ||
       (e = hipMalloc(&ix->d_status, sizeof(int32_t) * cap)) != hipSuccess) {
     free_transport(ix);
@@ -556,7 +561,7 @@ int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int3
   hipError_t e = hipStreamSynchronize(st);  // earlier work on the stream
   if (e != hipSuccess) return hip_fail(e, "stream sync");
   std::memset(ix->req, 0, sizeof(fa::AgentRequest) * nq);
-  std::memset(ix->cpl, 0, sizeof(uint32_t) * 2 * nq);
+  std::memset(ix->cpl, 0, sizeof(uint32_t) * fa::kCplStride * nq);
   if ((e = hipMemsetAsync(ix->d_status, 0, sizeof(int32_t) * nq, st)) != hipSuccess)
     return hip_fail(e, "status reset");
   a.req = dev_ptr((uint64_t *)ix->req);

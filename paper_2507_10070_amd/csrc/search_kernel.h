@@ -29,8 +29,8 @@ struct SearchArgs {
   int32_t *trace;          // optional: nq x trace_cap selected ids, in order
   unsigned long long *times;  // optional: nq x 2 wall-clock stamps (start, end)
   // TR_AGENT only (fine-grained host memory except `status`):
-  uint64_t *req;           // nq x 2 request slots: (node << 32) | seq
-  const uint32_t *cpl;     // nq x 2 completion words (seq or seq | 1<<31 on error)
+  uint64_t *req;           // nq x 8 u64 (64 B per query); slots 0,1: (node << 32) | seq
+  const uint32_t *cpl;     // nq x 16 u32 (64 B per query); words 0,1: seq or seq | 1<<31
   const uint8_t *stage;    // nq x 2 staging slots of stage_stride bytes
   int64_t stage_stride;
   uint32_t spin_limit;     // polls of a completion word before the query times out

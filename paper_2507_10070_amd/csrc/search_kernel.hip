@@ -326,7 +326,7 @@ struct Searcher {
     if (!real || failed) return make_uint4(0, 0, 0, 0);
     seq++;
     if (lane == 0)
-      __hip_atomic_store(A.req + 2 * qi + (seq & 1), ((uint64_t)v << 32) | seq, __ATOMIC_RELAXED,
+      __hip_atomic_store(A.req + 8 * qi + (seq & 1), ((uint64_t)v << 32) | seq, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_SYSTEM);
     return make_uint4(seq, 0, 0, 0);
   }
@@ -341,8 +341,8 @@ struct Searcher {
     if (failed || s == 0) return make_uint4(0, 0, 0, 0);
     uint32_t c = 0;
     if (lane == 0) {
-      const uint32_t *w = A.cpl + 2 * qi + (s & 1);
-      uint32_t spins = 0;
+      const uint32_t *w = A.cpl + 16 * qi + (s & 1);
+      uint32_t spins = 0, nap = 1;
       for (;;) {
         c = __hip_atomic_load(w, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
         if ((c & ~kCplErr) == s) break;
@@ -350,7 +350,10 @@ struct Searcher {
           c = kTimedOut;
           break;
         }
-        __builtin_amdgcn_s_sleep(2);
+        // back off (up to ~1.7 us) so that thousands of waiting waves do not
+        // flood the host link with polls
+        for (uint32_t i = 0; i < nap; i++) __builtin_amdgcn_s_sleep(16);
+        nap = nap < 4 ? nap * 2 : 4;
       }
     }
     c = (uint32_t)__builtin_amdgcn_readfirstlane((int)c);

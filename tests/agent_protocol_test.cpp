@@ -37,7 +37,7 @@ int main(int argc, char **argv) {
   agent.faults.fail_node = 11;
 
   std::vector<AgentRequest> req(nq);
-  std::vector<uint32_t> cpl(2 * nq, 0);
+  std::vector<uint32_t> cpl(fa::kCplStride * nq, 0);
   const int64_t stride = 512;
   std::vector<uint8_t> stage(nq * 2 * stride, 0);
   std::memset(req.data(), 0, sizeof(AgentRequest) * nq);
@@ -59,7 +59,7 @@ int main(int argc, char **argv) {
       // wait until this slot's completion word names request s
       uint32_t c;
       while (true) {
-        c = __atomic_load_n(&cpl[q * 2 + (s & 1)], __ATOMIC_ACQUIRE);
+        c = __atomic_load_n(&cpl[q * fa::kCplStride + (s & 1)], __ATOMIC_ACQUIRE);
         if ((c & ~fa::kCplError) == s) break;
         std::this_thread::yield();
       }
