@@ -96,6 +96,12 @@ typedef struct {
   unsigned long long *d_times; /* optional device buffer, nq x 2 u64: wall-clock
                                   stamps when each query's search starts and ends,
                                   in ticks of ann_device_clock_khz() kHz */
+  unsigned long long *d_phases; /* optional device buffer, nq x 2 u64, strict
+                                  schedule only (delay 0): per query, the summed
+                                  wall-clock ticks spent obtaining records (issue
+                                  to record in LDS, T_f) and computing (filter,
+                                  gathers, distances, merge, T_c) -- the stage
+                                  times the degree selector balances (section 4.3) */
   int32_t transport;       /* ann_transport (0 = AUTO) */
   uint32_t spin_limit;     /* AGENT: polls of a completion word before the query
                               gives up with ANN_ETIMEDOUT (0 = default 2^24) */

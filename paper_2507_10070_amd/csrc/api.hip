@@ -514,6 +514,8 @@ int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int3
   if (o.waves_per_block < 1 || o.waves_per_block > 4)
     return fail(ANN_EINVAL, "waves_per_block=%d not in [1,4]", o.waves_per_block);
   if (o.d_trace && o.trace_cap < 1) return fail(ANN_EINVAL, "trace_cap=%d with a trace buffer", o.trace_cap);
+  if (o.d_phases && o.delay != 0)
+    return fail(ANN_EINVAL, "phase times are measured on the strict schedule (delay 0) only");
   int transport = o.transport;
   if (transport == ANN_TRANSPORT_AUTO)
     transport = ix->tier == ANN_TIER_FILE ? ANN_TRANSPORT_AGENT : ANN_TRANSPORT_DIRECT;
@@ -537,6 +539,7 @@ int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int3
   a.trace = o.d_trace;
   a.trace_cap = o.d_trace ? o.trace_cap : 0;
   a.times = o.d_times;
+  a.phases = o.d_phases;
   a.nq = nq; a.n = ix->n; a.slot = ix->slot;
   a.nav_stride = ix->nav_stride; a.qbytes = ix->vec_bytes; a.vec_pad = ix->vec_pad;
   a.ids_off = ix->vec_pad; a.rec_chunks = ix->rec_chunks;

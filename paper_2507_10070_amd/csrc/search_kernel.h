@@ -28,6 +28,8 @@ struct SearchArgs {
   unsigned long long *stats;  // optional: [0] steps [1] rows scored [2] record mismatches
   int32_t *trace;          // optional: nq x trace_cap selected ids, in order
   unsigned long long *times;  // optional: nq x 2 wall-clock stamps (start, end)
+  unsigned long long *phases; // optional, strict schedule only: nq x 2 summed
+                              // wall-clock ticks (record fetch, compute)
   // TR_AGENT only (fine-grained host memory except `status`):
   uint64_t *req;           // nq x 8 u64 (64 B per query); slots 0,1: (node << 32) | seq
   const uint32_t *cpl;     // nq x 16 u32 (64 B per query); words 0,1: seq or seq | 1<<31

@@ -227,6 +227,7 @@ struct Searcher {
   uint32_t steps, rows, mismatches;
   uint32_t seq;   // TR_AGENT: last request number of this query
   bool failed;    // TR_AGENT: a record read failed or timed out
+  unsigned long long t_fetch, t_comp;  // summed phase ticks (strict, optional)
 
   __device__ Searcher(const SearchArgs &args, uint8_t *base, int64_t query) : A(args), qi(query) {
     lane = lane_id();
@@ -255,6 +256,17 @@ struct Searcher {
     steps = rows = mismatches = 0;
     seq = 0;
     failed = false;
+    t_fetch = t_comp = 0;
+  }
+
+  // Wall-clock stamp after every outstanding memory operation of the wave
+  // has completed (phase accounting only; not used on the timed path).
+  __device__ __forceinline__ unsigned long long stamp() const {
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0);
+    const unsigned long long t = __builtin_amdgcn_s_memrealtime();
+    __builtin_amdgcn_sched_barrier(0);
+    return t;
   }
 
   // Distance of the query to the row at `p` (all 8 lanes of a group call).
@@ -506,6 +518,13 @@ struct Searcher {
   __device__ __forceinline__ void process(uint64_t ukey, uint4 rec, uint32_t fid, bool freal,
                                           uint4 &frec) {
     if (!stage(rec)) return;
+    process_staged<RELAXED>(ukey, fid, freal, frec);
+  }
+
+  // The part of process() after the record is staged in LDS.
+  template <bool RELAXED>
+  __device__ __forceinline__ void process_staged(uint64_t ukey, uint32_t fid, bool freal,
+                                                 uint4 &frec) {
     if (A.stats) check_record(ukey);
     const int m = filter(0);
     if (m > 0) {
@@ -557,11 +576,33 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs A) {
   s.init_entry();
   if (DELAY == 0) {
     uint4 unused = make_uint4(0, 0, 0, 0);
-    for (;;) {
-      const uint64_t v = s.select();
-      if (v == kNoKey) break;
-      const uint4 rec = s.issue((uint32_t)v & ~kFlag, true);
-      s.template process<false>(v, rec, 0u, false, unused);
+    if (A.phases) {
+      // the same steps with a stamp at issue, after staging and after merge:
+      // fetch time (issue -> record in LDS) and compute time (filter,
+      // gathers, distances, merge) per expansion, summed per query
+      for (;;) {
+        const uint64_t v = s.select();
+        if (v == kNoKey) break;
+        const unsigned long long t0 = s.stamp();
+        const uint4 rec = s.issue((uint32_t)v & ~kFlag, true);
+        if (!s.stage(rec)) break;
+        const unsigned long long t1 = s.stamp();
+        s.template process_staged<false>(v, 0u, false, unused);
+        const unsigned long long t2 = s.stamp();
+        s.t_fetch += t1 - t0;
+        s.t_comp += t2 - t1;
+      }
+      if (s.lane == 0) {
+        A.phases[2 * qi] = s.t_fetch;
+        A.phases[2 * qi + 1] = s.t_comp;
+      }
+    } else {
+      for (;;) {
+        const uint64_t v = s.select();
+        if (v == kNoKey) break;
+        const uint4 rec = s.issue((uint32_t)v & ~kFlag, true);
+        s.template process<false>(v, rec, 0u, false, unused);
+      }
     }
   } else {
     // Two pipeline slots.  TR_DIRECT fills an empty slot (key kNoKey) with a

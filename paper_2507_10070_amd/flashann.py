@@ -36,7 +36,8 @@ class SearchOptions(ctypes.Structure):
                 ("hash_bits", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
                 ("d_stats", ctypes.c_void_p), ("d_trace", ctypes.c_void_p),
                 ("trace_cap", ctypes.c_int32), ("d_times", ctypes.c_void_p),
-                ("transport", ctypes.c_int32), ("spin_limit", ctypes.c_uint32)]
+                ("d_phases", ctypes.c_void_p), ("transport", ctypes.c_int32),
+                ("spin_limit", ctypes.c_uint32)]
 
 
 class IndexInfo(ctypes.Structure):
@@ -196,14 +197,16 @@ class Index:
 
 def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
            beam_width: int = 1, hash_bits: int = 0, waves_per_block: int = 0, stats=None,
-           trace=None, times=None, transport: int = TRANSPORT_AUTO, spin_limit: int = 0,
-           stream=None, out=None):
+           trace=None, times=None, phases=None, transport: int = TRANSPORT_AUTO,
+           spin_limit: int = 0, stream=None, out=None):
     """ann_search on torch CUDA tensors.
 
     queries: [nq, d] device tensor of the index dtype (uint8/int8/float32).
     stats: optional int64 device tensor of 3 counters (accumulated);
     trace: optional int32 device tensor [nq, cap] receiving expanded ids;
-    times: optional int64 device tensor [nq, 2] receiving start/end stamps.
+    times: optional int64 device tensor [nq, 2] receiving start/end stamps;
+    phases: optional int64 device tensor [nq, 2] (strict only): summed fetch and
+    compute ticks per query.
     Returns (ids int32 [nq,k], dists [nq,k] int32-viewed uint32 or float32,
     steps int32-viewed uint32 [nq]), all on the device.
     """
@@ -229,6 +232,7 @@ def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
                          trace.data_ptr() if trace is not None else None,
                          trace.shape[1] if trace is not None else 0,
                          times.data_ptr() if times is not None else None,
+                         phases.data_ptr() if phases is not None else None,
                          transport, spin_limit)
     st = stream if stream is not None else torch.cuda.current_stream(dev)
     _check(load_library().ann_search(index.handle, queries.data_ptr(), nq, k, L, R,

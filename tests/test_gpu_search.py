@@ -229,3 +229,27 @@ def test_invalid_arguments(cfg1):
     with pytest.raises(fa.flashann.AnnError) as e:
         fa.Index(base, adj, base.shape[0], 256)  # entry out of range
     assert e.value.code == -22
+
+
+def test_phase_stamps_do_not_change_results(cfg1):
+    base, q, adj, entry = cfg1
+    phases = torch.zeros((q.shape[0], 2), dtype=torch.int64, device=dev())
+    with fa.Index(base, adj, entry, 256, fa.TIER_HOST) as ix:
+        g = gpu_search(ix, q, 10, 64, delay=0, phases=phases)
+        with pytest.raises(fa.AnnError):
+            gpu_search(ix, q, 10, 64, delay=1, phases=phases)   # strict schedule only
+    ref = oracle.search(base, adj, entry, q, 10, 64, delay=0)
+    assert_int_parity(g, ref)
+    ph = phases.cpu().numpy()
+    assert (ph > 0).all()
+
+
+def test_degree_selector_small():
+    from paper_2507_10070_amd import degree_selector
+
+    rows = degree_selector.profile_degrees([8, 24], n=4000, d=32, dtype="u8", components=8,
+                                           slot=256, tier="host", nq=300, L=32)
+    assert [r["R"] for r in rows] == [8, 24]
+    for r in rows:
+        assert r["T_f_us"] > 0 and r["T_c_us"] > 0 and r["expansions"] > 0
+    assert degree_selector.select(rows) in (8, 24)
