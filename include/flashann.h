@@ -105,6 +105,19 @@ typedef struct {
   int32_t transport;       /* ann_transport (0 = AUTO) */
   uint32_t spin_limit;     /* AGENT: polls of a completion word before the query
                               gives up with ANN_ETIMEDOUT (0 = default 2^24) */
+  /* Batches of uneven searches (one kernel for all): */
+  const int32_t *d_L;      /* optional device array, nq: per-query list size,
+                              clamped to [1, L]; L is then the batch maximum */
+  const int32_t *d_k;      /* optional device array, nq: per-query result count,
+                              clamped to [1, min(k, L_q)]; rows keep stride k and
+                              are padded past k_q like missing results */
+  const int32_t *d_order;  /* optional device array, nq: processing order (a
+                              permutation of 0..nq-1), e.g. longest search first */
+  int32_t persistent;      /* 1: one wave per resident slot of the GPU; waves take
+                              the next query from a device work counter when
+                              done, so long and short searches share the kernel.
+                              Persistent searches on one index must be ordered
+                              (one stream or synchronised). */
 } ann_search_opts;
 
 /*
@@ -194,6 +207,21 @@ int ann_index_info_get(const ann_index *ix, ann_index_info *out);
 int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int32_t L, int32_t R,
                const ann_search_opts *opts, int32_t *d_ids, void *d_dists, uint32_t *d_steps,
                void *hip_stream);
+
+/*
+ * ann_search_graph -- record one persistent ann_search (DIRECT transport) in
+ * a HIP graph: a kernel that zeroes the work counter, then the search.  All
+ * arguments and buffers are captured as given; ann_graph_launch replays the
+ * same search (the caller may rewrite the contents of the query and per-query
+ * buffers between replays).  `hip_stream` must be a non-default stream.
+ * Errors: as ann_search, plus ANN_EINVAL for the default stream or AGENT.
+ */
+typedef struct ann_graph ann_graph;
+int ann_search_graph(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int32_t L,
+                     int32_t R, const ann_search_opts *opts, int32_t *d_ids, void *d_dists,
+                     uint32_t *d_steps, void *hip_stream, ann_graph **out);
+int ann_graph_launch(ann_graph *g, void *hip_stream);
+int ann_graph_free(ann_graph *g);
 
 /* ann_device_clock_khz -- frequency of the device wall clock used by
  * ann_search_opts.d_times on the current device (host int, caller-owned). */

@@ -52,6 +52,12 @@ struct ann_index {
   uint8_t *stage = nullptr;         // fine-grained pinned host
   int32_t *d_status = nullptr;      // device
   int64_t tcap = 0, stage_stride = 0;
+  uint32_t *d_work = nullptr;       // persistent launches: device work counter
+};
+
+struct ann_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -95,6 +101,7 @@ void free_transport(ann_index *ix) {
 void release(ann_index *ix) {
   if (!ix) return;
   free_transport(ix);
+  if (ix->d_work) (void)hipFree(ix->d_work);
   if (ix->nav) (void)hipFree(ix->nav);
   if (ix->rec_hbm) (void)hipFree(ix->rec_hbm);
   if (ix->rec_host) (void)hipHostFree(ix->rec_host);
@@ -491,9 +498,17 @@ int ann_agent_stats(const ann_index *ix, uint64_t *requests, uint64_t *bytes, ui
   return ANN_OK;
 }
 
-int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int32_t L, int32_t R,
-               const ann_search_opts *opts, int32_t *d_ids, void *d_dists, uint32_t *d_steps,
-               void *hip_stream) {
+}  // extern "C"
+
+namespace {
+
+// Validates a search and fills the kernel arguments.  Returns ANN_OK with
+// *empty set when there is nothing to launch (nq == 0).
+int prepare_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int32_t L,
+                   int32_t R, const ann_search_opts *opts, int32_t *d_ids, void *d_dists,
+                   uint32_t *d_steps, ann_search_opts *o_out, int *transport_out,
+                   fa::SearchArgs *args, bool *empty) {
+  *empty = false;
   if (!ix) return fail(ANN_EINVAL, "index is NULL");
   if (nq < 0) return fail(ANN_EINVAL, "nq=%lld", (long long)nq);
   if (k < 1) return fail(ANN_EINVAL, "k=%d must be >= 1", k);
@@ -525,10 +540,22 @@ int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int3
     return fail(ANN_EINVAL, "a file tier is read through the agent transport only");
   if (transport == ANN_TRANSPORT_AGENT && ix->tier == ANN_TIER_HBM)
     return fail(ANN_EINVAL, "HBM records are read directly by the kernel");
-  if (nq == 0) return ANN_OK;
+  if (o.persistent != 0 && o.persistent != 1) return fail(ANN_EINVAL, "persistent=%d", o.persistent);
+  if (nq > 0x7FFFFFFFll) return fail(ANN_EINVAL, "nq=%lld too large", (long long)nq);
+  *o_out = o;
+  *transport_out = transport;
+  if (nq == 0) {
+    *empty = true;
+    return ANN_OK;
+  }
   if (!d_queries || !d_ids || !d_dists) return fail(ANN_EINVAL, "NULL query/output pointer");
+  if (o.persistent && !ix->d_work) {
+    hipError_t e = hipMalloc(&ix->d_work, sizeof(uint32_t));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(work counter)");
+  }
 
-  fa::SearchArgs a{};
+  fa::SearchArgs &a = *args;
+  a = fa::SearchArgs{};
   a.nav = ix->nav;
   a.records = ix->rec_dev;
   a.queries = (const uint8_t *)d_queries;
@@ -544,14 +571,40 @@ int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int3
   a.nav_stride = ix->nav_stride; a.qbytes = ix->vec_bytes; a.vec_pad = ix->vec_pad;
   a.ids_off = ix->vec_pad; a.rec_chunks = ix->rec_chunks;
   a.R = R; a.L = L; a.Lcap = (int32_t)round_up(L, 64); a.k = k; a.entry = ix->entry;
+  a.k_stride = k;
+  a.q_L = o.d_L;
+  a.q_k = o.d_k;
+  a.order = o.d_order;
+  a.work = ix->d_work;
   a.hash_bits = o.hash_bits;
   a.lds_per_wave = fa::search_lds_bytes(a.Lcap, a.nav_stride, a.hash_bits);
   if ((int64_t)a.lds_per_wave * o.waves_per_block > 160 * 1024)
     return fail(ANN_EINVAL, "LDS need %u B per query x %d exceeds 160 KiB", a.lds_per_wave,
                 o.waves_per_block);
+  return ANN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int32_t L, int32_t R,
+               const ann_search_opts *opts, int32_t *d_ids, void *d_dists, uint32_t *d_steps,
+               void *hip_stream) {
+  ann_search_opts o;
+  int transport = 0;
+  fa::SearchArgs a;
+  bool empty = false;
+  int rc = prepare_search(ix, d_queries, nq, k, L, R, opts, d_ids, d_dists, d_steps, &o,
+                          &transport, &a, &empty);
+  if (rc || empty) return rc;
   hipStream_t st = (hipStream_t)hip_stream;
   if (transport == ANN_TRANSPORT_DIRECT) {
-    hipError_t e = fa::launch_search(a, ix->dtype, o.delay, fa::TR_DIRECT, o.waves_per_block, st);
+    hipError_t e = hipSuccess;
+    if (o.persistent) e = fa::launch_reset(ix->d_work, st);
+    if (e == hipSuccess)
+      e = fa::launch_search(a, ix->dtype, o.delay, fa::TR_DIRECT, o.waves_per_block,
+                            o.persistent != 0, st);
     if (e != hipSuccess) return hip_fail(e, "search launch");
     return ANN_OK;
   }
@@ -559,7 +612,7 @@ int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int3
   // Query-grained transport: arm the agent, run, wait, disarm.  Synchronous
   // with respect to the host so that the request, completion and staging
   // arrays are never reused while a kernel may still touch them.
-  int rc = ensure_transport(ix, nq);
+  rc = ensure_transport(ix, nq);
   if (rc) return rc;
   hipError_t e = hipStreamSynchronize(st);  // earlier work on the stream
   if (e != hipSuccess) return hip_fail(e, "stream sync");
@@ -576,7 +629,10 @@ int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int3
   if (!a.req || !a.cpl || !a.stage) return fail(ANN_EIO, "transport buffers not mapped");
   ix->agent->faults = ix->faults;
   ix->agent->arm(ix->req, ix->cpl, ix->stage, nq, ix->stage_stride);
-  e = fa::launch_search(a, ix->dtype, o.delay, fa::TR_AGENT, o.waves_per_block, st);
+  if (o.persistent) e = fa::launch_reset(ix->d_work, st);
+  if (e == hipSuccess)
+    e = fa::launch_search(a, ix->dtype, o.delay, fa::TR_AGENT, o.waves_per_block,
+                          o.persistent != 0, st);
   const hipError_t es = e == hipSuccess ? hipStreamSynchronize(st) : e;
   ix->agent->disarm();
   if (e != hipSuccess) return hip_fail(e, "search launch");
@@ -601,6 +657,62 @@ int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int3
                 (long long)bad, (long long)first, code == ANN_ETIMEDOUT ? "timed out" : "read error",
                 en ? ": " : "", en ? std::strerror(en) : "");
   }
+  return ANN_OK;
+}
+
+int ann_search_graph(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int32_t L,
+                     int32_t R, const ann_search_opts *opts, int32_t *d_ids, void *d_dists,
+                     uint32_t *d_steps, void *hip_stream, ann_graph **out) {
+  if (!out) return fail(ANN_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!hip_stream) return fail(ANN_EINVAL, "graph capture needs a non-default stream");
+  ann_search_opts o0{};
+  o0.delay = 1;
+  o0.beam_width = 1;
+  if (opts) o0 = *opts;
+  o0.persistent = 1;
+  ann_search_opts o;
+  int transport = 0;
+  fa::SearchArgs a;
+  bool empty = false;
+  int rc = prepare_search(ix, d_queries, nq, k, L, R, &o0, d_ids, d_dists, d_steps, &o,
+                          &transport, &a, &empty);
+  if (rc) return rc;
+  if (empty) return fail(ANN_EINVAL, "nothing to capture (nq == 0)");
+  if (transport != ANN_TRANSPORT_DIRECT)
+    return fail(ANN_EINVAL, "graphs capture the DIRECT transport only");
+  hipStream_t st = (hipStream_t)hip_stream;
+  ann_graph *g = new (std::nothrow) ann_graph();
+  if (!g) return fail(ANN_ENOMEM, "graph handle");
+  hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t e1 = fa::launch_reset(ix->d_work, st);
+    if (e1 == hipSuccess)
+      e1 = fa::launch_search(a, ix->dtype, o.delay, fa::TR_DIRECT, o.waves_per_block, true, st);
+    e = hipStreamEndCapture(st, &g->graph);
+    if (e == hipSuccess) e = e1;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    ann_graph_free(g);
+    return hip_fail(e, "graph capture");
+  }
+  *out = g;
+  return ANN_OK;
+}
+
+int ann_graph_launch(ann_graph *g, void *hip_stream) {
+  if (!g || !g->exec) return fail(ANN_EINVAL, "graph is NULL");
+  hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "graph launch");
+  return ANN_OK;
+}
+
+int ann_graph_free(ann_graph *g) {
+  if (!g) return ANN_OK;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
   return ANN_OK;
 }
 

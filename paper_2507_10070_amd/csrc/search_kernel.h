@@ -40,12 +40,22 @@ struct SearchArgs {
   int32_t trace_cap;
   int64_t nq, n, slot;
   int32_t nav_stride, qbytes, vec_pad, ids_off, rec_chunks;
-  int32_t R, L, Lcap, k, entry, hash_bits;
+  int32_t R, L, Lcap, k, entry, hash_bits;  // L, k: batch maxima when per-query arrays are set
+  int32_t k_stride;        // output row stride (>= k)
+  const int32_t *q_L;      // optional per-query L (clamped to [1, L])
+  const int32_t *q_k;      // optional per-query k (clamped to [1, min(k, L_q)])
+  const int32_t *order;    // optional processing order (persistent launches)
+  uint32_t *work;          // persistent launches: device work counter, zero at launch
   uint32_t lds_per_wave;
 };
 
 uint32_t search_lds_bytes(int Lcap, int nav_stride, int hash_bits);
+// persistent: grid sized to the resident capacity of the GPU; waves take
+// queries from a->work (which must be zero at launch) until all are done.
 hipError_t launch_search(const SearchArgs &a, int dtype, int delay, int transport,
-                         int waves_per_block, hipStream_t st);
+                         int waves_per_block, bool persistent, hipStream_t st);
+// Zero the persistent work counter (a kernel, so that it can be captured in a
+// graph).
+hipError_t launch_reset(uint32_t *work, hipStream_t st);
 
 }  // namespace fa

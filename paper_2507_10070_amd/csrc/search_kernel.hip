@@ -223,6 +223,7 @@ struct Searcher {
   uint4 qv[CPL];
   Acc qq;
   int nc;
+  int L, k;       // this query's list size and result count
   int64_t qi;
   uint32_t steps, rows, mismatches;
   uint32_t seq;   // TR_AGENT: last request number of this query
@@ -241,6 +242,17 @@ struct Searcher {
     S.ids = (uint32_t *)(base + lay.ids);
     S.dsc = (uint32_t *)(base + lay.dsc);
     S.hash = (uint32_t *)(base + lay.hash);
+    L = A.L;
+    k = A.k;
+    if (A.q_L) {
+      const int l = A.q_L[qi];
+      L = l < 1 ? 1 : (l > A.L ? A.L : l);
+    }
+    if (A.q_k) {
+      const int kk = A.q_k[qi];
+      k = kk < 1 ? 1 : (kk > A.k ? A.k : kk);
+    }
+    if (k > L) k = L;
     // query -> LDS, zero padded to the row stride
     const uint8_t *q = A.queries + qi * (int64_t)A.qbytes;
     for (int b = lane; b < A.nav_stride; b += 64) S.qbuf[b] = b < A.qbytes ? q[b] : (uint8_t)0;
@@ -440,7 +452,7 @@ struct Searcher {
     if (key != kNoKey) {
       const int r = lower_bound(S.cand, nc, key);
       const bool dup = r < nc && kmask(S.cand[r]) == key;
-      if (dup || r >= A.L) key = kNoKey;
+      if (dup || r >= L) key = kNoKey;
     }
     if (__ballot(key != kNoKey) == 0) return;
     key = wave_sort64(key);
@@ -468,17 +480,17 @@ struct Searcher {
     for (int t = nchunks - 1; t >= 0; t--) {
       const int i = 64 * t + lane;
       uint64_t e = 0;
-      int pos = A.L;
+      int pos = L;
       if (i < nc) {
         e = S.cand[i];
         pos = i + lower_bound(S.nk, m2, kmask(e));
       }
       __builtin_amdgcn_wave_barrier();
-      if (i < nc && pos < A.L) S.cand[pos] = e;
+      if (i < nc && pos < L) S.cand[pos] = e;
       __builtin_amdgcn_wave_barrier();
     }
-    if (lane < m2 && lane + rnew < A.L) S.cand[lane + rnew] = key;
-    nc = nc + m2 < A.L ? nc + m2 : A.L;
+    if (lane < m2 && lane + rnew < L) S.cand[lane + rnew] = key;
+    nc = nc + m2 < L ? nc + m2 : L;
     __builtin_amdgcn_wave_barrier();
   }
 
@@ -540,16 +552,16 @@ struct Searcher {
   }
 
   __device__ void finish_query(int64_t qi) {
-    for (int j = lane; j < A.k; j += 64) {
+    for (int j = lane; j < A.k_stride; j += 64) {
       int32_t id = -1;
       uint32_t dist = DT == DT_F32 ? 0x7F800000u : 0xFFFFFFFFu;
-      if (j < nc && !failed) {
+      if (j < nc && j < k && !failed) {
         const uint64_t e = S.cand[j];
         id = (int32_t)((uint32_t)e & ~kFlag);
         dist = (uint32_t)(e >> 32);
       }
-      A.out_ids[qi * A.k + j] = id;
-      ((uint32_t *)A.out_dists)[qi * A.k + j] = dist;
+      A.out_ids[qi * A.k_stride + j] = id;
+      ((uint32_t *)A.out_dists)[qi * A.k_stride + j] = dist;
     }
     if (lane == 0) {
       if (A.out_steps) A.out_steps[qi] = steps;
@@ -565,14 +577,11 @@ struct Searcher {
 // Strict and relaxed drivers.  The relaxed loop is unrolled twice so the two
 // in-flight record registers have static names; a slot whose id word holds
 // kNoKey is an empty pipeline slot.
+// One query, start to finish, in the wave's LDS region.
 template <int DT, int CPL, int DELAY, int TR>
-__global__ void __launch_bounds__(256) search_kernel(SearchArgs A) {
-  extern __shared__ __align__(16) uint8_t smem[];
-  const int wave = threadIdx.x >> 6;
-  const int64_t qi = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
-  if (qi >= A.nq) return;
+__device__ __forceinline__ void run_query(const SearchArgs &A, uint8_t *lds, int64_t qi) {
   const unsigned long long t_start = A.times ? __builtin_amdgcn_s_memrealtime() : 0ull;
-  Searcher<DT, CPL, TR> s(A, smem + (size_t)wave * A.lds_per_wave, qi);
+  Searcher<DT, CPL, TR> s(A, lds, qi);
   s.init_entry();
   if (DELAY == 0) {
     uint4 unused = make_uint4(0, 0, 0, 0);
@@ -633,34 +642,80 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs A) {
   }
 }
 
+template <int DT, int CPL, int DELAY, int TR, bool PERSIST>
+__global__ void __launch_bounds__(256) search_kernel(SearchArgs A) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int wave = threadIdx.x >> 6;
+  uint8_t *lds = smem + (size_t)wave * A.lds_per_wave;
+  if (!PERSIST) {
+    const int64_t qi = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (qi >= A.nq) return;
+    run_query<DT, CPL, DELAY, TR>(A, lds, qi);
+    return;
+  }
+  // Persistent: take queries from the work counter until none is left; every
+  // wave leaves once the counter has passed nq.
+  for (;;) {
+    uint32_t t = 0;
+    if (lane_id() == 0) t = atomicAdd(A.work, 1u);
+    t = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
+    if ((int64_t)t >= A.nq) break;
+    const int64_t qi = A.order ? (int64_t)A.order[t] : (int64_t)t;
+    if (qi < 0 || qi >= A.nq) continue;  // not a permutation entry: skipped
+    run_query<DT, CPL, DELAY, TR>(A, lds, qi);
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+__global__ void reset_work(uint32_t *work) { *work = 0u; }
+
 template <int DT, int CPL, int DELAY, int TR>
-static hipError_t launch_t(const SearchArgs &a, int waves_per_block, hipStream_t st) {
-  const int64_t blocks = (a.nq + waves_per_block - 1) / waves_per_block;
+static hipError_t launch_t(const SearchArgs &a, int waves_per_block, bool persistent,
+                           hipStream_t st) {
   const size_t lds = (size_t)a.lds_per_wave * waves_per_block;
-  hipLaunchKernelGGL((search_kernel<DT, CPL, DELAY, TR>), dim3((unsigned)blocks),
-                     dim3(64 * waves_per_block), lds, st, a);
+  const int threads = 64 * waves_per_block;
+  if (!persistent) {
+    const int64_t blocks = (a.nq + waves_per_block - 1) / waves_per_block;
+    hipLaunchKernelGGL((search_kernel<DT, CPL, DELAY, TR, false>), dim3((unsigned)blocks),
+                       dim3(threads), lds, st, a);
+    return hipGetLastError();
+  }
+  int per_cu = 0, dev = 0, cus = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, (const void *)search_kernel<DT, CPL, DELAY, TR, true>, threads, lds);
+  if (e != hipSuccess) return e;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return e;
+  int64_t blocks = (int64_t)(per_cu > 0 ? per_cu : 1) * cus;
+  const int64_t need = (a.nq + waves_per_block - 1) / waves_per_block;
+  if (blocks > need) blocks = need;
+  hipLaunchKernelGGL((search_kernel<DT, CPL, DELAY, TR, true>), dim3((unsigned)blocks),
+                     dim3(threads), lds, st, a);
   return hipGetLastError();
 }
 
 template <int DT, int CPL, int TR>
-static hipError_t launch_d(const SearchArgs &a, int delay, int wpb, hipStream_t st) {
-  return delay == 0 ? launch_t<DT, CPL, 0, TR>(a, wpb, st) : launch_t<DT, CPL, 1, TR>(a, wpb, st);
+static hipError_t launch_d(const SearchArgs &a, int delay, int wpb, bool pers, hipStream_t st) {
+  return delay == 0 ? launch_t<DT, CPL, 0, TR>(a, wpb, pers, st)
+                    : launch_t<DT, CPL, 1, TR>(a, wpb, pers, st);
 }
 
 template <int DT, int CPL>
-static hipError_t launch_tr(const SearchArgs &a, int delay, int tr, int wpb, hipStream_t st) {
-  return tr == TR_DIRECT ? launch_d<DT, CPL, TR_DIRECT>(a, delay, wpb, st)
-                         : launch_d<DT, CPL, TR_AGENT>(a, delay, wpb, st);
+static hipError_t launch_tr(const SearchArgs &a, int delay, int tr, int wpb, bool pers,
+                            hipStream_t st) {
+  return tr == TR_DIRECT ? launch_d<DT, CPL, TR_DIRECT>(a, delay, wpb, pers, st)
+                         : launch_d<DT, CPL, TR_AGENT>(a, delay, wpb, pers, st);
 }
 
 template <int DT>
-static hipError_t launch_c(const SearchArgs &a, int cpl, int delay, int tr, int wpb,
+static hipError_t launch_c(const SearchArgs &a, int cpl, int delay, int tr, int wpb, bool pers,
                            hipStream_t st) {
   switch (cpl) {
-    case 1: return launch_tr<DT, 1>(a, delay, tr, wpb, st);
-    case 2: return launch_tr<DT, 2>(a, delay, tr, wpb, st);
-    case 3: return launch_tr<DT, 3>(a, delay, tr, wpb, st);
-    case 4: return launch_tr<DT, 4>(a, delay, tr, wpb, st);
+    case 1: return launch_tr<DT, 1>(a, delay, tr, wpb, pers, st);
+    case 2: return launch_tr<DT, 2>(a, delay, tr, wpb, pers, st);
+    case 3: return launch_tr<DT, 3>(a, delay, tr, wpb, pers, st);
+    case 4: return launch_tr<DT, 4>(a, delay, tr, wpb, pers, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -670,14 +725,19 @@ uint32_t search_lds_bytes(int Lcap, int nav_stride, int hash_bits) {
 }
 
 hipError_t launch_search(const SearchArgs &a, int dtype, int delay, int transport,
-                         int waves_per_block, hipStream_t st) {
+                         int waves_per_block, bool persistent, hipStream_t st) {
   const int cpl = a.nav_stride / 128;
   switch (dtype) {
-    case DT_U8: return launch_c<DT_U8>(a, cpl, delay, transport, waves_per_block, st);
-    case DT_I8: return launch_c<DT_I8>(a, cpl, delay, transport, waves_per_block, st);
-    case DT_F32: return launch_c<DT_F32>(a, cpl, delay, transport, waves_per_block, st);
+    case DT_U8: return launch_c<DT_U8>(a, cpl, delay, transport, waves_per_block, persistent, st);
+    case DT_I8: return launch_c<DT_I8>(a, cpl, delay, transport, waves_per_block, persistent, st);
+    case DT_F32: return launch_c<DT_F32>(a, cpl, delay, transport, waves_per_block, persistent, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_reset(uint32_t *work, hipStream_t st) {
+  hipLaunchKernelGGL(reset_work, dim3(1), dim3(1), 0, st, work);
+  return hipGetLastError();
 }
 
 }  // namespace fa

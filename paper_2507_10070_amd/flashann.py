@@ -22,7 +22,8 @@ TRANSPORT_AUTO, TRANSPORT_DIRECT, TRANSPORT_AGENT = 0, 1, 2
 
 EXPORTED = ["ann_index_create", "ann_index_info_get", "ann_search", "ann_index_free",
             "ann_last_error", "ann_device_clock_khz", "ann_save_index", "ann_build_index",
-            "ann_load_records", "ann_agent_configure", "ann_agent_stats"]
+            "ann_load_records", "ann_agent_configure", "ann_agent_stats", "ann_search_graph",
+            "ann_graph_launch", "ann_graph_free"]
 
 
 class AnnError(RuntimeError):
@@ -37,7 +38,9 @@ class SearchOptions(ctypes.Structure):
                 ("d_stats", ctypes.c_void_p), ("d_trace", ctypes.c_void_p),
                 ("trace_cap", ctypes.c_int32), ("d_times", ctypes.c_void_p),
                 ("d_phases", ctypes.c_void_p), ("transport", ctypes.c_int32),
-                ("spin_limit", ctypes.c_uint32)]
+                ("spin_limit", ctypes.c_uint32), ("d_L", ctypes.c_void_p),
+                ("d_k", ctypes.c_void_p), ("d_order", ctypes.c_void_p),
+                ("persistent", ctypes.c_int32)]
 
 
 class IndexInfo(ctypes.Structure):
@@ -81,6 +84,13 @@ def load_library(path: str = LIB_PATH):
     lib.ann_agent_configure.restype = ctypes.c_int
     lib.ann_agent_stats.argtypes = [vp, u64p, u64p, u64p]
     lib.ann_agent_stats.restype = ctypes.c_int
+    lib.ann_search_graph.argtypes = [vp, vp, i64, i32, i32, i32, ctypes.POINTER(SearchOptions),
+                                     vp, vp, vp, vp, ctypes.POINTER(vp)]
+    lib.ann_search_graph.restype = ctypes.c_int
+    lib.ann_graph_launch.argtypes = [vp, vp]
+    lib.ann_graph_launch.restype = ctypes.c_int
+    lib.ann_graph_free.argtypes = [vp]
+    lib.ann_graph_free.restype = ctypes.c_int
     lib.ann_device_clock_khz.argtypes = [ctypes.POINTER(ctypes.c_int32)]
     lib.ann_device_clock_khz.restype = ctypes.c_int
     lib.ann_last_error.argtypes = []
@@ -195,21 +205,13 @@ class Index:
         self.close()
 
 
-def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
-           beam_width: int = 1, hash_bits: int = 0, waves_per_block: int = 0, stats=None,
-           trace=None, times=None, phases=None, transport: int = TRANSPORT_AUTO,
-           spin_limit: int = 0, stream=None, out=None):
-    """ann_search on torch CUDA tensors.
+def _ptr(t):
+    return t.data_ptr() if t is not None else None
 
-    queries: [nq, d] device tensor of the index dtype (uint8/int8/float32).
-    stats: optional int64 device tensor of 3 counters (accumulated);
-    trace: optional int32 device tensor [nq, cap] receiving expanded ids;
-    times: optional int64 device tensor [nq, 2] receiving start/end stamps;
-    phases: optional int64 device tensor [nq, 2] (strict only): summed fetch and
-    compute ticks per query.
-    Returns (ids int32 [nq,k], dists [nq,k] int32-viewed uint32 or float32,
-    steps int32-viewed uint32 [nq]), all on the device.
-    """
+
+def _prepare(index, queries, k, L, R, delay, beam_width, hash_bits, waves_per_block, stats,
+             trace, times, phases, transport, spin_limit, L_per_query, k_per_query, order,
+             persistent, out):
     import torch
 
     if queries.dim() != 2 or queries.shape[1] != index.d:
@@ -218,6 +220,10 @@ def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
             np.dtype(np.float32): torch.float32}[index.dtype]
     if queries.dtype != want or not queries.is_cuda or not queries.is_contiguous():
         raise ValueError("queries must be a contiguous CUDA %s tensor" % want)
+    for name, t in (("L_per_query", L_per_query), ("k_per_query", k_per_query),
+                    ("order", order)):
+        if t is not None and (t.dtype != torch.int32 or not t.is_cuda or t.numel() != queries.shape[0]):
+            raise ValueError("%s must be a CUDA int32 tensor of nq entries" % name)
     nq = queries.shape[0]
     dev = queries.device
     if out is None:
@@ -227,16 +233,77 @@ def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
         steps = torch.empty((nq,), dtype=torch.int32, device=dev)
     else:
         ids, dists, steps = out
-    opts = SearchOptions(delay, beam_width, hash_bits, waves_per_block,
-                         stats.data_ptr() if stats is not None else None,
-                         trace.data_ptr() if trace is not None else None,
-                         trace.shape[1] if trace is not None else 0,
-                         times.data_ptr() if times is not None else None,
-                         phases.data_ptr() if phases is not None else None,
-                         transport, spin_limit)
-    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    opts = SearchOptions(delay, beam_width, hash_bits, waves_per_block, _ptr(stats), _ptr(trace),
+                         trace.shape[1] if trace is not None else 0, _ptr(times), _ptr(phases),
+                         transport, spin_limit, _ptr(L_per_query), _ptr(k_per_query), _ptr(order),
+                         1 if persistent else 0)
+    return nq, ids, dists, steps, opts
+
+
+def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
+           beam_width: int = 1, hash_bits: int = 0, waves_per_block: int = 0, stats=None,
+           trace=None, times=None, phases=None, transport: int = TRANSPORT_AUTO,
+           spin_limit: int = 0, L_per_query=None, k_per_query=None, order=None,
+           persistent: bool = False, stream=None, out=None):
+    """ann_search on torch CUDA tensors.
+
+    queries: [nq, d] device tensor of the index dtype (uint8/int8/float32).
+    stats: optional int64 device tensor of 3 counters (accumulated);
+    trace: optional int32 device tensor [nq, cap] receiving expanded ids;
+    times: optional int64 device tensor [nq, 2] receiving start/end stamps;
+    phases: optional int64 device tensor [nq, 2] (strict only): summed fetch and
+    compute ticks per query;
+    L_per_query / k_per_query / order: optional int32 device tensors [nq]
+    (uneven batches; L and k are then the batch maxima).
+    Returns (ids int32 [nq,k], dists [nq,k] int32-viewed uint32 or float32,
+    steps int32-viewed uint32 [nq]), all on the device.
+    """
+    import torch
+
+    nq, ids, dists, steps, opts = _prepare(index, queries, k, L, R, delay, beam_width, hash_bits,
+                                           waves_per_block, stats, trace, times, phases,
+                                           transport, spin_limit, L_per_query, k_per_query,
+                                           order, persistent, out)
+    st = stream if stream is not None else torch.cuda.current_stream(queries.device)
     _check(load_library().ann_search(index.handle, queries.data_ptr(), nq, k, L, R,
                                      ctypes.byref(opts), ids.data_ptr(), dists.data_ptr(),
                                      steps.data_ptr() if steps is not None else None,
                                      st.cuda_stream))
     return ids, dists, steps
+
+
+class SearchGraph:
+    """ann_search_graph: one persistent search captured in a HIP graph.
+
+    The graph keeps the tensors it was recorded with; rewrite their contents
+    and call launch() to replay.  `stream` must not be the default stream.
+    """
+
+    def __init__(self, index: Index, queries, k: int, L: int, stream, R: int = 0,
+                 delay: int = 1, hash_bits: int = 0, waves_per_block: int = 0,
+                 L_per_query=None, k_per_query=None, order=None, out=None):
+        nq, ids, dists, steps, opts = _prepare(index, queries, k, L, R, delay, 1, hash_bits,
+                                               waves_per_block, None, None, None, None,
+                                               TRANSPORT_DIRECT, 0, L_per_query, k_per_query,
+                                               order, True, out)
+        self._keep = (index, queries, ids, dists, steps, L_per_query, k_per_query, order)
+        self.ids, self.dists, self.steps = ids, dists, steps
+        self.stream = stream
+        g = ctypes.c_void_p()
+        _check(load_library().ann_search_graph(index.handle, queries.data_ptr(), nq, k, L, R,
+                                               ctypes.byref(opts), ids.data_ptr(),
+                                               dists.data_ptr(), steps.data_ptr(),
+                                               stream.cuda_stream, ctypes.byref(g)))
+        self._g = g
+
+    def launch(self, stream=None):
+        st = stream if stream is not None else self.stream
+        _check(load_library().ann_graph_launch(self._g, st.cuda_stream))
+        return self.ids, self.dists, self.steps
+
+    def close(self):
+        if getattr(self, "_g", None) is not None:
+            load_library().ann_graph_free(self._g)
+            self._g = None
+
+    __del__ = close
