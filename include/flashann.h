@@ -227,6 +227,55 @@ int ann_graph_free(ann_graph *g);
  * ann_search_opts.d_times on the current device (host int, caller-owned). */
 int ann_device_clock_khz(int32_t *khz);
 
+/*
+ * Continuous-batching service (search state stays on the device; arrivals
+ * are admitted as room frees up and overlap with queries already running).
+ *
+ * ann_server_open -- start a persistent server kernel over `ix` (HBM or HOST
+ * tier).  Each admitted query holds one entry of (16 + nav_stride) bytes of
+ * device memory until its results are out; `hbm_budget_bytes` bounds the
+ * number admitted at once (after one entry per resident GPU wave, which the
+ * ring keeps in reserve).  Arrivals beyond that wait on the host in arrival
+ * order.  The server does not hold any caller pointer.
+ *   opts (NULL = defaults): k_max (100), L_max (256), delay (1),
+ *   waves_per_block (4), hash_bits (10), queue_cap (2^20 waiting arrivals),
+ *   idle_polls (50000: empty polls before the kernel leaves; it is started
+ *   again when work arrives).
+ * Errors: ANN_EINVAL, ANN_ENOMEM (budget too small or allocation), ANN_EIO.
+ */
+typedef struct ann_server ann_server;
+typedef struct {
+  int32_t k_max, L_max, delay, waves_per_block, hash_bits, queue_cap, idle_polls;
+} ann_server_opts;
+typedef struct {
+  uint64_t tag;          /* the caller's tag */
+  int32_t status;        /* ANN_OK */
+  int32_t k;             /* results in ids/dists */
+  const int32_t *ids;    /* host, valid until the next ann_server_poll */
+  const void *dists;     /* host, uint32 (u8/i8) or float (f32), same lifetime */
+  uint32_t steps;        /* expansions */
+  double submit_us;      /* ann_clock_us() at submission */
+  double done_us;        /* ann_clock_us() when the host saw the result */
+} ann_result;
+typedef struct {
+  uint64_t submitted, admitted, completed, relaunches;
+  int64_t max_inflight, slots, resident_waves;
+} ann_server_stats;
+
+int ann_server_open(ann_index *ix, size_t hbm_budget_bytes, const ann_server_opts *opts,
+                    ann_server **out);
+/* Queue one query (host, d elements of the index dtype; copied).  1 <= k <= k_max,
+ * k <= L <= L_max.  ANN_EBUSY when the arrival queue is full. */
+int ann_server_submit(ann_server *s, const void *host_query, int32_t k, int32_t L, uint64_t tag);
+/* Take up to `max` completed results, waiting up to timeout_us for the first. */
+int ann_server_poll(ann_server *s, ann_result *out, int32_t max, int32_t *n_out,
+                    int32_t timeout_us);
+int ann_server_stats_get(ann_server *s, ann_server_stats *out);
+/* Finish every admitted and waiting query, stop the kernel, release all. */
+int ann_server_close(ann_server *s);
+/* Monotonic host clock (microseconds) of ann_result's time stamps. */
+double ann_clock_us(void);
+
 /* ann_index_free -- release everything the index holds (NULL is a no-op). */
 int ann_index_free(ann_index *ix);
 

@@ -6,6 +6,6 @@ Importing the package does not load the library; the first call does, and it
 raises if the library has not been built.
 """
 from .flashann import (ANN_ERRORS, AnnError, Index, SearchGraph, SearchOptions,  # noqa: F401
-                       load_library, search,
+                       Server, clock_us, load_library, search,
                        build_index, save_index, device_clock_khz, DTYPE_CODES, TIER_HBM,
                        TIER_HOST, TIER_FILE, TRANSPORT_AUTO, TRANSPORT_DIRECT, TRANSPORT_AGENT)

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libflashann.so")
-SOURCES = ["search_kernel.hip", "api.hip", "agent.cpp",
+SOURCES = ["search_kernel.hip", "api.hip", "agent.cpp", "server.cpp",
            # the graph builder of the input generators, for ann_build_index
            os.path.join("..", "..", "synth", "csrc", "graph_build.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

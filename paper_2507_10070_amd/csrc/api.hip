@@ -716,6 +716,41 @@ int ann_graph_free(ann_graph *g) {
   return ANN_OK;
 }
 
+}  // extern "C"
+
+// Shared with server.cpp: error reporting and the index fields of a search.
+int ann_internal_fail(int code, const char *msg) { return fail(code, "%s", msg); }
+
+int ann_internal_server_args(ann_index *ix, int32_t k_max, int32_t L_max, int32_t hash_bits,
+                             fa::SearchArgs *base, int32_t *dtype) {
+  if (ix->tier == ANN_TIER_FILE)
+    return fail(ANN_EINVAL, "the server reads records directly: HBM or HOST tier");
+  if (hash_bits < 6 || hash_bits > 14) return fail(ANN_EINVAL, "hash_bits=%d", hash_bits);
+  fa::SearchArgs &a = *base;
+  a = fa::SearchArgs{};
+  a.nav = ix->nav;
+  a.records = ix->rec_dev;
+  a.n = ix->n;
+  a.slot = ix->slot;
+  a.nav_stride = ix->nav_stride;
+  a.qbytes = ix->vec_bytes;
+  a.vec_pad = ix->vec_pad;
+  a.ids_off = ix->vec_pad;
+  a.rec_chunks = ix->rec_chunks;
+  a.R = ix->R;
+  a.L = L_max;
+  a.Lcap = (int32_t)round_up(L_max, 64);
+  a.k = k_max;
+  a.k_stride = k_max;
+  a.entry = ix->entry;
+  a.hash_bits = hash_bits;
+  a.lds_per_wave = fa::search_lds_bytes(a.Lcap, a.nav_stride, a.hash_bits);
+  *dtype = ix->dtype;
+  return ANN_OK;
+}
+
+extern "C" {
+
 int ann_device_clock_khz(int32_t *khz) {
   if (!khz) return fail(ANN_EINVAL, "khz is NULL");
   int dev = 0, v = 0;

@@ -50,6 +50,27 @@ struct SearchArgs {
 };
 
 uint32_t search_lds_bytes(int Lcap, int nav_stride, int hash_bits);
+// Continuous-batching server: a persistent kernel whose waves take queries
+// from a ring in device memory as the host publishes them.
+//   ring entry (entry_bytes): u32 seq+1, u32 result slot, u32 k | L << 16,
+//   u32 pad, then the query zero-padded to nav_stride bytes.
+struct ServerArgs {
+  SearchArgs base;          // index fields, Lcap / hash_bits for L_max; k = k_max
+  const uint8_t *ring;      // device, ring_cap entries
+  int64_t entry_bytes;
+  uint32_t ring_cap, nslots;
+  uint32_t *next;           // device: next ring index to claim
+  const uint32_t *published;  // device: entries published (written by the host's stream)
+  const uint32_t *stop;     // device: non-zero = leave once idle
+  int32_t *res_ids;         // host-mapped, nslots x k_max
+  uint32_t *res_dists;      // host-mapped, nslots x k_max
+  uint32_t *res_steps;      // host-mapped, nslots
+  uint32_t *done;           // host-mapped, nslots x 16 (one 64 B line per slot)
+  uint32_t idle_limit;      // empty polls before a wave leaves
+};
+hipError_t launch_server(const ServerArgs &a, int dtype, int delay, int waves_per_block,
+                         int64_t *resident_waves, hipStream_t st);
+
 // persistent: grid sized to the resident capacity of the GPU; waves take
 // queries from a->work (which must be zero at launch) until all are done.
 hipError_t launch_search(const SearchArgs &a, int dtype, int delay, int transport,

@@ -212,6 +212,38 @@ __host__ __device__ inline LdsLayout lds_layout(int Lcap, int nav_stride, int ha
   return o;
 }
 
+// Where one query's vector comes from and where its results go.
+struct QueryIO {
+  const uint8_t *q;   // nav_stride readable bytes when `coherent`
+  bool coherent;      // read q with system-scope loads (memory rewritten by copies)
+  int32_t *ids;       // row of `width` result ids
+  uint32_t *dists;    // row of `width` distances
+  uint32_t *steps;    // optional
+  int L, k, width;    // list size, results, row width (entries k..width-1 padded)
+};
+
+__device__ __forceinline__ QueryIO batch_io(const SearchArgs &A, int64_t qi) {
+  QueryIO io;
+  io.q = A.queries + qi * (int64_t)A.qbytes;
+  io.coherent = false;
+  io.ids = A.out_ids + qi * A.k_stride;
+  io.dists = (uint32_t *)A.out_dists + qi * A.k_stride;
+  io.steps = A.out_steps ? A.out_steps + qi : nullptr;
+  int L = A.L, k = A.k;
+  if (A.q_L) {
+    const int l = A.q_L[qi];
+    L = l < 1 ? 1 : (l > A.L ? A.L : l);
+  }
+  if (A.q_k) {
+    const int kk = A.q_k[qi];
+    k = kk < 1 ? 1 : (kk > A.k ? A.k : kk);
+  }
+  io.L = L;
+  io.k = k > L ? L : k;
+  io.width = A.k_stride;
+  return io;
+}
+
 template <int DT, int CPL, int TR>
 struct Searcher {
   using D = Dist<DT>;
@@ -224,13 +256,15 @@ struct Searcher {
   Acc qq;
   int nc;
   int L, k;       // this query's list size and result count
+  QueryIO io;
   int64_t qi;
   uint32_t steps, rows, mismatches;
   uint32_t seq;   // TR_AGENT: last request number of this query
   bool failed;    // TR_AGENT: a record read failed or timed out
   unsigned long long t_fetch, t_comp;  // summed phase ticks (strict, optional)
 
-  __device__ Searcher(const SearchArgs &args, uint8_t *base, int64_t query) : A(args), qi(query) {
+  __device__ Searcher(const SearchArgs &args, uint8_t *base, int64_t query, const QueryIO &qio)
+      : A(args), io(qio), qi(query) {
     lane = lane_id();
     sub = lane & 7;
     grp = lane >> 3;
@@ -242,20 +276,17 @@ struct Searcher {
     S.ids = (uint32_t *)(base + lay.ids);
     S.dsc = (uint32_t *)(base + lay.dsc);
     S.hash = (uint32_t *)(base + lay.hash);
-    L = A.L;
-    k = A.k;
-    if (A.q_L) {
-      const int l = A.q_L[qi];
-      L = l < 1 ? 1 : (l > A.L ? A.L : l);
-    }
-    if (A.q_k) {
-      const int kk = A.q_k[qi];
-      k = kk < 1 ? 1 : (kk > A.k ? A.k : kk);
-    }
-    if (k > L) k = L;
+    L = io.L;
+    k = io.k;
     // query -> LDS, zero padded to the row stride
-    const uint8_t *q = A.queries + qi * (int64_t)A.qbytes;
-    for (int b = lane; b < A.nav_stride; b += 64) S.qbuf[b] = b < A.qbytes ? q[b] : (uint8_t)0;
+    const uint8_t *q = io.q;
+    if (io.coherent) {
+      for (int w = lane; w < A.nav_stride / 4; w += 64)
+        ((uint32_t *)S.qbuf)[w] = __hip_atomic_load((const uint32_t *)q + w, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_SYSTEM);
+    } else {
+      for (int b = lane; b < A.nav_stride; b += 64) S.qbuf[b] = b < A.qbytes ? q[b] : (uint8_t)0;
+    }
     for (int s = lane; s < (1 << A.hash_bits); s += 64) S.hash[s] = kEmpty;
     __builtin_amdgcn_wave_barrier();
     Acc a = Acc(0);
@@ -551,8 +582,8 @@ struct Searcher {
     }
   }
 
-  __device__ void finish_query(int64_t qi) {
-    for (int j = lane; j < A.k_stride; j += 64) {
+  __device__ void finish_query() {
+    for (int j = lane; j < io.width; j += 64) {
       int32_t id = -1;
       uint32_t dist = DT == DT_F32 ? 0x7F800000u : 0xFFFFFFFFu;
       if (j < nc && j < k && !failed) {
@@ -560,11 +591,11 @@ struct Searcher {
         id = (int32_t)((uint32_t)e & ~kFlag);
         dist = (uint32_t)(e >> 32);
       }
-      A.out_ids[qi * A.k_stride + j] = id;
-      ((uint32_t *)A.out_dists)[qi * A.k_stride + j] = dist;
+      io.ids[j] = id;
+      io.dists[j] = dist;
     }
     if (lane == 0) {
-      if (A.out_steps) A.out_steps[qi] = steps;
+      if (io.steps) *io.steps = steps;
       if (A.stats) {
         atomicAdd(&A.stats[0], (unsigned long long)steps);
         atomicAdd(&A.stats[1], (unsigned long long)rows);
@@ -579,9 +610,10 @@ struct Searcher {
 // kNoKey is an empty pipeline slot.
 // One query, start to finish, in the wave's LDS region.
 template <int DT, int CPL, int DELAY, int TR>
-__device__ __forceinline__ void run_query(const SearchArgs &A, uint8_t *lds, int64_t qi) {
+__device__ __forceinline__ void run_query(const SearchArgs &A, uint8_t *lds, int64_t qi,
+                                          const QueryIO &io) {
   const unsigned long long t_start = A.times ? __builtin_amdgcn_s_memrealtime() : 0ull;
-  Searcher<DT, CPL, TR> s(A, lds, qi);
+  Searcher<DT, CPL, TR> s(A, lds, qi, io);
   s.init_entry();
   if (DELAY == 0) {
     uint4 unused = make_uint4(0, 0, 0, 0);
@@ -635,7 +667,7 @@ __device__ __forceinline__ void run_query(const SearchArgs &A, uint8_t *lds, int
       else r1 = s.issue(f1, k1 != kNoKey);
     }
   }
-  s.finish_query(qi);
+  s.finish_query();
   if (A.times && s.lane == 0) {
     A.times[2 * qi] = t_start;
     A.times[2 * qi + 1] = __builtin_amdgcn_s_memrealtime();
@@ -650,7 +682,7 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs A) {
   if (!PERSIST) {
     const int64_t qi = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (qi >= A.nq) return;
-    run_query<DT, CPL, DELAY, TR>(A, lds, qi);
+    run_query<DT, CPL, DELAY, TR>(A, lds, qi, batch_io(A, qi));
     return;
   }
   // Persistent: take queries from the work counter until none is left; every
@@ -662,12 +694,73 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs A) {
     if ((int64_t)t >= A.nq) break;
     const int64_t qi = A.order ? (int64_t)A.order[t] : (int64_t)t;
     if (qi < 0 || qi >= A.nq) continue;  // not a permutation entry: skipped
-    run_query<DT, CPL, DELAY, TR>(A, lds, qi);
+    run_query<DT, CPL, DELAY, TR>(A, lds, qi, batch_io(A, qi));
     __builtin_amdgcn_wave_barrier();
   }
 }
 
 __global__ void reset_work(uint32_t *work) { *work = 0u; }
+
+// Continuous-batching server.  A wave claims ring index c only once the host
+// has published it (c < published), so a wave that leaves while idle holds no
+// claim.  The entry is read with system-scope loads because ring memory is
+// rewritten by host copies; results go to host-mapped rows, then the slot's
+// done word (system-scope release) tells the host.
+template <int DT, int CPL, int DELAY>
+__global__ void __launch_bounds__(256) server_kernel(ServerArgs S) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int wave = threadIdx.x >> 6;
+  const int lane = lane_id();
+  uint8_t *lds = smem + (size_t)wave * S.base.lds_per_wave;
+  for (;;) {
+    uint32_t got = 0xFFFFFFFFu;
+    if (lane == 0) {
+      uint32_t idle = 0, nap = 1;
+      for (;;) {
+        const uint32_t pub =
+            __hip_atomic_load(S.published, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+        const uint32_t c = __hip_atomic_load(S.next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (c < pub) {
+          if (atomicCAS(S.next, c, c + 1u) == c) {
+            got = c;
+            break;
+          }
+          continue;
+        }
+        if (__hip_atomic_load(S.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
+        if (++idle > S.idle_limit) break;
+        for (uint32_t i = 0; i < nap; i++) __builtin_amdgcn_s_sleep(8);
+        nap = nap < 8 ? nap * 2 : 8;
+      }
+    }
+    got = (uint32_t)__builtin_amdgcn_readfirstlane((int)got);
+    if (got == 0xFFFFFFFFu) return;
+    const uint8_t *e = S.ring + (int64_t)(got % S.ring_cap) * S.entry_bytes;
+    const uint32_t *ctrl = (const uint32_t *)e;
+    const uint32_t slot =
+        __hip_atomic_load(ctrl + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    const uint32_t kl = __hip_atomic_load(ctrl + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (slot >= S.nslots) continue;  // malformed entry: skipped
+    int k = (int)(kl & 0xFFFFu), L = (int)(kl >> 16);
+    L = L < 1 ? 1 : (L > S.base.L ? S.base.L : L);
+    k = k < 1 ? 1 : (k > S.base.k ? S.base.k : k);
+    if (k > L) k = L;
+    QueryIO io;
+    io.q = e + 16;
+    io.coherent = true;
+    io.ids = S.res_ids + (int64_t)slot * S.base.k;
+    io.dists = S.res_dists + (int64_t)slot * S.base.k;
+    io.steps = S.res_steps + slot;
+    io.L = L;
+    io.k = k;
+    io.width = k;
+    run_query<DT, CPL, DELAY, TR_DIRECT>(S.base, lds, (int64_t)slot, io);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    if (lane == 0)
+      __hip_atomic_store(S.done + 16 * (int64_t)slot, got + 1u, __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
 
 template <int DT, int CPL, int DELAY, int TR>
 static hipError_t launch_t(const SearchArgs &a, int waves_per_block, bool persistent,
@@ -731,6 +824,55 @@ hipError_t launch_search(const SearchArgs &a, int dtype, int delay, int transpor
     case DT_U8: return launch_c<DT_U8>(a, cpl, delay, transport, waves_per_block, persistent, st);
     case DT_I8: return launch_c<DT_I8>(a, cpl, delay, transport, waves_per_block, persistent, st);
     case DT_F32: return launch_c<DT_F32>(a, cpl, delay, transport, waves_per_block, persistent, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int DT, int CPL, int DELAY>
+static hipError_t launch_server_t(const ServerArgs &a, int wpb, int64_t *resident,
+                                  hipStream_t st) {
+  const size_t lds = (size_t)a.base.lds_per_wave * wpb;
+  const int threads = 64 * wpb;
+  int per_cu = 0, dev = 0, cus = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, (const void *)server_kernel<DT, CPL, DELAY>, threads, lds);
+  if (e != hipSuccess) return e;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return e;
+  const int64_t blocks = (int64_t)(per_cu > 0 ? per_cu : 1) * cus;
+  if (resident) *resident = blocks * wpb;
+  if (!st) return hipSuccess;  // size query only
+  hipLaunchKernelGGL((server_kernel<DT, CPL, DELAY>), dim3((unsigned)blocks), dim3(threads), lds,
+                     st, a);
+  return hipGetLastError();
+}
+
+template <int DT, int CPL>
+static hipError_t launch_server_d(const ServerArgs &a, int delay, int wpb, int64_t *res,
+                                  hipStream_t st) {
+  return delay == 0 ? launch_server_t<DT, CPL, 0>(a, wpb, res, st)
+                    : launch_server_t<DT, CPL, 1>(a, wpb, res, st);
+}
+
+template <int DT>
+static hipError_t launch_server_c(const ServerArgs &a, int delay, int wpb, int64_t *res,
+                                  hipStream_t st) {
+  switch (a.base.nav_stride / 128) {
+    case 1: return launch_server_d<DT, 1>(a, delay, wpb, res, st);
+    case 2: return launch_server_d<DT, 2>(a, delay, wpb, res, st);
+    case 3: return launch_server_d<DT, 3>(a, delay, wpb, res, st);
+    case 4: return launch_server_d<DT, 4>(a, delay, wpb, res, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_server(const ServerArgs &a, int dtype, int delay, int waves_per_block,
+                         int64_t *resident_waves, hipStream_t st) {
+  switch (dtype) {
+    case DT_U8: return launch_server_c<DT_U8>(a, delay, waves_per_block, resident_waves, st);
+    case DT_I8: return launch_server_c<DT_I8>(a, delay, waves_per_block, resident_waves, st);
+    case DT_F32: return launch_server_c<DT_F32>(a, delay, waves_per_block, resident_waves, st);
     default: return hipErrorInvalidValue;
   }
 }

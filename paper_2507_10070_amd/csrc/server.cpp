@@ -1,0 +1,457 @@
+// server.cpp -- continuous-batching search service over one index.
+//
+// Queries arrive one by one (ann_server_submit); an admission thread moves
+// them, in arrival order and while the HBM budget has room, into a ring in
+// device memory (one copy per batch) and then publishes the new count with a
+// stream write that is ordered after the copy.  The persistent server kernel
+// keeps running: each wave takes the next published query, searches it, and
+// writes its results into a host-mapped row plus a done word.  A reaper thread
+// turns done words into completed results and frees the slots, so arrivals
+// that come while others are on the GPU are admitted as room frees up and
+// overlap on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/flashann.h"
+#include "search_kernel.h"
+
+// Defined in api.hip.
+int ann_internal_server_args(ann_index *ix, int32_t k_max, int32_t L_max, int32_t hash_bits,
+                             fa::SearchArgs *base, int32_t *dtype);
+int ann_internal_fail(int code, const char *msg);
+
+namespace {
+
+double now_us() {
+  return std::chrono::duration<double, std::micro>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+struct Pending {
+  std::vector<uint8_t> q;
+  int32_t k, L;
+  uint64_t tag;
+  double submit_us;
+};
+
+struct Inflight {
+  uint64_t seq = 0;
+  uint64_t tag = 0;
+  int32_t k = 0;
+  double submit_us = 0;
+  bool used = false;
+};
+
+struct Done {
+  uint64_t tag;
+  int32_t k;
+  uint32_t steps;
+  double submit_us, done_us;
+  std::vector<int32_t> ids;
+  std::vector<uint32_t> dists;
+};
+
+}  // namespace
+
+struct ann_server {
+  ann_index *ix = nullptr;
+  fa::ServerArgs args{};
+  int32_t dtype = 0, delay = 1, wpb = 4, k_max = 100, L_max = 256;
+  int32_t qbytes = 0, nav_stride = 0;
+  int64_t queue_cap = 0, resident = 0;
+  // device
+  uint8_t *d_ring = nullptr;
+  uint32_t *d_ctl = nullptr;  // [0] next, [16] published, [32] stop (separate lines)
+  // host (pinned, mapped)
+  uint8_t *h_stage = nullptr;
+  int32_t *h_ids = nullptr;
+  uint32_t *h_dists = nullptr, *h_steps = nullptr, *h_done = nullptr;
+  hipStream_t st_kernel = nullptr, st_copy = nullptr;
+  hipEvent_t ev_kernel = nullptr;
+  bool kernel_live = false;
+  // host state
+  std::mutex mu;
+  std::condition_variable cv_admit, cv_done;
+  std::deque<Pending> arrivals;
+  std::vector<uint32_t> free_slots;
+  std::vector<Inflight> inflight;
+  std::deque<Done> done_q;
+  std::vector<Done> last_poll;
+  uint64_t published = 0;
+  std::atomic<bool> quit{false};
+  std::thread admit_thr, reap_thr;
+  // stats
+  std::atomic<uint64_t> submitted{0}, admitted{0}, completed{0}, relaunches{0};
+  std::atomic<int64_t> max_inflight{0};
+  int64_t n_inflight = 0;
+  std::atomic<int> error{0};
+  std::string error_msg;
+
+  int launch_kernel() {
+    hipError_t e = fa::launch_server(args, dtype, delay, wpb, nullptr, st_kernel);
+    if (e == hipSuccess) e = hipEventRecord(ev_kernel, st_kernel);
+    if (e != hipSuccess) {
+      error_msg = std::string("server kernel launch: ") + hipGetErrorString(e);
+      error.store(ANN_EIO);
+      return ANN_EIO;
+    }
+    kernel_live = true;
+    return ANN_OK;
+  }
+
+  // Admission: arrival order, while a slot (HBM budget) is free.
+  void admit_loop() {
+    const int64_t eb = args.entry_bytes;
+    const int64_t cap = args.ring_cap;
+    std::vector<std::pair<uint32_t, Pending>> batch;
+    while (!quit.load()) {
+      batch.clear();
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv_admit.wait_for(lk, std::chrono::microseconds(200), [&] {
+          return quit.load() || (!arrivals.empty() && !free_slots.empty());
+        });
+        while (!arrivals.empty() && !free_slots.empty() && batch.size() < 4096) {
+          const uint32_t slot = free_slots.back();
+          free_slots.pop_back();
+          batch.emplace_back(slot, std::move(arrivals.front()));
+          arrivals.pop_front();
+        }
+        for (size_t i = 0; i < batch.size(); i++) {
+          Inflight &f = inflight[batch[i].first];
+          f.seq = published + i;
+          f.tag = batch[i].second.tag;
+          f.k = batch[i].second.k;
+          f.submit_us = batch[i].second.submit_us;
+          f.used = true;
+        }
+        n_inflight += (int64_t)batch.size();
+        if (n_inflight > max_inflight.load()) max_inflight.store(n_inflight);
+      }
+      if (!batch.empty()) {
+        // stage the entries, copy the (at most two) contiguous ring ranges,
+        // then publish the count on the same stream
+        for (size_t i = 0; i < batch.size(); i++) {
+          const uint64_t seq = published + i;
+          uint8_t *ent = h_stage + (int64_t)(seq % cap) * eb;
+          const uint32_t ctrl[4] = {(uint32_t)(seq + 1), batch[i].first,
+                                    (uint32_t)batch[i].second.k | ((uint32_t)batch[i].second.L << 16),
+                                    0u};
+          std::memcpy(ent, ctrl, 16);
+          std::memset(ent + 16, 0, (size_t)(eb - 16));
+          std::memcpy(ent + 16, batch[i].second.q.data(), (size_t)qbytes);
+        }
+        const uint64_t first = published, last = published + batch.size();
+        hipError_t e = hipSuccess;
+        uint64_t s = first;
+        while (s < last && e == hipSuccess) {
+          const uint64_t r0 = s % cap;
+          const uint64_t run = std::min<uint64_t>(last - s, cap - r0);
+          e = hipMemcpyAsync(d_ring + r0 * eb, h_stage + r0 * eb, run * eb, hipMemcpyHostToDevice,
+                             st_copy);
+          s += run;
+        }
+        if (e == hipSuccess) e = hipStreamWriteValue32(st_copy, d_ctl + 16, (uint32_t)last, 0);
+        if (e == hipSuccess) e = hipStreamSynchronize(st_copy);
+        if (e != hipSuccess) {
+          error_msg = std::string("admission copy: ") + hipGetErrorString(e);
+          error.store(ANN_EIO);
+          return;
+        }
+        published = last;
+        admitted.fetch_add(batch.size());
+      }
+      // the kernel leaves after a long idle spell; start it again when work waits
+      if (published > completed.load() + 0 && (!kernel_live || hipEventQuery(ev_kernel) == hipSuccess)) {
+        if (kernel_live) relaunches.fetch_add(1);
+        if (launch_kernel() != ANN_OK) return;
+      }
+    }
+  }
+
+  // Reaper: done words -> completed results; frees slots.
+  void reap_loop() {
+    std::vector<std::pair<uint32_t, Inflight>> scan;
+    std::vector<Done> fresh;
+    std::vector<uint32_t> freed;
+    while (!quit.load()) {
+      scan.clear();
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        for (uint32_t s = 0; s < (uint32_t)inflight.size(); s++)
+          if (inflight[s].used) scan.emplace_back(s, inflight[s]);
+      }
+      fresh.clear();
+      freed.clear();
+      for (const auto &sf : scan) {
+        const uint32_t s = sf.first;
+        const Inflight &f = sf.second;
+        const uint32_t w = __atomic_load_n(&h_done[16 * (int64_t)s], __ATOMIC_ACQUIRE);
+        if (w != (uint32_t)(f.seq + 1)) continue;
+        Done d;
+        d.tag = f.tag;
+        d.k = f.k;
+        d.submit_us = f.submit_us;
+        d.done_us = now_us();
+        d.steps = h_steps[s];
+        d.ids.assign(h_ids + (int64_t)s * k_max, h_ids + (int64_t)s * k_max + f.k);
+        d.dists.assign(h_dists + (int64_t)s * k_max, h_dists + (int64_t)s * k_max + f.k);
+        fresh.push_back(std::move(d));
+        freed.push_back(s);
+      }
+      if (!fresh.empty()) {
+        {
+          std::lock_guard<std::mutex> lk(mu);
+          for (uint32_t s : freed) {
+            inflight[s].used = false;
+            free_slots.push_back(s);
+          }
+          n_inflight -= (int64_t)freed.size();
+          for (auto &d : fresh) done_q.push_back(std::move(d));
+        }
+        completed.fetch_add(freed.size());
+        cv_admit.notify_one();
+        cv_done.notify_all();
+      } else {
+        std::this_thread::sleep_for(std::chrono::microseconds(5));
+      }
+      if (error.load()) return;
+    }
+  }
+
+  int64_t n_inflight_snapshot() {
+    std::lock_guard<std::mutex> lk(mu);
+    return n_inflight;
+  }
+};
+
+namespace {
+
+void server_free(ann_server *s) {
+  if (!s) return;
+  if (s->ev_kernel) (void)hipEventDestroy(s->ev_kernel);
+  if (s->st_kernel) (void)hipStreamDestroy(s->st_kernel);
+  if (s->st_copy) (void)hipStreamDestroy(s->st_copy);
+  if (s->d_ring) (void)hipFree(s->d_ring);
+  if (s->d_ctl) (void)hipFree(s->d_ctl);
+  if (s->h_stage) (void)hipHostFree(s->h_stage);
+  if (s->h_ids) (void)hipHostFree(s->h_ids);
+  if (s->h_dists) (void)hipHostFree(s->h_dists);
+  if (s->h_steps) (void)hipHostFree(s->h_steps);
+  if (s->h_done) (void)hipHostFree(s->h_done);
+  delete s;
+}
+
+template <typename T>
+T *mapped(T *p) {
+  void *d = nullptr;
+  return hipHostGetDevicePointer(&d, p, 0) == hipSuccess ? (T *)d : nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+double ann_clock_us(void) { return now_us(); }
+
+int ann_server_open(ann_index *ix, size_t hbm_budget_bytes, const ann_server_opts *opts,
+                    ann_server **out) {
+  if (!out) return ann_internal_fail(ANN_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!ix) return ann_internal_fail(ANN_EINVAL, "index is NULL");
+  ann_server_opts o{};
+  o.k_max = 100;
+  o.L_max = 256;
+  o.delay = 1;
+  if (opts) o = *opts;
+  if (o.k_max == 0) o.k_max = 100;
+  if (o.L_max == 0) o.L_max = 256;
+  if (o.waves_per_block == 0) o.waves_per_block = 4;
+  if (o.hash_bits == 0) o.hash_bits = 10;
+  if (o.queue_cap == 0) o.queue_cap = 1 << 20;
+  if (o.idle_polls == 0) o.idle_polls = 50000;
+  if (o.k_max < 1 || o.k_max > 0xFFFF || o.L_max < o.k_max || o.L_max > 1024 ||
+      o.delay < 0 || o.delay > 1 || o.waves_per_block < 1 || o.waves_per_block > 4 ||
+      o.queue_cap < 1)
+    return ann_internal_fail(ANN_EINVAL, "bad server options");
+  ann_server *s = new (std::nothrow) ann_server();
+  if (!s) return ann_internal_fail(ANN_ENOMEM, "server handle");
+  s->ix = ix;
+  s->k_max = o.k_max;
+  s->L_max = o.L_max;
+  s->delay = o.delay;
+  s->wpb = o.waves_per_block;
+  s->queue_cap = o.queue_cap;
+  int rc = ann_internal_server_args(ix, o.k_max, o.L_max, o.hash_bits, &s->args.base, &s->dtype);
+  if (rc) {
+    server_free(s);
+    return rc;
+  }
+  s->nav_stride = s->args.base.nav_stride;
+  s->qbytes = s->args.base.qbytes;
+  // Per admitted query the device holds one ring entry (control + query);
+  // the budget fixes how many queries may be admitted at once.  The ring
+  // has room for every admitted query plus one claim per resident wave.
+  const int64_t eb = 16 + s->nav_stride;
+  int64_t resident = 0;
+  hipError_t e = fa::launch_server(s->args, s->dtype, s->delay, s->wpb, &resident, nullptr);
+  if (e != hipSuccess) {
+    server_free(s);
+    return ann_internal_fail(ANN_EIO, "server occupancy query failed");
+  }
+  s->resident = resident;
+  const int64_t nslots = (int64_t)(hbm_budget_bytes / (size_t)eb) - resident;
+  if (nslots < 1) {
+    server_free(s);
+    return ann_internal_fail(ANN_ENOMEM, "HBM budget below one query plus one entry per resident wave");
+  }
+  const int64_t slots = std::min<int64_t>(nslots, 1 << 20);
+  const int64_t ring_cap = slots + resident;
+  s->args.entry_bytes = eb;
+  s->args.ring_cap = (uint32_t)ring_cap;
+  s->args.nslots = (uint32_t)slots;
+  s->args.idle_limit = (uint32_t)o.idle_polls;
+  const unsigned fl = hipHostMallocCoherent | hipHostMallocMapped;
+  if ((e = hipMalloc(&s->d_ring, ring_cap * eb)) != hipSuccess ||
+      (e = hipMalloc(&s->d_ctl, 64 * sizeof(uint32_t))) != hipSuccess ||
+      (e = hipHostMalloc((void **)&s->h_stage, ring_cap * eb, hipHostMallocDefault)) != hipSuccess ||
+      (e = hipHostMalloc((void **)&s->h_ids, slots * o.k_max * 4, fl)) != hipSuccess ||
+      (e = hipHostMalloc((void **)&s->h_dists, slots * o.k_max * 4, fl)) != hipSuccess ||
+      (e = hipHostMalloc((void **)&s->h_steps, slots * 4, fl)) != hipSuccess ||
+      (e = hipHostMalloc((void **)&s->h_done, slots * 64, fl)) != hipSuccess ||
+      (e = hipMemset(s->d_ctl, 0, 64 * sizeof(uint32_t))) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&s->st_kernel, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&s->st_copy, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&s->ev_kernel, hipEventDisableTiming)) != hipSuccess) {
+    server_free(s);
+    return ann_internal_fail(e == hipErrorOutOfMemory ? ANN_ENOMEM : ANN_EIO,
+                             "server buffers / streams");
+  }
+  std::memset(s->h_done, 0, (size_t)slots * 64);
+  s->args.ring = s->d_ring;
+  s->args.next = s->d_ctl;
+  s->args.published = s->d_ctl + 16;
+  s->args.stop = s->d_ctl + 32;
+  s->args.res_ids = mapped(s->h_ids);
+  s->args.res_dists = mapped(s->h_dists);
+  s->args.res_steps = mapped(s->h_steps);
+  s->args.done = mapped(s->h_done);
+  if (!s->args.res_ids || !s->args.res_dists || !s->args.res_steps || !s->args.done) {
+    server_free(s);
+    return ann_internal_fail(ANN_EIO, "result rows not mapped");
+  }
+  s->inflight.assign((size_t)slots, Inflight{});
+  s->free_slots.reserve((size_t)slots);
+  for (int64_t i = slots - 1; i >= 0; i--) s->free_slots.push_back((uint32_t)i);
+  if (s->launch_kernel() != ANN_OK) {
+    const std::string m = s->error_msg;
+    server_free(s);
+    return ann_internal_fail(ANN_EIO, m.c_str());
+  }
+  s->admit_thr = std::thread([s] { s->admit_loop(); });
+  s->reap_thr = std::thread([s] { s->reap_loop(); });
+  *out = s;
+  return ANN_OK;
+}
+
+int ann_server_submit(ann_server *s, const void *host_query, int32_t k, int32_t L, uint64_t tag) {
+  if (!s || !host_query) return ann_internal_fail(ANN_EINVAL, "NULL argument");
+  if (k < 1 || k > s->k_max || L < k || L > s->L_max)
+    return ann_internal_fail(ANN_EINVAL, "need 1 <= k <= k_max and k <= L <= L_max");
+  if (s->error.load()) return ann_internal_fail(s->error.load(), s->error_msg.c_str());
+  Pending p;
+  p.q.assign((const uint8_t *)host_query, (const uint8_t *)host_query + s->qbytes);
+  p.k = k;
+  p.L = L;
+  p.tag = tag;
+  p.submit_us = now_us();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if ((int64_t)s->arrivals.size() >= s->queue_cap)
+      return ann_internal_fail(ANN_EBUSY, "arrival queue full");
+    s->arrivals.push_back(std::move(p));
+  }
+  s->submitted.fetch_add(1);
+  s->cv_admit.notify_one();
+  return ANN_OK;
+}
+
+int ann_server_poll(ann_server *s, ann_result *out, int32_t max, int32_t *n_out,
+                    int32_t timeout_us) {
+  if (!s || !n_out || (max > 0 && !out)) return ann_internal_fail(ANN_EINVAL, "NULL argument");
+  *n_out = 0;
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (s->done_q.empty() && timeout_us > 0)
+    s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us),
+                        [&] { return !s->done_q.empty() || s->error.load() != 0; });
+  s->last_poll.clear();
+  while (!s->done_q.empty() && (int32_t)s->last_poll.size() < max) {
+    s->last_poll.push_back(std::move(s->done_q.front()));
+    s->done_q.pop_front();
+  }
+  for (size_t i = 0; i < s->last_poll.size(); i++) {
+    const Done &d = s->last_poll[i];
+    out[i].tag = d.tag;
+    out[i].status = ANN_OK;
+    out[i].k = d.k;
+    out[i].steps = d.steps;
+    out[i].ids = d.ids.data();
+    out[i].dists = d.dists.data();
+    out[i].submit_us = d.submit_us;
+    out[i].done_us = d.done_us;
+  }
+  *n_out = (int32_t)s->last_poll.size();
+  if (*n_out == 0 && s->error.load()) return ann_internal_fail(s->error.load(), s->error_msg.c_str());
+  return ANN_OK;
+}
+
+int ann_server_stats_get(ann_server *s, ann_server_stats *out) {
+  if (!s || !out) return ann_internal_fail(ANN_EINVAL, "NULL argument");
+  out->submitted = s->submitted.load();
+  out->admitted = s->admitted.load();
+  out->completed = s->completed.load();
+  out->relaunches = s->relaunches.load();
+  out->max_inflight = s->max_inflight.load();
+  out->slots = s->args.nslots;
+  out->resident_waves = s->resident;
+  return ANN_OK;
+}
+
+int ann_server_close(ann_server *s) {
+  if (!s) return ANN_OK;
+  // let admitted work finish (at most a minute), then stop the kernel
+  const double give_up = now_us() + 60e6;
+  while (now_us() < give_up) {
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      if (s->arrivals.empty() && s->n_inflight == 0) break;
+    }
+    if (s->error.load()) break;
+    std::this_thread::sleep_for(std::chrono::microseconds(100));
+  }
+  s->quit.store(true);
+  s->cv_admit.notify_all();
+  if (s->admit_thr.joinable()) s->admit_thr.join();
+  if (s->reap_thr.joinable()) s->reap_thr.join();
+  int rc = ANN_OK;
+  hipError_t e = hipStreamWriteValue32(s->st_copy, s->d_ctl + 32, 1u, 0);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st_copy);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st_kernel);
+  if (e != hipSuccess) rc = ann_internal_fail(ANN_EIO, hipGetErrorString(e));
+  server_free(s);
+  return rc;
+}
+
+}  // extern "C"

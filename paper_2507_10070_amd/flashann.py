@@ -23,7 +23,8 @@ TRANSPORT_AUTO, TRANSPORT_DIRECT, TRANSPORT_AGENT = 0, 1, 2
 EXPORTED = ["ann_index_create", "ann_index_info_get", "ann_search", "ann_index_free",
             "ann_last_error", "ann_device_clock_khz", "ann_save_index", "ann_build_index",
             "ann_load_records", "ann_agent_configure", "ann_agent_stats", "ann_search_graph",
-            "ann_graph_launch", "ann_graph_free"]
+            "ann_graph_launch", "ann_graph_free", "ann_server_open", "ann_server_submit",
+            "ann_server_poll", "ann_server_stats_get", "ann_server_close", "ann_clock_us"]
 
 
 class AnnError(RuntimeError):
@@ -49,6 +50,25 @@ class IndexInfo(ctypes.Structure):
                 ("tier", ctypes.c_int32), ("nav_stride", ctypes.c_int32),
                 ("rec_bytes", ctypes.c_int32), ("hbm_bytes", ctypes.c_int64),
                 ("direct_io", ctypes.c_int32)]
+
+
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("k_max", ctypes.c_int32), ("L_max", ctypes.c_int32), ("delay", ctypes.c_int32),
+                ("waves_per_block", ctypes.c_int32), ("hash_bits", ctypes.c_int32),
+                ("queue_cap", ctypes.c_int32), ("idle_polls", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("ids", ctypes.c_void_p), ("dists", ctypes.c_void_p), ("steps", ctypes.c_uint32),
+                ("submit_us", ctypes.c_double), ("done_us", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64),
+                ("completed", ctypes.c_uint64), ("relaunches", ctypes.c_uint64),
+                ("max_inflight", ctypes.c_int64), ("slots", ctypes.c_int64),
+                ("resident_waves", ctypes.c_int64)]
 
 
 _lib = None
@@ -91,6 +111,19 @@ def load_library(path: str = LIB_PATH):
     lib.ann_graph_launch.restype = ctypes.c_int
     lib.ann_graph_free.argtypes = [vp]
     lib.ann_graph_free.restype = ctypes.c_int
+    lib.ann_server_open.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(ServerOptions),
+                                    ctypes.POINTER(vp)]
+    lib.ann_server_open.restype = ctypes.c_int
+    lib.ann_server_submit.argtypes = [vp, vp, i32, i32, ctypes.c_uint64]
+    lib.ann_server_submit.restype = ctypes.c_int
+    lib.ann_server_poll.argtypes = [vp, ctypes.POINTER(Result), i32, ctypes.POINTER(i32), i32]
+    lib.ann_server_poll.restype = ctypes.c_int
+    lib.ann_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    lib.ann_server_stats_get.restype = ctypes.c_int
+    lib.ann_server_close.argtypes = [vp]
+    lib.ann_server_close.restype = ctypes.c_int
+    lib.ann_clock_us.argtypes = []
+    lib.ann_clock_us.restype = ctypes.c_double
     lib.ann_device_clock_khz.argtypes = [ctypes.POINTER(ctypes.c_int32)]
     lib.ann_device_clock_khz.restype = ctypes.c_int
     lib.ann_last_error.argtypes = []
@@ -307,3 +340,66 @@ class SearchGraph:
             self._g = None
 
     __del__ = close
+
+
+def clock_us() -> float:
+    """The host clock (microseconds) of the server's result stamps."""
+    return load_library().ann_clock_us()
+
+
+class Server:
+    """ann_server_*: continuous-batching search service over an index."""
+
+    def __init__(self, index: Index, hbm_budget_bytes: int, k_max: int = 100, L_max: int = 256,
+                 delay: int = 1, waves_per_block: int = 0, hash_bits: int = 0,
+                 queue_cap: int = 0, idle_polls: int = 0):
+        self.index = index
+        self.dtype = index.dtype
+        self.d = index.d
+        self.k_max = k_max
+        opts = ServerOptions(k_max, L_max, delay, waves_per_block, hash_bits, queue_cap,
+                             idle_polls)
+        h = ctypes.c_void_p()
+        _check(load_library().ann_server_open(index.handle, int(hbm_budget_bytes),
+                                              ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+        self._buf = (Result * 4096)()
+
+    def submit(self, query: np.ndarray, k: int, L: int, tag: int) -> None:
+        q = np.ascontiguousarray(query, dtype=self.dtype).reshape(-1)
+        if q.shape[0] != self.d:
+            raise ValueError("query must have %d elements" % self.d)
+        _check(load_library().ann_server_submit(self._h, q.ctypes.data, int(k), int(L), int(tag)))
+
+    def poll(self, max_results: int = 4096, timeout_us: int = 0):
+        """Completed results: list of dicts (ids, dists copied to numpy)."""
+        n = ctypes.c_int32()
+        m = min(max_results, len(self._buf))
+        _check(load_library().ann_server_poll(self._h, self._buf, m, ctypes.byref(n), timeout_us))
+        dt = np.float32 if self.dtype == np.float32 else np.uint32
+        out = []
+        for i in range(n.value):
+            r = self._buf[i]
+            ids = np.ctypeslib.as_array(ctypes.cast(r.ids, ctypes.POINTER(ctypes.c_int32)),
+                                        shape=(r.k,)).copy()
+            raw = np.ctypeslib.as_array(ctypes.cast(r.dists, ctypes.POINTER(ctypes.c_uint32)),
+                                        shape=(r.k,)).copy()
+            out.append({"tag": r.tag, "status": r.status, "ids": ids, "dists": raw.view(dt),
+                        "steps": r.steps, "submit_us": r.submit_us, "done_us": r.done_us})
+        return out
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load_library().ann_server_stats_get(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            h, self._h = self._h, None
+            _check(load_library().ann_server_close(h))
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

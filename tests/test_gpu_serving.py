@@ -1,0 +1,116 @@
+"""Continuous-batching service: results are the same for a query served
+alone and inside a concurrent stream of arrivals with differing k and L
+(bit-exact for u8), equal the oracle, stay within the HBM budget, and the
+kernel is started again after it leaves when idle."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+fa = pytest.importorskip("paper_2507_10070_amd")
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    cfg = synth.CONFIGS[1]
+    base, q = synth.make_dataset(cfg)
+    adj, entry = synth.build_graph(base, cfg.R, 3001, threads=8)
+    return base, q, adj, entry
+
+
+def plan(nq, seed):
+    rng = np.random.default_rng(seed)
+    ks = rng.choice([10, 100], nq)
+    Ls = np.array([rng.choice([L for L in (32, 64, 128, 256) if L >= k]) for k in ks])
+    return ks, Ls
+
+
+def collect(srv, n, timeout_s=60):
+    got = {}
+    t_end = time.time() + timeout_s
+    while len(got) < n and time.time() < t_end:
+        for r in srv.poll(timeout_us=2000):
+            got[r["tag"]] = r
+    assert len(got) == n, "only %d of %d results" % (len(got), n)
+    return got
+
+
+def test_alone_vs_mix(cfg1):
+    base, q, adj, entry = cfg1
+    ks, Ls = plan(len(q), 1)
+    with fa.Index(base, adj, entry, 256, fa.TIER_HOST) as ix:
+        with fa.Server(ix, hbm_budget_bytes=64 << 20) as srv:
+            alone = {}
+            for i in range(len(q)):          # one at a time
+                srv.submit(q[i], int(ks[i]), int(Ls[i]), i)
+                alone.update(collect(srv, 1))
+            rng = np.random.default_rng(2)
+            for i in rng.permutation(len(q)):  # a stream with Poisson gaps
+                srv.submit(q[i], int(ks[i]), int(Ls[i]), 1000 + i)
+                time.sleep(rng.exponential(20e-6))
+            mix = {t - 1000: r for t, r in collect(srv, len(q)).items()}
+            st = srv.stats()
+    assert st["completed"] == 2 * len(q)
+    for i in range(len(q)):
+        a, m = alone[i], mix[i]
+        np.testing.assert_array_equal(a["ids"], m["ids"])
+        np.testing.assert_array_equal(a["dists"], m["dists"])
+        assert a["steps"] == m["steps"]
+        ref = oracle.search(base, adj, entry, q[i:i + 1], int(ks[i]), int(Ls[i]), delay=1)
+        np.testing.assert_array_equal(m["ids"], ref["ids"][0])
+        np.testing.assert_array_equal(m["dists"].astype(np.float64), ref["dists"][0])
+        assert m["steps"] == ref["steps"][0]
+
+
+def test_budget_bounds_admission(cfg1):
+    base, q, adj, entry = cfg1
+    with fa.Index(base, adj, entry, 256, fa.TIER_HBM) as ix:
+        probe = fa.Server(ix, hbm_budget_bytes=64 << 20)
+        resident = probe.stats()["resident_waves"]
+        probe.close()
+        entry_bytes = 16 + 128
+        with fa.Server(ix, hbm_budget_bytes=(resident + 3) * entry_bytes) as srv:
+            assert srv.stats()["slots"] == 3
+            for i in range(len(q)):
+                srv.submit(q[i], 10, 64, i)
+            got = collect(srv, len(q))
+            st = srv.stats()
+    assert st["max_inflight"] <= 3
+    ref = oracle.search(base, adj, entry, q, 10, 64, delay=1)
+    for i in range(len(q)):
+        np.testing.assert_array_equal(got[i]["ids"], ref["ids"][i])
+
+
+def test_idle_exit_and_relaunch(cfg1):
+    base, q, adj, entry = cfg1
+    with fa.Index(base, adj, entry, 256, fa.TIER_HBM) as ix:
+        with fa.Server(ix, hbm_budget_bytes=64 << 20, idle_polls=300) as srv:
+            srv.submit(q[0], 10, 64, 0)
+            r0 = collect(srv, 1)[0]
+            time.sleep(0.5)                   # the kernel leaves while idle
+            srv.submit(q[1], 10, 64, 1)
+            r1 = collect(srv, 1)[1]
+            st = srv.stats()
+    assert st["relaunches"] >= 1
+    ref = oracle.search(base, adj, entry, q[:2], 10, 64, delay=1)
+    np.testing.assert_array_equal(r0["ids"], ref["ids"][0])
+    np.testing.assert_array_equal(r1["ids"], ref["ids"][1])
+
+
+def test_server_rejects_bad_requests(cfg1):
+    base, q, adj, entry = cfg1
+    with fa.Index(base, adj, entry, 256, fa.TIER_HBM) as ix:
+        with fa.Server(ix, hbm_budget_bytes=64 << 20, k_max=20, L_max=64) as srv:
+            for k, L in ((0, 10), (21, 64), (10, 65), (30, 20)):
+                with pytest.raises(fa.AnnError) as e:
+                    srv.submit(q[0], k, L, 0)
+                assert e.value.code == -22
+        with pytest.raises(fa.AnnError) as e:
+            fa.Server(ix, hbm_budget_bytes=1000)
+        assert e.value.code == -12
