@@ -80,6 +80,64 @@ def stored_traffic(workload):
     return t.get("traffic_bytes_per_launch")
 
 
+def serving_leg(fa, ix, queries, kth, budget):
+    """Saturation throughput of the server on the serving mix, then Poisson
+    arrivals at fractions of it; latency from intended arrival to result."""
+    import numpy as np
+
+    rng = np.random.default_rng(5)
+    nq = queries.shape[0]
+
+    def mix(m):
+        ks = rng.choice(np.array([10, 100], np.int32), m)
+        Ls = np.array([rng.choice([L for L in (32, 64, 128, 256) if L >= k]) for k in ks],
+                      np.int32)
+        return ks, Ls
+
+    def recall(res):
+        qi = (res["tags"] % nq).astype(np.int64)
+        d10 = res["dists"][:, :10].astype(np.float64)
+        hit = np.minimum((d10 <= kth[qi][:, None]).sum(1), 10) / 10.0
+        return float(hit.mean())
+
+    out = {"workload": "1M u8/128 index, pinned host DRAM records, mix k {10,100}, "
+                       "L {32,64,128,256} >= k", "budget_bytes": budget}
+    with fa.Server(ix, hbm_budget_bytes=budget) as srv:
+        st = srv.stats()
+        out["slots"], out["resident_waves"] = st["slots"], st["resident_waves"]
+        m0 = 40000
+        ks, Ls = mix(m0)
+        idx = np.arange(m0) % nq
+        t0 = fa.clock_us()
+        srv.submit_batch(queries[idx], ks, Ls, np.arange(m0, dtype=np.uint64))
+        res = srv.drain(m0)
+        qmax = m0 / ((res["done_us"].max() - t0) / 1e6)
+        out["saturation_qps"] = round(qmax, 1)
+        out["saturation_recall@10"] = round(recall(res), 4)
+        rates = []
+        for frac in (0.25, 0.5, 0.75, 0.9):
+            lam = frac * qmax
+            m = int(min(max(3000, lam * 0.5), 150000))
+            ks, Ls = mix(m)
+            idx = rng.integers(0, nq, m)
+            start = fa.clock_us() + 20000.0
+            arr = start + np.cumsum(rng.exponential(1e6 / lam, m))
+            srv.submit_batch(queries[idx], ks, Ls, idx.astype(np.uint64), arr)
+            res = srv.drain(m)
+            lat = (res["done_us"] - res["submit_us"]) / 1e3
+            rates.append({"offered_qps": round(lam, 1), "queries": int(len(lat)),
+                          "achieved_qps": round(len(lat) / ((res["done_us"].max() - start) / 1e6), 1),
+                          "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
+                          "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
+                          "recall@10": round(recall(res), 4)})
+            log("serving at %.0f QPS offered: %s" % (lam, rates[-1]))
+        out["rates"] = rates
+        st = srv.stats()
+        out["relaunches"] = st["relaunches"]
+        out["max_inflight"] = st["max_inflight"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +152,10 @@ def main():
                     help="queries per oracle pass in the CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="repeat oracle passes until this much CPU time has elapsed")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the continuous-batching serving measurement")
+    ap.add_argument("--serving-budget-mb", type=int, default=256,
+                    help="HBM budget of the serving admission")
     ap.add_argument("--no-transports", action="store_true",
                     help="skip the agent-transport and file-tier measurements")
     ap.add_argument("--file-queries", type=int, default=1000,
@@ -283,6 +345,13 @@ def main():
 
             shutil.rmtree(tmpd, ignore_errors=True)
 
+    # ---- serving: continuous batching under open-loop Poisson arrivals with
+    # the serving mix (k in {10, 100}, L in {32, 64, 128, 256} with L >= k)
+    serving = None
+    if not args.no_serving and tier == fa.TIER_HOST:
+        serving = serving_leg(fa, ix, queries, kth, args.serving_budget_mb << 20)
+        log("serving: %s" % json.dumps(serving))
+
     # ---- CPU baseline: the oracle on this host's cores, bounded sample
     cpu = None
     if not args.no_cpu_baseline:
@@ -330,6 +399,7 @@ def main():
         "sweep": {"strict": sweep[0], "relaxed": sweep[1]},
         "roofline": roofline,
         "transports": transports,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -267,9 +267,21 @@ int ann_server_open(ann_index *ix, size_t hbm_budget_bytes, const ann_server_opt
 /* Queue one query (host, d elements of the index dtype; copied).  1 <= k <= k_max,
  * k <= L <= L_max.  ANN_EBUSY when the arrival queue is full. */
 int ann_server_submit(ann_server *s, const void *host_query, int32_t k, int32_t L, uint64_t tag);
+/* Queue n queries (host, n x d) with their k, L and tags.  With `arrival_us`
+ * (non-decreasing ann_clock_us() times, optional) each query is admitted no
+ * earlier than its arrival time and its submit_us is that time, so an
+ * open-loop load measures latency from the intended arrival. */
+int ann_server_submit_batch(ann_server *s, const void *host_queries, int64_t n, const int32_t *ks,
+                            const int32_t *Ls, const uint64_t *tags, const double *arrival_us);
 /* Take up to `max` completed results, waiting up to timeout_us for the first. */
 int ann_server_poll(ann_server *s, ann_result *out, int32_t max, int32_t *n_out,
                     int32_t timeout_us);
+/* Bulk form of ann_server_poll into caller-owned host arrays of `max` rows:
+ * tags, ks, ids (max x k_max, padded with -1), dists (max x k_max, padded
+ * with 0xFFFFFFFF bits), and optional steps, submit_us, done_us. */
+int ann_server_poll_into(ann_server *s, int32_t max, uint64_t *tags, int32_t *ks, int32_t *ids,
+                         void *dists, uint32_t *steps, double *submit_us, double *done_us,
+                         int32_t *n_out, int32_t timeout_us);
 int ann_server_stats_get(ann_server *s, ann_server_stats *out);
 /* Finish every admitted and waiting query, stop the kernel, release all. */
 int ann_server_close(ann_server *s);

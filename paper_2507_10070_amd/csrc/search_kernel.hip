@@ -215,7 +215,8 @@ __host__ __device__ inline LdsLayout lds_layout(int Lcap, int nav_stride, int ha
 // Where one query's vector comes from and where its results go.
 struct QueryIO {
   const uint8_t *q;   // nav_stride readable bytes when `coherent`
-  bool coherent;      // read q with system-scope loads (memory rewritten by copies)
+  bool coherent;      // q is rewritten by host copies and the result rows are
+                      // read by the host: system-scope loads and stores
   int32_t *ids;       // row of `width` result ids
   uint32_t *dists;    // row of `width` distances
   uint32_t *steps;    // optional
@@ -399,7 +400,7 @@ struct Searcher {
       const uint32_t *w = A.cpl + 16 * qi + (s & 1);
       uint32_t spins = 0, nap = 1;
       for (;;) {
-        c = __hip_atomic_load(w, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+        c = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         if ((c & ~kCplErr) == s) break;
         if (++spins > A.spin_limit) {
           c = kTimedOut;
@@ -412,14 +413,23 @@ struct Searcher {
       }
     }
     c = (uint32_t)__builtin_amdgcn_readfirstlane((int)c);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
     if (c == kTimedOut || (c & kCplErr)) {
       failed = true;
       if (lane == 0) A.status[qi] = c == kTimedOut ? -110 : -5;
       return make_uint4(0, 0, 0, 0);
     }
+    // The staged bytes are read with system-scope loads, issued after the
+    // completion word was seen; they bypass the GPU caches, so no acquire
+    // fence (which would invalidate the whole L2 on every record) is needed.
     const int ch = lane < A.rec_chunks ? lane : A.rec_chunks - 1;
-    return *(const uint4 *)(A.stage + (qi * 2 + (s & 1)) * A.stage_stride + 16 * ch);
+    const uint32_t *src =
+        (const uint32_t *)(A.stage + (qi * 2 + (s & 1)) * A.stage_stride + 16 * ch);
+    uint4 r;
+    r.x = __hip_atomic_load(src + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    r.y = __hip_atomic_load(src + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    r.z = __hip_atomic_load(src + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    r.w = __hip_atomic_load(src + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    return r;
   }
 
   // Part 1 of processing node u: stage its record (false if it failed).
@@ -591,11 +601,24 @@ struct Searcher {
         id = (int32_t)((uint32_t)e & ~kFlag);
         dist = (uint32_t)(e >> 32);
       }
-      io.ids[j] = id;
-      io.dists[j] = dist;
+      if (io.coherent) {
+        // host rows read by the host once a done word follows: write-through
+        // system-scope stores, so that waiting for them to complete orders
+        // them before that word
+        __hip_atomic_store(io.ids + j, id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(io.dists + j, dist, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      } else {
+        io.ids[j] = id;
+        io.dists[j] = dist;
+      }
     }
     if (lane == 0) {
-      if (io.steps) *io.steps = steps;
+      if (io.steps) {
+        if (io.coherent)
+          __hip_atomic_store(io.steps, steps, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        else
+          *io.steps = steps;
+      }
       if (A.stats) {
         atomicAdd(&A.stats[0], (unsigned long long)steps);
         atomicAdd(&A.stats[1], (unsigned long long)rows);
@@ -705,7 +728,7 @@ __global__ void reset_work(uint32_t *work) { *work = 0u; }
 // has published it (c < published), so a wave that leaves while idle holds no
 // claim.  The entry is read with system-scope loads because ring memory is
 // rewritten by host copies; results go to host-mapped rows, then the slot's
-// done word (system-scope release) tells the host.
+// done word tells the host.
 template <int DT, int CPL, int DELAY>
 __global__ void __launch_bounds__(256) server_kernel(ServerArgs S) {
   extern __shared__ __align__(16) uint8_t smem[];
@@ -715,16 +738,34 @@ __global__ void __launch_bounds__(256) server_kernel(ServerArgs S) {
   for (;;) {
     uint32_t got = 0xFFFFFFFFu;
     if (lane == 0) {
+      // Tickets come from one fetch-add on `next` (one L2 atomic per claim,
+      // however many waves look for work at once).  A wave whose ticket is
+      // not published yet keeps it while it waits, or hands it back with
+      // CAS(next, t + 1 -> t), which succeeds only for the highest ticket
+      // out, so returns happen in LIFO order and no ticket is ever dropped:
+      // the holders of unpublished tickets always drain back to zero unless
+      // new entries get published, and then they are served instead.
       uint32_t idle = 0, nap = 1;
       for (;;) {
-        const uint32_t pub =
-            __hip_atomic_load(S.published, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+        // relaxed system-scope polls bypass the caches without the L2
+        // invalidation an acquire would cost every idle wave on every poll;
+        // the entry itself is read with system-scope loads below
+        uint32_t pub = __hip_atomic_load(S.published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         const uint32_t c = __hip_atomic_load(S.next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (c < pub) {
-          if (atomicCAS(S.next, c, c + 1u) == c) {
-            got = c;
-            break;
+          const uint32_t t = atomicAdd(S.next, 1u);
+          uint32_t hold_nap = 1;
+          for (;;) {
+            if (t < pub) {
+              got = t;
+              break;
+            }
+            if (atomicCAS(S.next, t + 1u, t) == t + 1u) break;  // handed back
+            for (uint32_t i = 0; i < hold_nap; i++) __builtin_amdgcn_s_sleep(2);
+            hold_nap = hold_nap < 8 ? hold_nap * 2 : 8;
+            pub = __hip_atomic_load(S.published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
           }
+          if (got != 0xFFFFFFFFu) break;
           continue;
         }
         if (__hip_atomic_load(S.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
@@ -755,9 +796,14 @@ __global__ void __launch_bounds__(256) server_kernel(ServerArgs S) {
     io.k = k;
     io.width = k;
     run_query<DT, CPL, DELAY, TR_DIRECT>(S.base, lds, (int64_t)slot, io);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    // The result rows were written with system-scope (write-through) stores:
+    // once they have completed, the done word may follow.  This avoids a
+    // release fence, which would write back the whole L2 for every query.
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_sched_barrier(0);
     if (lane == 0)
-      __hip_atomic_store(S.done + 16 * (int64_t)slot, got + 1u, __ATOMIC_RELEASE,
+      __hip_atomic_store(S.done + 16 * (int64_t)slot, got + 1u, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }

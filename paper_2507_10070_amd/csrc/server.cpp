@@ -43,7 +43,7 @@ struct Pending {
   std::vector<uint8_t> q;
   int32_t k, L;
   uint64_t tag;
-  double submit_us;
+  double submit_us;  // arrival time: admitted no earlier than this
 };
 
 struct Inflight {
@@ -86,7 +86,10 @@ struct ann_server {
   std::condition_variable cv_admit, cv_done;
   std::deque<Pending> arrivals;
   std::vector<uint32_t> free_slots;
-  std::vector<Inflight> inflight;
+  std::vector<Inflight> inflight;   // per slot; only the admission thread fills a
+                                    // free slot, only the reaper frees a used one
+  std::vector<uint32_t> active;     // slots in use, compact (swap removal)
+  std::vector<int64_t> active_pos;  // slot -> index in `active`, or -1
   std::deque<Done> done_q;
   std::vector<Done> last_poll;
   uint64_t published = 0;
@@ -120,22 +123,41 @@ struct ann_server {
       batch.clear();
       {
         std::unique_lock<std::mutex> lk(mu);
-        cv_admit.wait_for(lk, std::chrono::microseconds(200), [&] {
-          return quit.load() || (!arrivals.empty() && !free_slots.empty());
+        // an arrival is due once the clock has reached its arrival time
+        // (timed submissions of an open-loop load); spin briefly for one due
+        // within half a millisecond, otherwise sleep on the condition
+        double wait_us = 200.0;
+        if (!arrivals.empty() && !free_slots.empty()) {
+          const double ahead = arrivals.front().submit_us - now_us();
+          if (ahead > 0 && ahead < 500.0) {
+            lk.unlock();
+            while (now_us() < arrivals_front_time()) std::this_thread::yield();
+            lk.lock();
+          }
+          wait_us = std::max(0.0, std::min(wait_us, arrivals.front().submit_us - now_us()));
+        }
+        cv_admit.wait_for(lk, std::chrono::microseconds((int64_t)wait_us), [&] {
+          return quit.load() ||
+                 (!arrivals.empty() && !free_slots.empty() && arrivals.front().submit_us <= now_us());
         });
-        while (!arrivals.empty() && !free_slots.empty() && batch.size() < 4096) {
+        const double tnow = now_us();
+        while (!arrivals.empty() && !free_slots.empty() && batch.size() < 4096 &&
+               arrivals.front().submit_us <= tnow) {
           const uint32_t slot = free_slots.back();
           free_slots.pop_back();
           batch.emplace_back(slot, std::move(arrivals.front()));
           arrivals.pop_front();
         }
         for (size_t i = 0; i < batch.size(); i++) {
-          Inflight &f = inflight[batch[i].first];
+          const uint32_t slot = batch[i].first;
+          Inflight &f = inflight[slot];
           f.seq = published + i;
           f.tag = batch[i].second.tag;
           f.k = batch[i].second.k;
           f.submit_us = batch[i].second.submit_us;
           f.used = true;
+          active_pos[slot] = (int64_t)active.size();
+          active.push_back(slot);
         }
         n_inflight += (int64_t)batch.size();
         if (n_inflight > max_inflight.load()) max_inflight.store(n_inflight);
@@ -181,23 +203,21 @@ struct ann_server {
     }
   }
 
-  // Reaper: done words -> completed results; frees slots.
+  // Reaper: done words -> completed results; frees slots.  It scans only the
+  // slots in use; their Inflight records are not written while in use.
   void reap_loop() {
-    std::vector<std::pair<uint32_t, Inflight>> scan;
+    std::vector<uint32_t> scan;
     std::vector<Done> fresh;
     std::vector<uint32_t> freed;
     while (!quit.load()) {
-      scan.clear();
       {
         std::lock_guard<std::mutex> lk(mu);
-        for (uint32_t s = 0; s < (uint32_t)inflight.size(); s++)
-          if (inflight[s].used) scan.emplace_back(s, inflight[s]);
+        scan.assign(active.begin(), active.end());
       }
       fresh.clear();
       freed.clear();
-      for (const auto &sf : scan) {
-        const uint32_t s = sf.first;
-        const Inflight &f = sf.second;
+      for (const uint32_t s : scan) {
+        const Inflight &f = inflight[s];
         const uint32_t w = __atomic_load_n(&h_done[16 * (int64_t)s], __ATOMIC_ACQUIRE);
         if (w != (uint32_t)(f.seq + 1)) continue;
         Done d;
@@ -216,6 +236,12 @@ struct ann_server {
           std::lock_guard<std::mutex> lk(mu);
           for (uint32_t s : freed) {
             inflight[s].used = false;
+            const int64_t p = active_pos[s];
+            const uint32_t last = active.back();
+            active[(size_t)p] = last;
+            active_pos[last] = p;
+            active.pop_back();
+            active_pos[s] = -1;
             free_slots.push_back(s);
           }
           n_inflight -= (int64_t)freed.size();
@@ -229,6 +255,11 @@ struct ann_server {
       }
       if (error.load()) return;
     }
+  }
+
+  double arrivals_front_time() {
+    std::lock_guard<std::mutex> lk(mu);
+    return arrivals.empty() ? 0.0 : arrivals.front().submit_us;
   }
 
   int64_t n_inflight_snapshot() {
@@ -353,6 +384,8 @@ int ann_server_open(ann_index *ix, size_t hbm_budget_bytes, const ann_server_opt
     return ann_internal_fail(ANN_EIO, "result rows not mapped");
   }
   s->inflight.assign((size_t)slots, Inflight{});
+  s->active_pos.assign((size_t)slots, -1);
+  s->active.reserve((size_t)std::min<int64_t>(slots, 1 << 16));
   s->free_slots.reserve((size_t)slots);
   for (int64_t i = slots - 1; i >= 0; i--) s->free_slots.push_back((uint32_t)i);
   if (s->launch_kernel() != ANN_OK) {
@@ -388,6 +421,40 @@ int ann_server_submit(ann_server *s, const void *host_query, int32_t k, int32_t 
   return ANN_OK;
 }
 
+int ann_server_submit_batch(ann_server *s, const void *host_queries, int64_t n, const int32_t *ks,
+                            const int32_t *Ls, const uint64_t *tags, const double *arrival_us) {
+  if (!s || (n > 0 && (!host_queries || !ks || !Ls || !tags)) || n < 0)
+    return ann_internal_fail(ANN_EINVAL, "NULL argument");
+  if (s->error.load()) return ann_internal_fail(s->error.load(), s->error_msg.c_str());
+  for (int64_t i = 0; i < n; i++) {
+    if (ks[i] < 1 || ks[i] > s->k_max || Ls[i] < ks[i] || Ls[i] > s->L_max)
+      return ann_internal_fail(ANN_EINVAL, "need 1 <= k <= k_max and k <= L <= L_max");
+    if (arrival_us && i > 0 && arrival_us[i] < arrival_us[i - 1])
+      return ann_internal_fail(ANN_EINVAL, "arrival times must not decrease");
+  }
+  const double t0 = now_us();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if ((int64_t)s->arrivals.size() + n > s->queue_cap)
+      return ann_internal_fail(ANN_EBUSY, "arrival queue full");
+    if (arrival_us && n > 0 && !s->arrivals.empty() && arrival_us[0] < s->arrivals.back().submit_us)
+      return ann_internal_fail(ANN_EINVAL, "arrival times must not go back in time");
+    for (int64_t i = 0; i < n; i++) {
+      Pending p;
+      const uint8_t *q = (const uint8_t *)host_queries + i * (int64_t)s->qbytes;
+      p.q.assign(q, q + s->qbytes);
+      p.k = ks[i];
+      p.L = Ls[i];
+      p.tag = tags[i];
+      p.submit_us = arrival_us ? arrival_us[i] : t0;
+      s->arrivals.push_back(std::move(p));
+    }
+  }
+  s->submitted.fetch_add((uint64_t)n);
+  s->cv_admit.notify_one();
+  return ANN_OK;
+}
+
 int ann_server_poll(ann_server *s, ann_result *out, int32_t max, int32_t *n_out,
                     int32_t timeout_us) {
   if (!s || !n_out || (max > 0 && !out)) return ann_internal_fail(ANN_EINVAL, "NULL argument");
@@ -414,6 +481,38 @@ int ann_server_poll(ann_server *s, ann_result *out, int32_t max, int32_t *n_out,
   }
   *n_out = (int32_t)s->last_poll.size();
   if (*n_out == 0 && s->error.load()) return ann_internal_fail(s->error.load(), s->error_msg.c_str());
+  return ANN_OK;
+}
+
+int ann_server_poll_into(ann_server *s, int32_t max, uint64_t *tags, int32_t *ks, int32_t *ids,
+                         void *dists, uint32_t *steps, double *submit_us, double *done_us,
+                         int32_t *n_out, int32_t timeout_us) {
+  if (!s || !n_out || max < 0 || (max > 0 && (!tags || !ks || !ids || !dists)))
+    return ann_internal_fail(ANN_EINVAL, "NULL argument");
+  *n_out = 0;
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (s->done_q.empty() && timeout_us > 0)
+    s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us),
+                        [&] { return !s->done_q.empty() || s->error.load() != 0; });
+  int32_t n = 0;
+  while (!s->done_q.empty() && n < max) {
+    const Done &d = s->done_q.front();
+    tags[n] = d.tag;
+    ks[n] = d.k;
+    int32_t *row = ids + (int64_t)n * s->k_max;
+    uint32_t *drow = (uint32_t *)dists + (int64_t)n * s->k_max;
+    for (int32_t j = 0; j < s->k_max; j++) {
+      row[j] = j < d.k ? d.ids[(size_t)j] : -1;
+      drow[j] = j < d.k ? d.dists[(size_t)j] : 0xFFFFFFFFu;
+    }
+    if (steps) steps[n] = d.steps;
+    if (submit_us) submit_us[n] = d.submit_us;
+    if (done_us) done_us[n] = d.done_us;
+    s->done_q.pop_front();
+    n++;
+  }
+  *n_out = n;
+  if (n == 0 && s->error.load()) return ann_internal_fail(s->error.load(), s->error_msg.c_str());
   return ANN_OK;
 }
 

@@ -24,7 +24,8 @@ EXPORTED = ["ann_index_create", "ann_index_info_get", "ann_search", "ann_index_f
             "ann_last_error", "ann_device_clock_khz", "ann_save_index", "ann_build_index",
             "ann_load_records", "ann_agent_configure", "ann_agent_stats", "ann_search_graph",
             "ann_graph_launch", "ann_graph_free", "ann_server_open", "ann_server_submit",
-            "ann_server_poll", "ann_server_stats_get", "ann_server_close", "ann_clock_us"]
+            "ann_server_poll", "ann_server_stats_get", "ann_server_close", "ann_clock_us",
+            "ann_server_submit_batch", "ann_server_poll_into"]
 
 
 class AnnError(RuntimeError):
@@ -116,6 +117,11 @@ def load_library(path: str = LIB_PATH):
     lib.ann_server_open.restype = ctypes.c_int
     lib.ann_server_submit.argtypes = [vp, vp, i32, i32, ctypes.c_uint64]
     lib.ann_server_submit.restype = ctypes.c_int
+    lib.ann_server_submit_batch.argtypes = [vp, vp, i64, vp, vp, vp, vp]
+    lib.ann_server_submit_batch.restype = ctypes.c_int
+    lib.ann_server_poll_into.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp,
+                                         ctypes.POINTER(i32), i32]
+    lib.ann_server_poll_into.restype = ctypes.c_int
     lib.ann_server_poll.argtypes = [vp, ctypes.POINTER(Result), i32, ctypes.POINTER(i32), i32]
     lib.ann_server_poll.restype = ctypes.c_int
     lib.ann_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
@@ -371,6 +377,18 @@ class Server:
             raise ValueError("query must have %d elements" % self.d)
         _check(load_library().ann_server_submit(self._h, q.ctypes.data, int(k), int(L), int(tag)))
 
+    def submit_batch(self, queries: np.ndarray, ks, Ls, tags, arrival_us=None) -> None:
+        """Queue many queries; optional non-decreasing arrival times (clock_us())."""
+        q = np.ascontiguousarray(queries, dtype=self.dtype)
+        n = q.shape[0]
+        ks = np.ascontiguousarray(ks, dtype=np.int32)
+        Ls = np.ascontiguousarray(Ls, dtype=np.int32)
+        tags = np.ascontiguousarray(tags, dtype=np.uint64)
+        arr = None if arrival_us is None else np.ascontiguousarray(arrival_us, dtype=np.float64)
+        _check(load_library().ann_server_submit_batch(
+            self._h, q.ctypes.data, n, ks.ctypes.data, Ls.ctypes.data, tags.ctypes.data,
+            arr.ctypes.data if arr is not None else None))
+
     def poll(self, max_results: int = 4096, timeout_us: int = 0):
         """Completed results: list of dicts (ids, dists copied to numpy)."""
         n = ctypes.c_int32()
@@ -386,6 +404,34 @@ class Server:
                                         shape=(r.k,)).copy()
             out.append({"tag": r.tag, "status": r.status, "ids": ids, "dists": raw.view(dt),
                         "steps": r.steps, "submit_us": r.submit_us, "done_us": r.done_us})
+        return out
+
+    def drain(self, n_expected: int, timeout_s: float = 120.0, chunk: int = 8192):
+        """Collect n_expected results with the bulk poll; returns numpy arrays
+        (tags, ks, ids [n, k_max], dists [n, k_max], steps, submit_us, done_us)."""
+        import time
+
+        dt = np.float32 if self.dtype == np.float32 else np.uint32
+        out = {"tags": np.zeros(n_expected, np.uint64), "ks": np.zeros(n_expected, np.int32),
+               "ids": np.zeros((n_expected, self.k_max), np.int32),
+               "dists": np.zeros((n_expected, self.k_max), np.uint32),
+               "steps": np.zeros(n_expected, np.uint32),
+               "submit_us": np.zeros(n_expected), "done_us": np.zeros(n_expected)}
+        got = 0
+        nn = ctypes.c_int32()
+        end = time.time() + timeout_s
+        lib = load_library()
+        while got < n_expected and time.time() < end:
+            m = min(chunk, n_expected - got)
+            _check(lib.ann_server_poll_into(
+                self._h, m, out["tags"][got:].ctypes.data, out["ks"][got:].ctypes.data,
+                out["ids"][got:].ctypes.data, out["dists"][got:].ctypes.data,
+                out["steps"][got:].ctypes.data, out["submit_us"][got:].ctypes.data,
+                out["done_us"][got:].ctypes.data, ctypes.byref(nn), 2000))
+            got += nn.value
+        for key in out:
+            out[key] = out[key][:got]
+        out["dists"] = out["dists"].view(dt)
         return out
 
     def stats(self) -> dict:
