@@ -105,7 +105,7 @@ def serving_leg(fa, ix, queries, kth, budget):
     with fa.Server(ix, hbm_budget_bytes=budget) as srv:
         st = srv.stats()
         out["slots"], out["resident_waves"] = st["slots"], st["resident_waves"]
-        m0 = 40000
+        m0 = 200000
         ks, Ls = mix(m0)
         idx = np.arange(m0) % nq
         t0 = fa.clock_us()
