@@ -81,8 +81,12 @@ typedef struct {
 
 /* Search options; a NULL pointer means {delay = 1, beam_width = 1, defaults}. */
 typedef struct {
-  int32_t delay;           /* staleness: 0 = strict best-first, 1 = relaxed (section 4.1.4 default) */
-  int32_t beam_width;      /* nodes selected per iteration; only 1 is implemented */
+  int32_t delay;           /* staleness delta (section 4.1.2): a node selected in
+                              one iteration is processed once delta * W newer
+                              nodes are in flight; 0 = strict best-first,
+                              1 = the paper's default (section 4.1.4) */
+  int32_t beam_width;      /* W, nodes selected per iteration (default 1);
+                              (delay + 1) * W <= 8 nodes may be in flight */
   int32_t hash_bits;       /* log2 of the per-query visited-hash slots (0 = default 10) */
   int32_t waves_per_block; /* queries per workgroup, 1..4 (0 = default 4) */
   unsigned long long *d_stats; /* optional device counters, 3 x u64, accumulated:
@@ -200,9 +204,14 @@ int ann_index_info_get(const ann_index *ix, ann_index_info *out);
  *              (f32, padding +inf)
  *   d_steps    device, nq uint32 expansions per query, optional (NULL)
  * Buffers must stay valid until the stream syncs.
- * Errors: ANN_EINVAL before any device work; ANN_ENOTSUP for delay > 1 or
- * beam_width > 1; AGENT: ANN_EIO / ANN_ETIMEDOUT when a record read failed or
- * never completed (those queries return ids -1; the others are valid).
+ * Schedule: select up to W unexpanded candidates per iteration into a FIFO
+ * of in-flight nodes, then process the oldest while more than delay * W are
+ * in flight (the oldest min(W, in flight) when nothing was selected); stop
+ * when nothing is selectable and nothing is in flight.
+ * Errors: ANN_EINVAL before any device work; ANN_ENOTSUP when
+ * (delay + 1) * beam_width > 8; AGENT: ANN_EIO / ANN_ETIMEDOUT when a record
+ * read failed or never completed (those queries return ids -1; the others
+ * are valid).
  */
 int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int32_t L, int32_t R,
                const ann_search_opts *opts, int32_t *d_ids, void *d_dists, uint32_t *d_steps,

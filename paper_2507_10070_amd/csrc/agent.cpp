@@ -35,7 +35,8 @@ Agent::~Agent() {
 }
 
 void Agent::arm(AgentRequest *req, uint32_t *cpl, uint8_t *stage, int64_t nq,
-                int64_t stage_stride) {
+                int64_t stage_stride, int slots) {
+  slots_ = slots < 1 ? 1 : (slots > kMaxSlots ? kMaxSlots : slots);
   req_ = req;
   cpl_ = cpl;
   stage_ = stage;
@@ -57,7 +58,8 @@ bool Agent::serve(int64_t q, uint32_t seq, uint32_t node, uint8_t *bounce) {
   if ((int32_t)node == faults.drop_node) return false;  // never completes
   if ((int32_t)node == faults.delay_node && faults.delay_us > 0)
     std::this_thread::sleep_for(std::chrono::microseconds(faults.delay_us));
-  uint8_t *dst = stage_ + (q * 2 + (seq & 1)) * stage_stride_;
+  const uint32_t sl = seq % (uint32_t)slots_;
+  uint8_t *dst = stage_ + (q * slots_ + sl) * stage_stride_;
   bool ok = true;
   if (mem_) {
     std::memcpy(dst, mem_ + (int64_t)node * slot_, (size_t)copy_bytes_);
@@ -69,7 +71,7 @@ bool Agent::serve(int64_t q, uint32_t seq, uint32_t node, uint8_t *bounce) {
     if (ok && direct_) std::memcpy(dst, bounce, (size_t)copy_bytes_);
   }
   if ((int32_t)node == faults.fail_node) ok = false;
-  __atomic_store_n(&cpl_[q * kCplStride + (seq & 1)], ok ? seq : (seq | kCplError), __ATOMIC_RELEASE);
+  __atomic_store_n(&cpl_[q * kCplStride + sl], ok ? seq : (seq | kCplError), __ATOMIC_RELEASE);
   stats.requests.fetch_add(1, std::memory_order_relaxed);
   stats.bytes.fetch_add(mem_ ? (uint64_t)copy_bytes_ : (uint64_t)io_bytes_,
                         std::memory_order_relaxed);
@@ -96,7 +98,8 @@ void Agent::run(int t) {
     for (int64_t q = q0; q < q1; q++) {
       uint32_t d = done_[(size_t)q];
       for (;;) {
-        const uint64_t w = __atomic_load_n(&req_[q].slot[(d + 1) & 1], __ATOMIC_ACQUIRE);
+        const uint64_t w =
+            __atomic_load_n(&req_[q].slot[(d + 1) % (uint32_t)slots_], __ATOMIC_ACQUIRE);
         if ((uint32_t)w != d + 1) break;
         d++;
         serve(q, d, (uint32_t)(w >> 32), bounce);

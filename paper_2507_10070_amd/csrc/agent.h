@@ -15,23 +15,24 @@
 
 namespace fa {
 
-// One query's request slots, written by its GPU wave: request s is the
-// 64-bit word slot[s & 1] = (node << 32) | s, stored in one piece, so the
-// agent never sees a sequence number without its node.  At most two requests
-// of a query are outstanding (strict or one-step-stale schedule), and a wave
-// reuses a slot only after consuming the request that held it.
-// Padded to a 64 B line so that no two queries (and no GPU wave and agent
-// thread pair) share a cache line.
+// One query's request slots, written by its GPU wave: with P slots in use,
+// request s is the 64-bit word slot[s % P] = (node << 32) | s, stored in one
+// piece, so the agent never sees a sequence number without its node.  At most
+// P requests of a query are outstanding (P >= the nodes in flight of the
+// schedule: 2 for strict and one-step-stale search, (delay + 1) * W in
+// general) and they are consumed in order, so a wave reuses a slot only after
+// consuming the request that held it.  One 64 B line per query, so that no
+// two queries (and no GPU wave and agent thread pair) share a cache line.
+constexpr int kMaxSlots = 8;
 struct alignas(64) AgentRequest {
-  uint64_t slot[2];
-  uint64_t pad[6];
+  uint64_t slot[kMaxSlots];
 };
 
-// Completion words of query q: cpl[kCplStride * q + (s & 1)], one 64 B line
+// Completion words of query q: cpl[kCplStride * q + (s % P)], one 64 B line
 // per query.
 constexpr int kCplStride = 16;
 
-// Completion words: two per query, cpl[kCplStride q + (s & 1)] = s when
+// Completion words: P per query, cpl[kCplStride q + (s % P)] = s when
 // request s has been staged, s | kCplError when its read failed.  One word
 // per in-flight slot keeps each request's status until its wave has
 // consumed it.
@@ -63,9 +64,11 @@ class Agent {
   ~Agent();
 
   // Serve the requests of `nq` queries until disarm().  `cpl` holds
-  // kCplStride x nq completion words and `stage` two staging slots of `stage_stride` bytes
-  // per query (slot s & 1 for request s).  The caller zeroes req/cpl.
-  void arm(AgentRequest *req, uint32_t *cpl, uint8_t *stage, int64_t nq, int64_t stage_stride);
+  // kCplStride x nq completion words and `stage` `slots` staging slots of
+  // `stage_stride` bytes per query (slot s % slots for request s, slots in
+  // [1, kMaxSlots]).  The caller zeroes req/cpl.
+  void arm(AgentRequest *req, uint32_t *cpl, uint8_t *stage, int64_t nq, int64_t stage_stride,
+           int slots);
   // Stop serving; returns once no agent thread touches the arrays any more.
   void disarm();
 
@@ -92,6 +95,7 @@ class Agent {
   uint32_t *cpl_ = nullptr;
   uint8_t *stage_ = nullptr;
   int64_t nq_ = 0, stage_stride_ = 0;
+  int slots_ = 2;
   std::vector<uint32_t> done_;          // per query: last request served
 };
 

@@ -52,6 +52,7 @@ struct ann_index {
   uint8_t *stage = nullptr;         // fine-grained pinned host
   int32_t *d_status = nullptr;      // device
   int64_t tcap = 0, stage_stride = 0;
+  int32_t tslots = 0;               // staging slots per query
   uint32_t *d_work = nullptr;       // persistent launches: device work counter
 };
 
@@ -96,6 +97,7 @@ void free_transport(ann_index *ix) {
   ix->stage = nullptr;
   ix->d_status = nullptr;
   ix->tcap = 0;
+  ix->tslots = 0;
 }
 
 void release(ann_index *ix) {
@@ -235,7 +237,7 @@ int default_agent_threads(bool file) {
 }
 
 // Transport buffers for nq queries and the agent itself.
-int ensure_transport(ann_index *ix, int64_t nq) {
+int ensure_transport(ann_index *ix, int64_t nq, int32_t pslots) {
   const bool file = ix->tier == ANN_TIER_FILE;
   const int32_t io = file && ix->direct_io ? (int32_t)round_up(ix->rec_bytes, 512) : ix->rec_bytes;
   if (!ix->agent) {
@@ -243,23 +245,25 @@ int ensure_transport(ann_index *ix, int64_t nq) {
     ix->agent.reset(new fa::Agent(file ? nullptr : (const uint8_t *)ix->rec_host, ix->fd,
                                   ix->direct_io, ix->slot, ix->rec_bytes, io, t));
   }
-  if (nq <= ix->tcap) return ANN_OK;
+  if (nq <= ix->tcap && pslots <= ix->tslots) return ANN_OK;
+  const int64_t cap = std::max<int64_t>({nq, ix->tcap, 1024});
+  const int32_t slots = std::max(pslots, ix->tslots);
   fa::Agent *keep = ix->agent.release();
   free_transport(ix);
   ix->agent.reset(keep);
-  const int64_t cap = std::max<int64_t>(nq, 1024);
   ix->stage_stride = round_up(io, 512);
   hipError_t e;
   const unsigned fl = hipHostMallocCoherent | hipHostMallocMapped;
   if ((e = hipHostMalloc((void **)&ix->req, sizeof(fa::AgentRequest) * cap, fl)) != hipSuccess ||
       (e = hipHostMalloc((void **)&ix->cpl, sizeof(uint32_t) * fa::kCplStride * cap, fl)) !=
           hipSuccess ||
-      (e = hipHostMalloc((void **)&ix->stage, ix->stage_stride * 2 * cap, fl)) != hipSuccess ||
+      (e = hipHostMalloc((void **)&ix->stage, ix->stage_stride * slots * cap, fl)) != hipSuccess ||
       (e = hipMalloc(&ix->d_status, sizeof(int32_t) * cap)) != hipSuccess) {
     free_transport(ix);
     return hip_fail(e, "transport buffers");
   }
   ix->tcap = cap;
+  ix->tslots = slots;
   return ANN_OK;
 }
 
@@ -523,8 +527,9 @@ int prepare_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, 
   if (o.waves_per_block == 0) o.waves_per_block = 4;
   if (o.delay < 0) return fail(ANN_EINVAL, "delay=%d must be >= 0", o.delay);
   if (o.beam_width < 1) return fail(ANN_EINVAL, "beam_width=%d must be >= 1", o.beam_width);
-  if (o.delay > 1) return fail(ANN_ENOTSUP, "delay=%d: the GPU kernels implement 0 and 1", o.delay);
-  if (o.beam_width != 1) return fail(ANN_ENOTSUP, "beam_width=%d: only 1 is implemented", o.beam_width);
+  if ((int64_t)(o.delay + 1) * o.beam_width > fa::kMaxPipe)
+    return fail(ANN_ENOTSUP, "(delay+1)*beam_width = %lld nodes in flight exceeds %d",
+                (long long)(o.delay + 1) * o.beam_width, fa::kMaxPipe);
   if (o.hash_bits < 6 || o.hash_bits > 14) return fail(ANN_EINVAL, "hash_bits=%d not in [6,14]", o.hash_bits);
   if (o.waves_per_block < 1 || o.waves_per_block > 4)
     return fail(ANN_EINVAL, "waves_per_block=%d not in [1,4]", o.waves_per_block);
@@ -577,6 +582,9 @@ int prepare_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, 
   a.order = o.d_order;
   a.work = ix->d_work;
   a.hash_bits = o.hash_bits;
+  a.delay = o.delay;
+  a.beam = o.beam_width;
+  a.pslots = std::max(2, (o.delay + 1) * o.beam_width);
   a.lds_per_wave = fa::search_lds_bytes(a.Lcap, a.nav_stride, a.hash_bits);
   if ((int64_t)a.lds_per_wave * o.waves_per_block > 160 * 1024)
     return fail(ANN_EINVAL, "LDS need %u B per query x %d exceeds 160 KiB", a.lds_per_wave,
@@ -603,7 +611,7 @@ int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int3
     hipError_t e = hipSuccess;
     if (o.persistent) e = fa::launch_reset(ix->d_work, st);
     if (e == hipSuccess)
-      e = fa::launch_search(a, ix->dtype, o.delay, fa::TR_DIRECT, o.waves_per_block,
+      e = fa::launch_search(a, ix->dtype, fa::TR_DIRECT, o.waves_per_block,
                             o.persistent != 0, st);
     if (e != hipSuccess) return hip_fail(e, "search launch");
     return ANN_OK;
@@ -612,7 +620,7 @@ int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int3
   // Query-grained transport: arm the agent, run, wait, disarm.  Synchronous
   // with respect to the host so that the request, completion and staging
   // arrays are never reused while a kernel may still touch them.
-  rc = ensure_transport(ix, nq);
+  rc = ensure_transport(ix, nq, a.pslots);
   if (rc) return rc;
   hipError_t e = hipStreamSynchronize(st);  // earlier work on the stream
   if (e != hipSuccess) return hip_fail(e, "stream sync");
@@ -628,10 +636,10 @@ int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int3
   a.status = ix->d_status;
   if (!a.req || !a.cpl || !a.stage) return fail(ANN_EIO, "transport buffers not mapped");
   ix->agent->faults = ix->faults;
-  ix->agent->arm(ix->req, ix->cpl, ix->stage, nq, ix->stage_stride);
+  ix->agent->arm(ix->req, ix->cpl, ix->stage, nq, ix->stage_stride, a.pslots);
   if (o.persistent) e = fa::launch_reset(ix->d_work, st);
   if (e == hipSuccess)
-    e = fa::launch_search(a, ix->dtype, o.delay, fa::TR_AGENT, o.waves_per_block,
+    e = fa::launch_search(a, ix->dtype, fa::TR_AGENT, o.waves_per_block,
                           o.persistent != 0, st);
   const hipError_t es = e == hipSuccess ? hipStreamSynchronize(st) : e;
   ix->agent->disarm();
@@ -688,7 +696,7 @@ int ann_search_graph(ann_index *ix, const void *d_queries, int64_t nq, int32_t k
   if (e == hipSuccess) {
     hipError_t e1 = fa::launch_reset(ix->d_work, st);
     if (e1 == hipSuccess)
-      e1 = fa::launch_search(a, ix->dtype, o.delay, fa::TR_DIRECT, o.waves_per_block, true, st);
+      e1 = fa::launch_search(a, ix->dtype, fa::TR_DIRECT, o.waves_per_block, true, st);
     e = hipStreamEndCapture(st, &g->graph);
     if (e == hipSuccess) e = e1;
   }

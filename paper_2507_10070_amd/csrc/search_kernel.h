@@ -13,9 +13,15 @@ enum { DT_U8 = 1, DT_I8 = 2, DT_F32 = 3 };
 // per-query staging slot (query-grained transport).
 enum { TR_DIRECT = 0, TR_AGENT = 1 };
 
+// Kernel schedules: strict (delay 0, one node per step), one-step-stale
+// (delay 1, one node per step), and any delay with any beam width W, the
+// in-flight nodes held in an LDS FIFO of at most (delay + 1) * W <= kMaxPipe.
+enum { SCHED_STRICT = 0, SCHED_RELAXED = 1, SCHED_GENERIC = 2 };
+constexpr int kMaxPipe = 8;
+
 // Byte offsets of one wave's LDS region.
 struct LdsLayout {
-  uint32_t cand, nk, stage, qbuf, ids, dsc, hash, bytes;
+  uint32_t cand, nk, stage, qbuf, ids, dsc, hash, fifo, bytes;
 };
 
 struct SearchArgs {
@@ -31,10 +37,11 @@ struct SearchArgs {
   unsigned long long *phases; // optional, strict schedule only: nq x 2 summed
                               // wall-clock ticks (record fetch, compute)
   // TR_AGENT only (fine-grained host memory except `status`):
-  uint64_t *req;           // nq x 8 u64 (64 B per query); slots 0,1: (node << 32) | seq
-  const uint32_t *cpl;     // nq x 16 u32 (64 B per query); words 0,1: seq or seq | 1<<31
-  const uint8_t *stage;    // nq x 2 staging slots of stage_stride bytes
+  uint64_t *req;           // nq x 8 u64 (64 B per query); slot seq % pslots: (node << 32) | seq
+  const uint32_t *cpl;     // nq x 16 u32 (64 B per query); word seq % pslots: seq or seq | 1<<31
+  const uint8_t *stage;    // nq x pslots staging slots of stage_stride bytes
   int64_t stage_stride;
+  int32_t pslots;          // request slots per query: at least the requests in flight
   uint32_t spin_limit;     // polls of a completion word before the query times out
   int32_t *status;         // nq per-query status, device: 0, -5 (read error), -110 (timeout)
   int32_t trace_cap;
@@ -46,6 +53,7 @@ struct SearchArgs {
   const int32_t *q_k;      // optional per-query k (clamped to [1, min(k, L_q)])
   const int32_t *order;    // optional processing order (persistent launches)
   uint32_t *work;          // persistent launches: device work counter, zero at launch
+  int32_t delay, beam;     // SCHED_GENERIC: staleness and beam width, (delay+1)*beam <= kMaxPipe
   uint32_t lds_per_wave;
 };
 
@@ -73,8 +81,10 @@ hipError_t launch_server(const ServerArgs &a, int dtype, int delay, int waves_pe
 
 // persistent: grid sized to the resident capacity of the GPU; waves take
 // queries from a->work (which must be zero at launch) until all are done.
-hipError_t launch_search(const SearchArgs &a, int dtype, int delay, int transport,
-                         int waves_per_block, bool persistent, hipStream_t st);
+// The schedule follows a.delay and a.beam: strict or one-step-stale kernels
+// for beam 1 and delay <= 1, the generic FIFO kernel otherwise.
+hipError_t launch_search(const SearchArgs &a, int dtype, int transport, int waves_per_block,
+                         bool persistent, hipStream_t st);
 // Zero the persistent work counter (a kernel, so that it can be captured in a
 // graph).
 hipError_t launch_reset(uint32_t *work, hipStream_t st);

@@ -10,6 +10,7 @@
 //   qbuf        the query, zero-padded to the navigation row stride
 //   ids/dsc     per-batch neighbour ids and their distances
 //   hash[H]     visited set: exact ids, linear probing, may forget
+//   fifo[8]     generic schedule: keys of the nodes in flight, oldest first
 // Forgetting is harmless: a forgotten node is either still in the list (its
 // recomputed key is identical and is dropped as a duplicate) or its key is
 // above the current L-th key, which never increases, so it is rejected again.
@@ -196,6 +197,7 @@ struct WaveLds {
   uint32_t *ids;
   uint32_t *dsc;
   uint32_t *hash;
+  uint64_t *fifo;
 };
 
 __host__ __device__ inline LdsLayout lds_layout(int Lcap, int nav_stride, int hash_bits) {
@@ -208,6 +210,7 @@ __host__ __device__ inline LdsLayout lds_layout(int Lcap, int nav_stride, int ha
   o.ids = off; off += 4u * 64u;
   o.dsc = off; off += 4u * 64u;
   o.hash = off; off += 4u << hash_bits;
+  o.fifo = off; off += 8u * (uint32_t)kMaxPipe;
   o.bytes = (off + 15u) & ~15u;
   return o;
 }
@@ -277,6 +280,7 @@ struct Searcher {
     S.ids = (uint32_t *)(base + lay.ids);
     S.dsc = (uint32_t *)(base + lay.dsc);
     S.hash = (uint32_t *)(base + lay.hash);
+    S.fifo = (uint64_t *)(base + lay.fifo);
     L = io.L;
     k = io.k;
     // query -> LDS, zero padded to the row stride
@@ -369,11 +373,18 @@ struct Searcher {
     return *(const uint4 *)(A.records + (int64_t)v * A.slot + 16 * c);
   }
 
+  // Request slot of request number s (TR_AGENT).  At most pslots requests of
+  // a query are in flight, and they are consumed in order, so request s
+  // reuses the slot of request s - pslots, which was consumed already.
+  __device__ __forceinline__ uint32_t pslot(uint32_t s) const {
+    return s % (uint32_t)A.pslots;
+  }
+
   // Start obtaining the record of v.  TR_DIRECT: the load itself (in flight
   // until used); `real` is ignored so that the load is unconditional.
   // TR_AGENT: post request seq+1 for v as one 64-bit system-scope store of
-  // (v << 32 | seq) into the query's request slot seq & 1, then continue;
-  // the returned handle carries the sequence number.  The store needs no
+  // (v << 32 | seq) into the query's request slot, then continue; the
+  // returned handle carries the sequence number.  The store needs no
   // release: the slot's previous request was consumed (its staged bytes
   // loaded and written to LDS) before this point, so the agent cannot
   // overwrite data the wave still reads.
@@ -382,7 +393,7 @@ struct Searcher {
     if (!real || failed) return make_uint4(0, 0, 0, 0);
     seq++;
     if (lane == 0)
-      __hip_atomic_store(A.req + 8 * qi + (seq & 1), ((uint64_t)v << 32) | seq, __ATOMIC_RELAXED,
+      __hip_atomic_store(A.req + 8 * qi + pslot(seq), ((uint64_t)v << 32) | seq, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_SYSTEM);
     return make_uint4(seq, 0, 0, 0);
   }
@@ -397,7 +408,7 @@ struct Searcher {
     if (failed || s == 0) return make_uint4(0, 0, 0, 0);
     uint32_t c = 0;
     if (lane == 0) {
-      const uint32_t *w = A.cpl + 16 * qi + (s & 1);
+      const uint32_t *w = A.cpl + 16 * qi + pslot(s);
       uint32_t spins = 0, nap = 1;
       for (;;) {
         c = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -423,7 +434,7 @@ struct Searcher {
     // fence (which would invalidate the whole L2 on every record) is needed.
     const int ch = lane < A.rec_chunks ? lane : A.rec_chunks - 1;
     const uint32_t *src =
-        (const uint32_t *)(A.stage + (qi * 2 + (s & 1)) * A.stage_stride + 16 * ch);
+        (const uint32_t *)(A.stage + (qi * A.pslots + pslot(s)) * A.stage_stride + 16 * ch);
     uint4 r;
     r.x = __hip_atomic_load(src + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     r.y = __hip_atomic_load(src + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -638,7 +649,55 @@ __device__ __forceinline__ void run_query(const SearchArgs &A, uint8_t *lds, int
   const unsigned long long t_start = A.times ? __builtin_amdgcn_s_memrealtime() : 0ull;
   Searcher<DT, CPL, TR> s(A, lds, qi, io);
   s.init_entry();
-  if (DELAY == 0) {
+  if (DELAY == SCHED_GENERIC) {
+    // Any staleness delta and beam width W (section 4.1.2, with W nodes taken
+    // per step): each iteration selects up to W unexpanded candidates into
+    // the FIFO of in-flight nodes, then processes the oldest while more than
+    // delta * W are in flight -- or the oldest min(W, in flight) when nothing
+    // was selected.  TR_AGENT posts each request when its node is selected,
+    // so up to (delta + 1) * W reads of one query are in flight at once.
+    // TR_DIRECT loads the record of the next node in the FIFO while the
+    // current one is scored (in-order memory counters allow one such load to
+    // overlap the gathers that follow it).
+    const int W = A.beam, lim = A.delay * A.beam;
+    const uint32_t dummy = (uint32_t)A.entry;
+    int head = 0, len = 0;
+    uint32_t cseq = 0;  // TR_AGENT: requests consumed so far
+    uint4 nxt = make_uint4(0, 0, 0, 0);
+    bool have_nxt = false;
+    for (;;) {
+      int nsel = 0;
+      while (nsel < W) {
+        const uint64_t v = s.select();
+        if (v == kNoKey) break;
+        if (s.lane == 0) s.S.fifo[(head + len) & (kMaxPipe - 1)] = v;
+        if (TR == TR_AGENT) (void)s.issue((uint32_t)v & ~kFlag, true);
+        len++;
+        nsel++;
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (nsel == 0 && len == 0) break;
+      int todo = len > lim ? len - lim : 0;
+      if (nsel == 0 && todo == 0) todo = len < W ? len : W;
+      for (; todo > 0; todo--) {
+        const uint64_t u = s.S.fifo[head];
+        head = (head + 1) & (kMaxPipe - 1);
+        len--;
+        if (TR == TR_DIRECT) {
+          const bool more = len > 0;
+          const uint32_t fid = more ? ((uint32_t)s.S.fifo[head] & ~kFlag) : dummy;
+          uint4 rec;
+          if (have_nxt) rec = nxt;
+          else rec = s.fetch((uint32_t)u & ~kFlag);
+          s.template process<true>(u, rec, fid, more, nxt);
+          have_nxt = more;
+        } else {
+          uint4 unused;
+          s.template process<false>(u, make_uint4(++cseq, 0, 0, 0), 0u, false, unused);
+        }
+      }
+    }
+  } else if (DELAY == SCHED_STRICT) {
     uint4 unused = make_uint4(0, 0, 0, 0);
     if (A.phases) {
       // the same steps with a stamp at issue, after staging and after merge:
@@ -724,11 +783,11 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs A) {
 
 __global__ void reset_work(uint32_t *work) { *work = 0u; }
 
-// Continuous-batching server.  A wave claims ring index c only once the host
-// has published it (c < published), so a wave that leaves while idle holds no
-// claim.  The entry is read with system-scope loads because ring memory is
-// rewritten by host copies; results go to host-mapped rows, then the slot's
-// done word tells the host.
+// Continuous-batching server.  Waves take ring indices as tickets from one
+// counter and serve each once the host has published it; a wave that leaves
+// while idle holds no ticket (see the claim loop).  The entry is read with
+// system-scope loads because ring memory is rewritten by host copies; results
+// go to host-mapped rows, then the slot's done word tells the host.
 template <int DT, int CPL, int DELAY>
 __global__ void __launch_bounds__(256) server_kernel(ServerArgs S) {
   extern __shared__ __align__(16) uint8_t smem[];
@@ -835,26 +894,27 @@ static hipError_t launch_t(const SearchArgs &a, int waves_per_block, bool persis
 }
 
 template <int DT, int CPL, int TR>
-static hipError_t launch_d(const SearchArgs &a, int delay, int wpb, bool pers, hipStream_t st) {
-  return delay == 0 ? launch_t<DT, CPL, 0, TR>(a, wpb, pers, st)
-                    : launch_t<DT, CPL, 1, TR>(a, wpb, pers, st);
+static hipError_t launch_d(const SearchArgs &a, int wpb, bool pers, hipStream_t st) {
+  if (a.delay < 0 || a.beam < 1 || (a.delay + 1) * a.beam > kMaxPipe) return hipErrorInvalidValue;
+  if (a.beam == 1 && a.delay == 0) return launch_t<DT, CPL, SCHED_STRICT, TR>(a, wpb, pers, st);
+  if (a.beam == 1 && a.delay == 1) return launch_t<DT, CPL, SCHED_RELAXED, TR>(a, wpb, pers, st);
+  return launch_t<DT, CPL, SCHED_GENERIC, TR>(a, wpb, pers, st);
 }
 
 template <int DT, int CPL>
-static hipError_t launch_tr(const SearchArgs &a, int delay, int tr, int wpb, bool pers,
-                            hipStream_t st) {
-  return tr == TR_DIRECT ? launch_d<DT, CPL, TR_DIRECT>(a, delay, wpb, pers, st)
-                         : launch_d<DT, CPL, TR_AGENT>(a, delay, wpb, pers, st);
+static hipError_t launch_tr(const SearchArgs &a, int tr, int wpb, bool pers, hipStream_t st) {
+  return tr == TR_DIRECT ? launch_d<DT, CPL, TR_DIRECT>(a, wpb, pers, st)
+                         : launch_d<DT, CPL, TR_AGENT>(a, wpb, pers, st);
 }
 
 template <int DT>
-static hipError_t launch_c(const SearchArgs &a, int cpl, int delay, int tr, int wpb, bool pers,
+static hipError_t launch_c(const SearchArgs &a, int cpl, int tr, int wpb, bool pers,
                            hipStream_t st) {
   switch (cpl) {
-    case 1: return launch_tr<DT, 1>(a, delay, tr, wpb, pers, st);
-    case 2: return launch_tr<DT, 2>(a, delay, tr, wpb, pers, st);
-    case 3: return launch_tr<DT, 3>(a, delay, tr, wpb, pers, st);
-    case 4: return launch_tr<DT, 4>(a, delay, tr, wpb, pers, st);
+    case 1: return launch_tr<DT, 1>(a, tr, wpb, pers, st);
+    case 2: return launch_tr<DT, 2>(a, tr, wpb, pers, st);
+    case 3: return launch_tr<DT, 3>(a, tr, wpb, pers, st);
+    case 4: return launch_tr<DT, 4>(a, tr, wpb, pers, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -863,13 +923,13 @@ uint32_t search_lds_bytes(int Lcap, int nav_stride, int hash_bits) {
   return lds_layout(Lcap, nav_stride, hash_bits).bytes;
 }
 
-hipError_t launch_search(const SearchArgs &a, int dtype, int delay, int transport,
-                         int waves_per_block, bool persistent, hipStream_t st) {
+hipError_t launch_search(const SearchArgs &a, int dtype, int transport, int waves_per_block,
+                         bool persistent, hipStream_t st) {
   const int cpl = a.nav_stride / 128;
   switch (dtype) {
-    case DT_U8: return launch_c<DT_U8>(a, cpl, delay, transport, waves_per_block, persistent, st);
-    case DT_I8: return launch_c<DT_I8>(a, cpl, delay, transport, waves_per_block, persistent, st);
-    case DT_F32: return launch_c<DT_F32>(a, cpl, delay, transport, waves_per_block, persistent, st);
+    case DT_U8: return launch_c<DT_U8>(a, cpl, transport, waves_per_block, persistent, st);
+    case DT_I8: return launch_c<DT_I8>(a, cpl, transport, waves_per_block, persistent, st);
+    case DT_F32: return launch_c<DT_F32>(a, cpl, transport, waves_per_block, persistent, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -320,8 +320,8 @@ class SearchGraph:
 
     def __init__(self, index: Index, queries, k: int, L: int, stream, R: int = 0,
                  delay: int = 1, hash_bits: int = 0, waves_per_block: int = 0,
-                 L_per_query=None, k_per_query=None, order=None, out=None):
-        nq, ids, dists, steps, opts = _prepare(index, queries, k, L, R, delay, 1, hash_bits,
+                 L_per_query=None, k_per_query=None, order=None, out=None, beam_width: int = 1):
+        nq, ids, dists, steps, opts = _prepare(index, queries, k, L, R, delay, beam_width, hash_bits,
                                                waves_per_block, None, None, None, None,
                                                TRANSPORT_DIRECT, 0, L_per_query, k_per_query,
                                                order, True, out)

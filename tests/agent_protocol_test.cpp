@@ -2,13 +2,14 @@
 // waves (same structs, same atomics), the real agent serves them.  Built with
 // ThreadSanitizer by tests/test_agent_protocol.py.
 //
-// Each fake wave issues requests in the strict pattern (one outstanding) or
-// the relaxed pattern (a second request issued before the first is consumed),
-// waits on its completion word with acquire loads, and checks the staged bytes
+// Each fake wave keeps up to `depth` requests outstanding (1: strict, 2: one
+// step stale, P: a full pipeline of P slots), consumes them in order, waits on
+// each completion word with acquire loads, and checks the staged bytes
 // against the record store.  Faults: a slow node (straggler) and a failing
 // node (error completion).
 #include <atomic>
 #include <cstdio>
+#include <deque>
 #include <cstring>
 #include <random>
 #include <thread>
@@ -39,9 +40,10 @@ int main(int argc, char **argv) {
   std::vector<AgentRequest> req(nq);
   std::vector<uint32_t> cpl(fa::kCplStride * nq, 0);
   const int64_t stride = 512;
-  std::vector<uint8_t> stage(nq * 2 * stride, 0);
+  const int P = 5;
+  std::vector<uint8_t> stage(nq * P * stride, 0);
   std::memset(req.data(), 0, sizeof(AgentRequest) * nq);
-  agent.arm(req.data(), cpl.data(), stage.data(), nq, stride);
+  agent.arm(req.data(), cpl.data(), stage.data(), nq, stride, P);
 
   std::atomic<int> errors{0}, failures_seen{0};
   auto wave = [&](int64_t q) {
@@ -52,14 +54,14 @@ int main(int argc, char **argv) {
       // release: this thread's reads of the slot's previous staging data are
       // ordered before the agent may overwrite it (on the GPU the wave has
       // consumed that data into LDS before it issues the next request)
-      __atomic_store_n(&req[q].slot[seq & 1], ((uint64_t)node << 32) | seq, __ATOMIC_RELEASE);
+      __atomic_store_n(&req[q].slot[seq % P], ((uint64_t)node << 32) | seq, __ATOMIC_RELEASE);
       return seq;
     };
     auto consume = [&](uint32_t s, uint32_t node) {
       // wait until this slot's completion word names request s
       uint32_t c;
       while (true) {
-        c = __atomic_load_n(&cpl[q * fa::kCplStride + (s & 1)], __ATOMIC_ACQUIRE);
+        c = __atomic_load_n(&cpl[q * fa::kCplStride + s % P], __ATOMIC_ACQUIRE);
         if ((c & ~fa::kCplError) == s) break;
         std::this_thread::yield();
       }
@@ -68,25 +70,25 @@ int main(int argc, char **argv) {
         failures_seen++;
         return;
       }
-      const uint8_t *got = &stage[(q * 2 + (s & 1)) * stride];
+      const uint8_t *got = &stage[(q * P + s % P) * stride];
       if (std::memcmp(got, &records[(int64_t)node * slot], copy) != 0) errors++;
     };
-    const bool relaxed = q % 2 == 1;
-    uint32_t prev_node = 0, prev_seq = 0;
+    const int depth = q % 3 == 0 ? 1 : (q % 3 == 1 ? 2 : P);
+    std::deque<std::pair<uint32_t, uint32_t>> inflight;  // (seq, node), oldest first
     for (int i = 0; i < steps; i++) {
       uint32_t node = rng() % n;
       if (i % 50 == 3) node = 7;    // straggler
       if (i % 97 == 5) node = 11;   // failing read
-      const uint32_t s = issue(node);
-      if (relaxed) {
-        if (prev_seq) consume(prev_seq, prev_node);
-        prev_seq = s;
-        prev_node = node;
-      } else {
-        consume(s, node);
+      inflight.emplace_back(issue(node), node);
+      if ((int)inflight.size() == depth) {
+        consume(inflight.front().first, inflight.front().second);
+        inflight.pop_front();
       }
     }
-    if (relaxed && prev_seq) consume(prev_seq, prev_node);
+    while (!inflight.empty()) {
+      consume(inflight.front().first, inflight.front().second);
+      inflight.pop_front();
+    }
   };
   std::vector<std::thread> waves;
   for (int64_t q = 0; q < nq; q++) waves.emplace_back(wave, q);
@@ -101,7 +103,7 @@ int main(int argc, char **argv) {
   // the agent must be reusable after disarm
   std::memset(req.data(), 0, sizeof(AgentRequest) * nq);
   std::fill(cpl.begin(), cpl.end(), 0u);
-  agent.arm(req.data(), cpl.data(), stage.data(), nq, stride);
+  agent.arm(req.data(), cpl.data(), stage.data(), nq, stride, 2);
   __atomic_store_n(&req[0].slot[1], (42ull << 32) | 1u, __ATOMIC_RELEASE);
   while (__atomic_load_n(&cpl[1], __ATOMIC_ACQUIRE) != 1u) std::this_thread::yield();
   bad += check(std::memcmp(&stage[1 * stride], &records[42 * slot], copy) == 0, "re-armed serve");

@@ -217,7 +217,9 @@ def test_invalid_arguments(cfg1):
     with fa.Index(base, adj, entry, 256) as ix:
         for kw, code in [(dict(k=0, L=8), -22), (dict(k=9, L=8), -22), (dict(k=1, L=8, R=33), -22),
                          (dict(k=1, L=2000), -22), (dict(k=1, L=8, delay=-1), -22),
-                         (dict(k=1, L=8, delay=2), -95), (dict(k=1, L=8, beam_width=2), -95),
+                         (dict(k=1, L=8, delay=8), -95), (dict(k=1, L=8, beam_width=9), -95),
+                         (dict(k=1, L=8, delay=2, beam_width=3), -95),
+                         (dict(k=1, L=8, beam_width=0), -22),
                          (dict(k=1, L=8, hash_bits=3), -22),
                          (dict(k=1, L=8, waves_per_block=5), -22)]:
             with pytest.raises(fa.flashann.AnnError) as e:
@@ -253,3 +255,62 @@ def test_degree_selector_small():
     for r in rows:
         assert r["T_f_us"] > 0 and r["T_c_us"] > 0 and r["expansions"] > 0
     assert degree_selector.select(rows) in (8, 24)
+
+
+# Any staleness and beam width: the generic FIFO kernel (delta * W nodes may
+# stay in flight after each iteration, up to (delta + 1) * W = 8 in all).
+GENERIC = [(2, 1), (3, 1), (7, 1), (0, 2), (1, 2), (2, 2), (3, 2), (0, 4), (1, 4), (0, 8)]
+
+
+@pytest.mark.parametrize("tier", ["hbm", "host"])
+@pytest.mark.parametrize("delay,beam", GENERIC)
+def test_generic_schedule_parity(cfg1, tier, delay, beam):
+    base, q, adj, entry = cfg1
+    t = fa.TIER_HBM if tier == "hbm" else fa.TIER_HOST
+    with fa.Index(base, adj, entry, 256, t) as ix:
+        for L in (16, 100):
+            g = gpu_search(ix, q, 10, L, delay=delay, beam_width=beam, trace_cap=800)
+            ref = oracle.search(base, adj, entry, q, 10, L, delay=delay, beam=beam,
+                                trace_cap=800)
+            assert_int_parity(g, ref, check_trace=True)
+
+
+@pytest.mark.parametrize("delay,beam", [(2, 1), (1, 3), (0, 4)])
+def test_generic_schedule_shapes(delay, beam):
+    """i8/100 with R = 48 (two gather blocks per record, ids at a 112 B
+    offset), ragged batch, persistent grid."""
+    base = synth.make_base(6000, 100, "i8", 32, 701)
+    q = synth.make_queries(77, 100, "i8", 32, 701, 702)
+    adj, entry = synth.build_graph(base, 48, 703, threads=8)
+    with fa.Index(base, adj, entry, 512) as ix:
+        for persistent in (False, True):
+            g = gpu_search(ix, q, 7, 72, delay=delay, beam_width=beam, persistent=persistent,
+                           trace_cap=500)
+            ref = oracle.search(base, adj, entry, q, 7, 72, delay=delay, beam=beam, trace_cap=500)
+            assert_int_parity(g, ref, check_trace=True)
+
+
+@pytest.mark.parametrize("delay,beam", [(2, 1), (1, 2), (0, 4)])
+def test_generic_schedule_f32(delay, beam):
+    base = synth.make_base(5000, 96, "f32", 64, 611)
+    q = synth.make_queries(100, 96, "f32", 64, 611, 612)
+    adj, entry = synth.build_graph(base, 32, 613, threads=8)
+    with fa.Index(base, adj, entry, min_slot(96, 4, 32)) as ix:
+        g = gpu_search(ix, q, 10, 96, delay=delay, beam_width=beam, trace_cap=800)
+    ref = oracle.search(base, adj, entry, q, 10, 96, delay=delay, beam=beam, trace_cap=800)
+    assert_f32_parity(base, q, g, ref)
+
+
+def test_generic_exhaustive_equals_bruteforce():
+    """L >= N on a connected graph expands every node: any schedule returns
+    the exact top-k."""
+    base = synth.make_base(200, 128, "u8", 4, 721)
+    q = synth.make_queries(40, 128, "u8", 4, 721, 722)
+    adj, entry = synth.build_graph(base, 16, 723, threads=4)
+    bf_ids, bf_d = oracle.bruteforce(base, q, 10)
+    with fa.Index(base, adj, entry, 256) as ix:
+        for delay, beam in ((2, 1), (1, 4), (0, 8)):
+            g = gpu_search(ix, q, 10, 256, delay=delay, beam_width=beam)
+            np.testing.assert_array_equal(g["ids"], bf_ids)
+            np.testing.assert_array_equal(g["dists"].astype(np.float64), bf_d)
+            assert (g["steps"] == 200).all()

@@ -145,3 +145,53 @@ def test_transport_validation(cfg1):
         with pytest.raises(fa.AnnError) as e:
             fa.search(ix, qd, k=10, L=64, transport=7)
         assert e.value.code == -22
+
+
+@pytest.mark.parametrize("delay,beam", [(2, 1), (3, 1), (1, 2), (0, 4), (3, 2), (7, 1)])
+def test_agent_deep_pipeline_parity(cfg1, tmp_path, delay, beam):
+    """Up to (delay + 1) * W requests of one query in flight through the
+    agent: host DRAM and file tiers give the oracle's results bit-exactly."""
+    base, q, adj, entry = cfg1
+    ref = oracle.search(base, adj, entry, q, 10, 64, delay=delay, beam=beam, trace_cap=600)
+    with fa.Index(base, adj, entry, 256, fa.TIER_HOST) as ix:
+        ix.configure_agent(threads=4)
+        g = run(ix, q, 10, 64, delay=delay, beam_width=beam, transport=fa.TRANSPORT_AGENT,
+                trace_cap=600)
+        assert_same(g, ref)
+        np.testing.assert_array_equal(g["trace"], ref["trace"])
+        assert ix.agent_stats()["requests"] == int(ref["steps"].sum())
+    d = str(tmp_path / "ix")
+    fa.save_index(d, base, adj, entry, 512)
+    with fa.Index.load(d, fa.TIER_FILE) as fix:
+        assert_same(run(fix, q, 10, 64, delay=delay, beam_width=beam), ref)
+
+
+def test_agent_deep_pipeline_faults(cfg1):
+    base, q, adj, entry = cfg1
+    ref = oracle.search(base, adj, entry, q, 10, 64, delay=2, beam=2, trace_cap=400)
+    bad_node = _node_in_some_traces(ref)
+    hit = np.array([(row == bad_node).any() for row in ref["trace"]])
+    qd = torch.from_numpy(q).to("cuda:0")
+    ids = torch.empty((len(q), 10), dtype=torch.int32, device="cuda:0")
+    dists = torch.empty((len(q), 10), dtype=torch.int32, device="cuda:0")
+    steps = torch.empty((len(q),), dtype=torch.int32, device="cuda:0")
+    with fa.Index(base, adj, entry, 256, fa.TIER_HOST) as ix:
+        ix.configure_agent(threads=3, delay_node=bad_node, delay_us=2000)
+        assert_same(run(ix, q, 10, 64, delay=2, beam_width=2, transport=fa.TRANSPORT_AGENT), ref)
+        ix.configure_agent(threads=3, fail_node=bad_node)
+        with pytest.raises(fa.AnnError) as e:
+            fa.search(ix, qd, k=10, L=64, delay=2, beam_width=2, transport=fa.TRANSPORT_AGENT,
+                      out=(ids, dists, steps))
+        assert e.value.code == -5
+        g = {"ids": ids.cpu().numpy(), "dists": dists.cpu().numpy().view(np.uint32),
+             "steps": steps.cpu().numpy().view(np.uint32)}
+        assert (g["ids"][hit] == -1).all()
+        assert_same(g, ref, rows=~hit)
+        ix.configure_agent(threads=3, drop_node=bad_node)
+        with pytest.raises(fa.AnnError) as e:
+            fa.search(ix, qd, k=10, L=64, delay=2, beam_width=2, transport=fa.TRANSPORT_AGENT,
+                      spin_limit=2000, out=(ids, dists, steps))
+        assert e.value.code == -110
+        g["ids"] = ids.cpu().numpy()
+        assert (g["ids"][hit] == -1).all()
+        np.testing.assert_array_equal(g["ids"][~hit], ref["ids"][~hit])
