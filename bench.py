@@ -26,6 +26,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 L_SWEEP = (32, 48, 64, 96, 128, 192, 256)
+# (delta, W) pairs of the schedule sweep; (delta + 1) * W <= 8
+SCHEDULES = ((0, 1), (1, 1), (2, 1), (3, 1), (0, 2), (1, 2), (3, 2), (0, 4), (1, 4), (0, 8))
 
 
 def log(msg):
@@ -170,6 +172,11 @@ def main():
                     help="skip the continuous-batching serving measurement")
     ap.add_argument("--serving-budget-mb", type=int, default=256,
                     help="HBM budget of the serving admission")
+    ap.add_argument("--no-schedule-sweep", action="store_true",
+                    help="skip the (delay, beam width) sweep")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the autotuned uneven-L batch")
+    ap.add_argument("--batched-queries", type=int, default=100000)
     ap.add_argument("--no-transports", action="store_true",
                     help="skip the agent-transport and file-tier measurements")
     ap.add_argument("--file-queries", type=int, default=1000,
@@ -253,17 +260,18 @@ def main():
                          "query_latency_ms_p99": float(np.percentile(lat_ms, 99))}
 
     # ---- timed region: K launches per schedule, HIP events on the launch stream
-    def timed(L, delay):
-        for _ in range(args.warmup):
-            run(L, delay)
+    def timed(L, delay, steps_=None, warmup_=None, **kw):
+        steps_ = args.steps if steps_ is None else steps_
+        for _ in range(args.warmup if warmup_ is None else warmup_):
+            run(L, delay, **kw)
         torch.cuda.synchronize()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps_ + 1)]
         ev[0].record(stream)
-        for i in range(args.steps):
-            run(L, delay)
+        for i in range(steps_):
+            run(L, delay, **kw)
             ev[i + 1].record(stream)
         torch.cuda.synchronize()
-        per = [ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]
+        per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps_)]
         return sum(per) / len(per)
 
     log("timing strict at L=%d and relaxed at L=%d" % (op[0], op[1]))
@@ -296,7 +304,8 @@ def main():
     workload = "config2-1M-u8-128-R64-host" if (n, nq, tier) == (cfg.n, cfg.nq, fa.TIER_HOST) \
         else "custom"
     hbm_ach = hbm_bytes / sec / 1e9
-    roofline = {"bound": "hbm", "achieved": round(hbm_ach, 2), "peak": HBM_PEAK_GBS,
+    roofline = {"bound": "hbm", "binding": "host_link" if link_bytes else "hbm",
+                "achieved": round(hbm_ach, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(hbm_ach / HBM_PEAK_GBS, 5),
                 "traffic": stored_traffic(workload),
                 "algorithmic_bytes_per_launch": hbm_bytes,
@@ -304,6 +313,73 @@ def main():
                               "peak_probe": round(link_peak, 2), "unit": "GB/s",
                               "frac": round(link_bytes / sec / 1e9 / link_peak, 4),
                               "bytes_per_launch": link_bytes}}
+
+    # ---- staleness delta and beam width W at the relaxed operating L: steps,
+    # recall and throughput of each schedule (direct loads; agent transport
+    # too when records are in host DRAM)
+    schedules = None
+    if not args.no_schedule_sweep:
+        schedules = []
+        Lr = op[1]
+        for delay, beam in SCHEDULES:
+            run(Lr, delay, beam_width=beam)
+            torch.cuda.synchronize()
+            row = {"delay": delay, "W": beam,
+                   "recall@10": round(recall_at(dists.cpu().numpy().view(np.uint32), kth), 4),
+                   "mean_steps": round(float(steps.cpu().numpy().mean()), 2)}
+            row["qps"] = round(nq / (timed(Lr, delay, 3, 1, beam_width=beam) / 1e3), 1)
+            if tier == fa.TIER_HOST and not args.no_transports:
+                t = time.perf_counter()
+                run(Lr, delay, beam_width=beam, transport=fa.TRANSPORT_AGENT)
+                row["agent_qps"] = round(nq / (time.perf_counter() - t), 1)
+            schedules.append(row)
+            log("schedule %s" % row)
+
+    # ---- batched form: 100k searches with L uniform over {32, 64, 128, 256}
+    # in one launch, tiles and schedule chosen by the autotuner
+    batched = None
+    if not args.no_batched:
+        from paper_2507_10070_amd import autotune
+
+        nb = args.batched_queries
+        rng = np.random.default_rng(17)
+        rows = rng.integers(0, nq, nb)
+        qb = qd[torch.from_numpy(rows).to(dev)].contiguous()
+        Lq = rng.choice(np.array([32, 64, 128, 256], np.int32), nb)
+        Lt = torch.from_numpy(Lq).to(dev)
+        kthb = kth[rows]
+
+        def score(i_, d_, s_):
+            return recall_at(d_.cpu().numpy().view(np.uint32), kthb)
+
+        t = time.time()
+        tuned = autotune.tune(ix, qb, k, 256, score=score, cache_path=None, reps=2,
+                              L_per_query=Lt)
+        t_tune = time.time() - t
+        kw = autotune.search_kwargs(tuned["params"], {"L_per_query": Lt})
+        ob = (torch.empty((nb, k), dtype=torch.int32, device=dev),
+              torch.empty((nb, k), dtype=torch.int32, device=dev),
+              torch.empty((nb,), dtype=torch.int32, device=dev))
+        fa.search(ix, qb, k=k, L=256, out=ob, stream=stream, **kw)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        reps_b = 3
+        for _ in range(reps_b):
+            fa.search(ix, qb, k=k, L=256, out=ob, stream=stream, **kw)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        ms_b = ev[0].elapsed_time(ev[1]) / reps_b
+        batched = {"queries": nb, "L": [32, 64, 128, 256], "k": k,
+                   "tuned": {"params": tuned["params"], "qps": round(nb / (ms_b / 1e3), 1),
+                             "ms_per_launch": round(ms_b, 3),
+                             "recall@10": round(score(*ob), 4)},
+                   "default": {"params": tuned["default"]["params"],
+                               "qps": round(nb / (tuned["default"]["ms"] / 1e3), 1),
+                               "recall@10": round(tuned["default"]["score"], 4)},
+                   "settings_tried": len(tuned["table"]), "tune_s": round(t_tune, 1)}
+        log("batched: %s" % batched)
+        del qb, ob
 
     # ---- the paper's query-grained I/O stack on the same workload: agent
     # transport from pinned DRAM (all queries) and from a file (O_DIRECT)
@@ -412,6 +488,8 @@ def main():
         "detail": {"strict": detail[0], "relaxed": detail[1]},
         "sweep": {"strict": sweep[0], "relaxed": sweep[1]},
         "roofline": roofline,
+        "schedules": schedules,
+        "batched": batched,
         "transports": transports,
         "serving": serving,
         "cpu_baseline": cpu,

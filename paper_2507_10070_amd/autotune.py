@@ -1,26 +1,40 @@
 """Autotuner for search launches.
 
-Tiles that do not change results -- queries per workgroup, visited-hash size,
-persistent or one-shot grid -- and the prefetch depth (the staleness delay,
-which changes the search path but keeps it valid) are measured on a
-representative batch; the fastest setting is cached per
-(dtype, d, R, tier, L bucket, nq bucket) in a JSON file.
+Two kinds of parameters are tuned on a representative batch:
+
+* tiles that do not change results -- queries per workgroup, visited-hash
+  size, persistent or one-shot grid, and for uneven batches (per-query L) the
+  processing order: as given, or longest list first (`longest_first`);
+* schedule parameters that change the search path but keep it valid -- the
+  staleness delay (prefetch depth, paper section 4.1.2) and the beam width W.
+  These can move recall a little either way, so a setting is admissible only
+  if its quality score (e.g. recall@10) is at least the default setting's
+  minus `score_slack`.
+
+The search is coordinate descent from the default setting (each parameter in
+turn over its values, others fixed, `passes` times), which needs a few dozen
+launches instead of the full product.  The fastest admissible setting is cached
+per (dtype, d, R, tier, L bucket, nq bucket, uneven) in a JSON file.
 
     best = autotune.tune(index, queries, k=10, L=192)
-    fa.search(index, queries, k=10, L=192, **best["params"])
+    fa.search(index, queries, k=10, L=192, **autotune.search_kwargs(best["params"], {}))
 """
 from __future__ import annotations
 
-import itertools
 import json
 import os
 
 SPACE = {
-    "delay": (0, 1),
+    "delay": (0, 1, 2, 3),
+    "beam_width": (1, 2, 4),
     "waves_per_block": (1, 2, 4),
     "hash_bits": (8, 9, 10, 11, 12),
     "persistent": (False, True),
 }
+DEFAULT = {"delay": 1, "beam_width": 1, "waves_per_block": 4, "hash_bits": 10,
+           "persistent": False}
+SEMANTIC = ("delay", "beam_width")
+MAX_IN_FLIGHT = 8   # (delay + 1) * beam_width limit of the kernels
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "flashann", "autotune.json")
 
@@ -32,33 +46,59 @@ def _bucket(x: int) -> int:
     return b
 
 
-def cache_key(index, L: int, nq: int) -> str:
+def cache_key(index, L: int, nq: int, uneven: bool = False) -> str:
     info = index.info()
-    return "dt%d-d%d-R%d-tier%d-L%d-nq%d" % (info["dtype"], info["d"], info["R"], info["tier"],
-                                            _bucket(L), _bucket(nq))
+    return "dt%d-d%d-R%d-tier%d-L%d-nq%d%s" % (info["dtype"], info["d"], info["R"], info["tier"],
+                                              _bucket(L), _bucket(nq), "-uneven" if uneven else "")
 
 
-def measure(index, queries, k, L, params, reps=3, **extra):
-    """Mean milliseconds per launch over `reps` launches (HIP events)."""
+def valid(params) -> bool:
+    return (params.get("delay", 1) + 1) * params.get("beam_width", 1) <= MAX_IN_FLIGHT
+
+
+def search_kwargs(params, extra):
+    """fa.search keyword arguments of a tuned setting: `longest_first` turns
+    into a processing order sorted by decreasing per-query L."""
+    import torch
+
+    p = dict(params)
+    kw = dict(extra)
+    if p.pop("longest_first", False) and kw.get("L_per_query") is not None:
+        kw["order"] = torch.argsort(kw["L_per_query"], descending=True, stable=True).to(torch.int32)
+    kw.update(p)
+    return kw
+
+
+def measure(index, queries, k, L, params, reps=3, score=None, **extra):
+    """Mean milliseconds per launch over `reps` launches (HIP events on the
+    launch stream) and, if `score` is given, score(ids, dists, steps) of the
+    warm-up launch."""
     import torch
 
     import paper_2507_10070_amd as fa
 
+    kw = search_kwargs(params, extra)
+    params, extra = {}, kw
     st = torch.cuda.current_stream(queries.device)
-    fa.search(index, queries, k=k, L=L, stream=st, **params, **extra)  # warm-up
+    out = fa.search(index, queries, k=k, L=L, stream=st, **params, **extra)  # warm-up
+    q = score(*out) if score is not None else None
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(st)
     for _ in range(reps):
         fa.search(index, queries, k=k, L=L, stream=st, **params, **extra)
     e1.record(st)
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / reps
+    return e0.elapsed_time(e1) / reps, q
 
 
 def tune(index, queries, k, L, space=None, reps=3, cache_path=DEFAULT_CACHE, use_cache=True,
-         **extra):
-    """Try every combination of `space`; return {"params", "ms", "table", "key"}."""
-    key = cache_key(index, L, queries.shape[0])
+         score=None, score_slack=0.001, passes=2, start=None, **extra):
+    """Coordinate descent over `space` from `start` (default DEFAULT).
+    Returns {"params", "ms", "score", "key", "table"}; `table` lists every
+    setting tried with its time and score (None where the launch failed,
+    e.g. a tile whose LDS need exceeds the CU)."""
+    uneven = extra.get("L_per_query") is not None or extra.get("k_per_query") is not None
+    key = cache_key(index, L, queries.shape[0], uneven)
     cache = {}
     if cache_path and os.path.exists(cache_path):
         try:
@@ -68,20 +108,52 @@ def tune(index, queries, k, L, space=None, reps=3, cache_path=DEFAULT_CACHE, use
             cache = {}
     if use_cache and key in cache:
         return cache[key]
-    space = space or SPACE
-    names = sorted(space)
-    table = []
-    for combo in itertools.product(*(space[n] for n in names)):
-        params = dict(zip(names, combo))
-        try:
-            ms = measure(index, queries, k, L, params, reps=reps, **extra)
-        except Exception as e:  # e.g. a tile whose LDS need exceeds the CU
-            table.append({"params": params, "ms": None, "error": str(e)})
-            continue
-        table.append({"params": params, "ms": round(ms, 4)})
-    ok = [r for r in table if r["ms"] is not None]
-    best = min(ok, key=lambda r: r["ms"])
-    res = {"params": best["params"], "ms": best["ms"], "key": key, "table": table}
+    space = dict(space or SPACE)
+    if uneven and extra.get("order") is None:
+        space.setdefault("longest_first", (False, True))
+    cur = dict(start or DEFAULT)
+    cur = {n: cur.get(n, DEFAULT.get(n, space[n][0])) for n in space}
+    if score is None:  # no quality measure: results-neutral parameters only
+        for n in SEMANTIC:
+            if n in space:
+                space[n] = (cur[n],)
+    seen = {}
+
+    def run(p):
+        t = tuple(sorted(p.items()))
+        if t not in seen:
+            try:
+                ms, q = measure(index, queries, k, L, p, reps=reps, score=score, **extra)
+                seen[t] = {"params": dict(p), "ms": round(ms, 4), "score": q}
+            except Exception as e:  # noqa: BLE001 -- recorded, setting skipped
+                seen[t] = {"params": dict(p), "ms": None, "score": None, "error": str(e)}
+        return seen[t]
+
+    base = run(cur)
+    if base["ms"] is None:
+        raise RuntimeError("the starting setting failed: %s" % base.get("error"))
+    floor = None if score is None else base["score"] - score_slack
+
+    def admissible(r):
+        return r["ms"] is not None and (floor is None or r["score"] >= floor)
+
+    best = base
+    for _ in range(passes):
+        changed = False
+        for name in sorted(space):
+            for v in space[name]:
+                p = dict(best["params"])
+                p[name] = v
+                if not valid(p):
+                    continue
+                r = run(p)
+                if admissible(r) and r["ms"] < best["ms"]:
+                    best, changed = r, True
+        if not changed:
+            break
+    res = {"params": best["params"], "ms": best["ms"], "score": best["score"], "key": key,
+           "default": {"params": base["params"], "ms": base["ms"], "score": base["score"]},
+           "table": list(seen.values())}
     if cache_path:
         cache[key] = res
         os.makedirs(os.path.dirname(cache_path), exist_ok=True)
