@@ -389,33 +389,52 @@ def main():
 
         transports = {}
 
-        def measure(index, qsub, L, delay, reps):
+        def measure(index, qsub, L, delay, reps, **kw):
             outs = (torch.empty((qsub.shape[0], k), dtype=torch.int32, device=dev),
                     torch.empty((qsub.shape[0], k), dtype=torch.int32, device=dev),
                     torch.empty((qsub.shape[0],), dtype=torch.int32, device=dev))
-            fa.search(index, qsub, k=k, L=L, delay=delay, transport=fa.TRANSPORT_AGENT, out=outs)
             times = torch.zeros((qsub.shape[0], 2), dtype=torch.int64, device=dev)
             fa.search(index, qsub, k=k, L=L, delay=delay, transport=fa.TRANSPORT_AGENT, out=outs,
-                      times=times)
+                      times=times, **kw)
             tt = times.cpu().numpy()
             lat = (tt[:, 1] - tt[:, 0]) / khz
             t = time.perf_counter()
             for _ in range(reps):
                 fa.search(index, qsub, k=k, L=L, delay=delay, transport=fa.TRANSPORT_AGENT,
-                          out=outs)
+                          out=outs, **kw)
             el = (time.perf_counter() - t) / reps
             return {"qps": round(qsub.shape[0] / el, 1), "ms_per_step": round(el * 1e3, 3),
-                    "query_latency_ms_p50": float(np.percentile(lat, 50)),
-                    "query_latency_ms_p99": float(np.percentile(lat, 99))}
+                    "query_latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
+                    "query_latency_ms_p99": round(float(np.percentile(lat, 99)), 3)}
+
+        # query-grained (each query waits for its own records; relaxed and
+        # strict) against kernel-grained (lockstep rounds, strict)
+        modes = (("relaxed", 1, {}), ("strict", 0, {}),
+                 ("kernel_grained", 0, {"sync_grain": fa.SYNC_KERNEL}))
+
+        def compare(index, qsub, reps, rounds):
+            res = {m: [] for m, _, _ in modes}
+            for _ in range(rounds):  # alternate the modes so drift hits all alike
+                for m, delay, kw in modes:
+                    res[m].append(measure(index, qsub, op[1], delay, reps, **kw))
+            out = {}
+            for m, rows in res.items():
+                out[m] = {key: round(float(np.mean([r[key] for r in rows])), 3) for key in rows[0]}
+            return out
 
         if tier == fa.TIER_HOST:
-            reps = max(1, min(args.steps, 5))
-            transports["agent_host"] = {"queries": nq, "L": op[1],
-                                        "relaxed": measure(ix, qd, op[1], 1, reps),
-                                        "strict": measure(ix, qd, op[1], 0, reps)}
+            reps = max(1, min(args.steps, 3))
+            transports["agent_host"] = {"queries": nq, "L": op[1], **compare(ix, qd, reps, 1)}
             st = ix.agent_stats()
             transports["agent_host"]["agent_threads_requests"] = st["requests"]
             log("agent transport: %s" % transports["agent_host"])
+            kg = timed(op[1], 0, 3, 1, sync_grain=fa.SYNC_KERNEL)
+            transports["direct_host"] = {
+                "queries": nq, "L": op[1],
+                "relaxed": {"qps": round(nq / (ms[1] / 1e3), 1)},
+                "strict": {"qps": round(nq / (ms_equal_L / 1e3), 1)},
+                "kernel_grained": {"qps": round(nq / (kg / 1e3), 1)}}
+            log("direct transport: %s" % transports["direct_host"])
         tmpd = tempfile.mkdtemp(prefix="flashann_", dir=os.environ.get("TMPDIR", "/tmp"))
         try:
             t = time.time()
@@ -424,10 +443,9 @@ def main():
             fix = fa.Index.load(tmpd, fa.TIER_FILE)
             mq = min(args.file_queries, nq)
             qsub = qd[:mq].contiguous()
+            fa.search(fix, qsub, k=k, L=op[1])  # warm-up pass
             transports["file"] = {"queries": mq, "L": op[1], "direct_io": fix.info()["direct_io"],
-                                  "write_s": round(t_save, 1),
-                                  "relaxed": measure(fix, qsub, op[1], 1, 1),
-                                  "strict": measure(fix, qsub, op[1], 0, 1)}
+                                  "write_s": round(t_save, 1), **compare(fix, qsub, 1, 2)}
             fix.close()
             log("file tier: %s" % transports["file"])
         finally:

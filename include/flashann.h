@@ -122,6 +122,17 @@ typedef struct {
                               done, so long and short searches share the kernel.
                               Persistent searches on one index must be ordered
                               (one stream or synchronised). */
+  int32_t sync_grain;      /* 0: query-grained (default): each query waits only
+                              for its own records (section 4.2).  1: kernel-
+                              grained, the comparison point of section 4.2: the
+                              queries resident on the GPU advance one strict step
+                              per round in lockstep, with a grid-wide barrier
+                              once every record of the round is in and another
+                              after the compute.  Needs delay 0, beam_width 1,
+                              no persistent, d_order or d_phases; synchronous;
+                              results equal the strict search.  spin_limit
+                              bounds each barrier wait (0 = 2^24 polls), else
+                              ANN_ETIMEDOUT. */
 } ann_search_opts;
 
 /*

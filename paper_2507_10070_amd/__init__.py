@@ -8,4 +8,5 @@ raises if the library has not been built.
 from .flashann import (ANN_ERRORS, AnnError, Index, SearchGraph, SearchOptions,  # noqa: F401
                        Server, clock_us, load_library, search,
                        build_index, save_index, device_clock_khz, DTYPE_CODES, TIER_HBM,
-                       TIER_HOST, TIER_FILE, TRANSPORT_AUTO, TRANSPORT_DIRECT, TRANSPORT_AGENT)
+                       TIER_HOST, TIER_FILE, TRANSPORT_AUTO, TRANSPORT_DIRECT, TRANSPORT_AGENT,
+                       SYNC_QUERY, SYNC_KERNEL)

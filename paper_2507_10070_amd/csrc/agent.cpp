@@ -83,6 +83,7 @@ void Agent::run(int t) {
   uint8_t *bounce = nullptr;
   if (direct_ && posix_memalign((void **)&bounce, 4096, (size_t)io_bytes_ + 4096) != 0)
     bounce = nullptr;
+  uint32_t idle = 0;
   while (!quit_.load(std::memory_order_relaxed)) {
     // Announce the pass before checking armed_: disarm() stores armed_ then
     // waits for busy_ to drain, so a pass either sees armed_ == false or is
@@ -108,7 +109,15 @@ void Agent::run(int t) {
       done_[(size_t)q] = d;
     }
     busy_.fetch_sub(1);
-    if (!any) cpu_relax();
+    // Idle passes spin briefly, then yield: file agents outnumber the cores,
+    // and a spinning thread must not keep one with a read to issue waiting.
+    if (any) {
+      idle = 0;
+    } else if (++idle < 64) {
+      cpu_relax();
+    } else {
+      std::this_thread::yield();
+    }
   }
   std::free(bounce);
 }

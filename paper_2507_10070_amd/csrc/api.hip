@@ -54,6 +54,7 @@ struct ann_index {
   int64_t tcap = 0, stage_stride = 0;
   int32_t tslots = 0;               // staging slots per query
   uint32_t *d_work = nullptr;       // persistent launches: device work counter
+  uint32_t *d_ctl = nullptr;        // kernel-grained launches: barrier state (16 u32)
 };
 
 struct ann_graph {
@@ -104,6 +105,7 @@ void release(ann_index *ix) {
   if (!ix) return;
   free_transport(ix);
   if (ix->d_work) (void)hipFree(ix->d_work);
+  if (ix->d_ctl) (void)hipFree(ix->d_ctl);
   if (ix->nav) (void)hipFree(ix->nav);
   if (ix->rec_hbm) (void)hipFree(ix->rec_hbm);
   if (ix->rec_host) (void)hipHostFree(ix->rec_host);
@@ -299,11 +301,19 @@ bool meta_dtype(const std::string &s, int32_t *out) {
   return *out != 0;
 }
 
+// Flush a written file to the device before closing it: an index file is
+// then durable, and reads of it never compete with its own write-back.
+bool sync_close(FILE *f) {
+  bool ok = std::fflush(f) == 0;
+  ok = fsync(fileno(f)) == 0 && ok;
+  return std::fclose(f) == 0 && ok;
+}
+
 int write_all(const std::string &path, const void *p, int64_t bytes) {
   FILE *f = std::fopen(path.c_str(), "wb");
   if (!f) return fail(ANN_EIO, "cannot create %s: %s", path.c_str(), std::strerror(errno));
   const bool ok = bytes == 0 || std::fwrite(p, 1, (size_t)bytes, f) == (size_t)bytes;
-  if (std::fclose(f) != 0 || !ok) return fail(ANN_EIO, "write of %s failed", path.c_str());
+  if (!sync_close(f) || !ok) return fail(ANN_EIO, "write of %s failed", path.c_str());
   return ANN_OK;
 }
 
@@ -372,7 +382,7 @@ int ann_save_index(const char *dir, const void *vectors, const int32_t *adjacenc
     const size_t bytes = (size_t)((i1 - i0) * slot_bytes);
     ok = std::fwrite(buf.data(), 1, bytes, f) == bytes;
   }
-  if (std::fclose(f) != 0 || !ok) return fail(ANN_EIO, "write of records.bin failed");
+  if (!sync_close(f) || !ok) return fail(ANN_EIO, "write of records.bin failed");
   return ANN_OK;
 }
 
@@ -506,6 +516,16 @@ int ann_agent_stats(const ann_index *ix, uint64_t *requests, uint64_t *bytes, ui
 
 namespace {
 
+// Waits for a kernel-grained search and reports an abandoned barrier wait.
+int check_lockstep(ann_index *ix, hipStream_t st) {
+  uint32_t flag = 0;
+  hipError_t e = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = hipMemcpy(&flag, ix->d_ctl + 4, sizeof(flag), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "kernel-grained search");
+  if (flag) return fail(ANN_ETIMEDOUT, "a grid barrier wait exceeded spin_limit; results invalid");
+  return ANN_OK;
+}
+
 // Validates a search and fills the kernel arguments.  Returns ANN_OK with
 // *empty set when there is nothing to launch (nq == 0).
 int prepare_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int32_t L,
@@ -546,6 +566,11 @@ int prepare_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, 
   if (transport == ANN_TRANSPORT_AGENT && ix->tier == ANN_TIER_HBM)
     return fail(ANN_EINVAL, "HBM records are read directly by the kernel");
   if (o.persistent != 0 && o.persistent != 1) return fail(ANN_EINVAL, "persistent=%d", o.persistent);
+  if (o.sync_grain != 0 && o.sync_grain != 1) return fail(ANN_EINVAL, "sync_grain=%d", o.sync_grain);
+  if (o.sync_grain == 1 && (o.delay != 0 || o.beam_width != 1 || o.persistent || o.d_order ||
+                            o.d_phases))
+    return fail(ANN_EINVAL, "kernel-grained search runs the strict schedule (delay 0, beam 1) "
+                            "without persistent waves, order or phase times");
   if (nq > 0x7FFFFFFFll) return fail(ANN_EINVAL, "nq=%lld too large", (long long)nq);
   *o_out = o;
   *transport_out = transport;
@@ -557,6 +582,10 @@ int prepare_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, 
   if (o.persistent && !ix->d_work) {
     hipError_t e = hipMalloc(&ix->d_work, sizeof(uint32_t));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(work counter)");
+  }
+  if (o.sync_grain && !ix->d_ctl) {
+    hipError_t e = hipMalloc(&ix->d_ctl, fa::kLockstepCtlWords * sizeof(uint32_t));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(barrier state)");
   }
 
   fa::SearchArgs &a = *args;
@@ -607,6 +636,12 @@ int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int3
                           &transport, &a, &empty);
   if (rc || empty) return rc;
   hipStream_t st = (hipStream_t)hip_stream;
+  if (o.sync_grain) a.spin_limit = o.spin_limit ? o.spin_limit : (1u << 24);
+  if (transport == ANN_TRANSPORT_DIRECT && o.sync_grain) {
+    hipError_t e = fa::launch_lockstep(a, ix->d_ctl, ix->dtype, fa::TR_DIRECT, o.waves_per_block, st);
+    if (e != hipSuccess) return hip_fail(e, "kernel-grained search launch");
+    return check_lockstep(ix, st);
+  }
   if (transport == ANN_TRANSPORT_DIRECT) {
     hipError_t e = hipSuccess;
     if (o.persistent) e = fa::launch_reset(ix->d_work, st);
@@ -639,12 +674,15 @@ int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int3
   ix->agent->arm(ix->req, ix->cpl, ix->stage, nq, ix->stage_stride, a.pslots);
   if (o.persistent) e = fa::launch_reset(ix->d_work, st);
   if (e == hipSuccess)
-    e = fa::launch_search(a, ix->dtype, fa::TR_AGENT, o.waves_per_block,
-                          o.persistent != 0, st);
+    e = o.sync_grain ? fa::launch_lockstep(a, ix->d_ctl, ix->dtype, fa::TR_AGENT,
+                                           o.waves_per_block, st)
+                     : fa::launch_search(a, ix->dtype, fa::TR_AGENT, o.waves_per_block,
+                                         o.persistent != 0, st);
   const hipError_t es = e == hipSuccess ? hipStreamSynchronize(st) : e;
   ix->agent->disarm();
   if (e != hipSuccess) return hip_fail(e, "search launch");
   if (es != hipSuccess) return hip_fail(es, "search");
+  if (o.sync_grain && (rc = check_lockstep(ix, st)) != ANN_OK) return rc;
   std::vector<int32_t> status((size_t)nq);
   if ((e = hipMemcpy(status.data(), ix->d_status, sizeof(int32_t) * nq, hipMemcpyDeviceToHost)) !=
       hipSuccess)
@@ -689,6 +727,7 @@ int ann_search_graph(ann_index *ix, const void *d_queries, int64_t nq, int32_t k
   if (empty) return fail(ANN_EINVAL, "nothing to capture (nq == 0)");
   if (transport != ANN_TRANSPORT_DIRECT)
     return fail(ANN_EINVAL, "graphs capture the DIRECT transport only");
+  if (o.sync_grain) return fail(ANN_EINVAL, "graphs capture query-grained searches only");
   hipStream_t st = (hipStream_t)hip_stream;
   ann_graph *g = new (std::nothrow) ann_graph();
   if (!g) return fail(ANN_ENOMEM, "graph handle");

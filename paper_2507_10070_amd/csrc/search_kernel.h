@@ -85,6 +85,16 @@ hipError_t launch_server(const ServerArgs &a, int dtype, int delay, int waves_pe
 // for beam 1 and delay <= 1, the generic FIFO kernel otherwise.
 hipError_t launch_search(const SearchArgs &a, int dtype, int transport, int waves_per_block,
                          bool persistent, hipStream_t st);
+// Kernel-grained synchronisation (ablation): a cooperative grid advances
+// groups of co-resident queries one strict step per round, with grid-wide
+// barriers after the record fetches and after the compute.  `ctl` is
+// kLockstepCtlWords u32 of device memory (zeroed here by a kernel); ctl[4] != 0
+// afterwards means a barrier wait exceeded a.spin_limit polls and the search
+// was abandoned.  The grid has at most kLockstepGroups groups of 32 blocks.
+constexpr int kLockstepGroups = 256;
+constexpr int kLockstepCtlWords = 16 + 16 * kLockstepGroups;
+hipError_t launch_lockstep(const SearchArgs &a, uint32_t *ctl, int dtype, int transport,
+                           int waves_per_block, hipStream_t st);
 // Zero the persistent work counter (a kernel, so that it can be captured in a
 // graph).
 hipError_t launch_reset(uint32_t *work, hipStream_t st);

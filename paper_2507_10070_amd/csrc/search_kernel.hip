@@ -783,6 +783,151 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs A) {
 
 __global__ void reset_work(uint32_t *work) { *work = 0u; }
 
+// ------------------------------------------------------- kernel-grained sync
+// The alternative the paper's query-grained I/O (section 4.2) is measured
+// against: synchronisation at the granularity of the whole batch.  The waves
+// of a co-resident (cooperative) grid take G queries at a time and advance
+// them in lockstep, one strict step per round: every live query selects its
+// node and obtains the record; a grid-wide barrier waits until every record
+// of the round is in; every query scores and merges; a second barrier ends
+// the round.  A query never waits for its own I/O alone but for the slowest
+// of the round, and no query's compute overlaps another's I/O.  Results equal
+// the strict schedule.
+//
+// ctl (device, zeroed before launch): [0] arrivals, [1] barrier generation,
+// [2], [3] live queries of even / odd rounds, [4] failure flag.
+
+// Wait until every memory operation the wave has issued has completed, so
+// that relaxed device-scope atomics issued before it are performed before
+// any issued after it (vmcnt counts stores and atomics on this architecture).
+__device__ __forceinline__ void drain_memory() {
+  __builtin_amdgcn_sched_barrier(0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// Grid barrier, two levels deep so that no counter takes more than 32
+// arrivals: the waves of a block meet at the block barrier, the block's
+// first thread adds the block's live queries (when `count`) to the round's
+// counter, arrives at its group's counter (32 blocks per group), and the last
+// block of each group arrives at the root; the last group advances the
+// generation that every block leader polls.  A counter update is complete
+// before the arrival that follows it, and a counter is reset before the
+// arrival above it, so a block released by the new generation sees all of
+// them.  Returns false (for the whole block) once any block gave up: a spin
+// limit of polls bounds every wait.
+constexpr int kBarrierGroup = 32;
+
+__device__ __forceinline__ bool grid_sync(uint32_t *ctl, uint32_t nblocks, uint32_t spin_limit,
+                                          bool count, bool live, uint32_t par) {
+  __shared__ uint32_t s_live[4];
+  __shared__ uint32_t s_ok;
+  const int wave = threadIdx.x >> 6;
+  if (lane_id() == 0) s_live[wave] = live ? 1u : 0u;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t ok = 1;
+    if (count) {
+      uint32_t n = 0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); w++) n += s_live[w];
+      if (n) __hip_atomic_fetch_add(ctl + 2 + par, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    drain_memory();
+    const uint32_t gen = __hip_atomic_load(ctl + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    drain_memory();  // the generation is read before this block's arrival counts
+    const uint32_t grp = blockIdx.x / kBarrierGroup;
+    const uint32_t gsize = min((uint32_t)kBarrierGroup, nblocks - grp * kBarrierGroup);
+    const uint32_t ngroups = (nblocks + kBarrierGroup - 1) / kBarrierGroup;
+    uint32_t *gc = ctl + 16 + 16 * grp;  // one 64 B line per group
+    bool wait = true;
+    if (__hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u == gsize) {
+      __hip_atomic_store(gc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      drain_memory();
+      if (__hip_atomic_fetch_add(ctl, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u ==
+          ngroups) {
+        __hip_atomic_store(ctl, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        drain_memory();
+        __hip_atomic_fetch_add(ctl + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        wait = false;
+      }
+    }
+    if (wait) {
+      uint32_t spins = 0;
+      while (__hip_atomic_load(ctl + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        if (__hip_atomic_load(ctl + 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          ok = 0;
+          break;
+        }
+        if (++spins > spin_limit) {
+          __hip_atomic_store(ctl + 4, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(4);
+      }
+    }
+    s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+template <int DT, int CPL, int TR>
+__global__ void __launch_bounds__(256) lockstep_kernel(SearchArgs A, uint32_t *ctl) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int wave = threadIdx.x >> 6;
+  uint8_t *lds = smem + (size_t)wave * A.lds_per_wave;
+  const uint32_t G = gridDim.x * (blockDim.x >> 6);
+  const uint32_t gw = blockIdx.x * (blockDim.x >> 6) + wave;
+  const uint32_t spin = A.spin_limit;
+  uint32_t round = 0;
+  for (int64_t base = 0; base < A.nq; base += G) {
+    const int64_t qi = base + gw;
+    const bool mine = qi < A.nq;
+    const int64_t qx = mine ? qi : base;  // waves without a query only keep step
+    const unsigned long long t_start = A.times ? __builtin_amdgcn_s_memrealtime() : 0ull;
+    Searcher<DT, CPL, TR> s(A, lds, qx, batch_io(A, qx));
+    s.init_entry();
+    bool live = mine;
+    for (;; round++) {
+      const uint32_t par = round & 1u;
+      uint64_t v = kNoKey;
+      if (live) {
+        v = s.select();
+        live = v != kNoKey;
+      }
+      if (live && !s.stage(s.issue((uint32_t)v & ~kFlag, true))) live = false;
+      if (!grid_sync(ctl, gridDim.x, spin, false, false, par)) return;
+      // every record of the round is in LDS; the other parity's live count
+      // was read by every wave before its block arrived here
+      if (gw == 0 && s.lane == 0)
+        __hip_atomic_store(ctl + 2 + (par ^ 1u), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (live) {
+        uint4 unused;
+        s.template process_staged<false>(v, 0u, false, unused);
+      }
+      if (!grid_sync(ctl, gridDim.x, spin, true, live, par)) return;
+      const uint32_t nlive =
+          __hip_atomic_load(ctl + 2 + par, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (nlive == 0) {
+        round++;
+        break;
+      }
+    }
+    if (mine) {
+      s.finish_query();
+      if (A.times && s.lane == 0) {
+        A.times[2 * qi] = t_start;
+        A.times[2 * qi + 1] = __builtin_amdgcn_s_memrealtime();
+      }
+    }
+  }
+}
+
+__global__ void reset_ctl(uint32_t *ctl, uint32_t words) {
+  for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) ctl[i] = 0u;
+}
+
 // Continuous-batching server.  Waves take ring indices as tickets from one
 // counter and serve each once the host has published it; a wave that leaves
 // while idle holds no ticket (see the claim loop).  The entry is read with
@@ -915,6 +1060,62 @@ static hipError_t launch_c(const SearchArgs &a, int cpl, int tr, int wpb, bool p
     case 2: return launch_tr<DT, 2>(a, tr, wpb, pers, st);
     case 3: return launch_tr<DT, 3>(a, tr, wpb, pers, st);
     case 4: return launch_tr<DT, 4>(a, tr, wpb, pers, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int DT, int CPL, int TR>
+static hipError_t launch_lockstep_t(const SearchArgs &a, uint32_t *ctl, int wpb, hipStream_t st) {
+  const size_t lds = (size_t)a.lds_per_wave * wpb;
+  const int threads = 64 * wpb;
+  const void *fn = (const void *)lockstep_kernel<DT, CPL, TR>;
+  int per_cu = 0, dev = 0, cus = 0, coop = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
+  if (e != hipSuccess) return e;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return e;
+  if ((e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev)) != hipSuccess)
+    return e;
+  if (!coop || per_cu < 1) return hipErrorNotSupported;
+  int64_t blocks = (int64_t)per_cu * cus;
+  const int64_t need = (a.nq + wpb - 1) / wpb;
+  if (blocks > need) blocks = need;
+  if (blocks > (int64_t)kLockstepGroups * kBarrierGroup) blocks = (int64_t)kLockstepGroups * kBarrierGroup;
+  hipLaunchKernelGGL(reset_ctl, dim3(1), dim3(256), 0, st, ctl, (uint32_t)kLockstepCtlWords);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  SearchArgs args = a;
+  uint32_t *c = ctl;
+  void *params[] = {(void *)&args, (void *)&c};
+  // a cooperative launch fails instead of starting a grid whose waves could
+  // not all be resident at once, so the barriers cannot wait for an absent wave
+  return hipLaunchCooperativeKernel(fn, dim3((unsigned)blocks), dim3(threads), params,
+                                    (unsigned)lds, st);
+}
+
+template <int DT>
+static hipError_t launch_lockstep_c(const SearchArgs &a, uint32_t *ctl, int tr, int wpb,
+                                    hipStream_t st) {
+  const int cpl = a.nav_stride / 128;
+#define FA_LS(C)                                                               \
+  return tr == TR_DIRECT ? launch_lockstep_t<DT, C, TR_DIRECT>(a, ctl, wpb, st) \
+                         : launch_lockstep_t<DT, C, TR_AGENT>(a, ctl, wpb, st)
+  switch (cpl) {
+    case 1: FA_LS(1);
+    case 2: FA_LS(2);
+    case 3: FA_LS(3);
+    case 4: FA_LS(4);
+    default: return hipErrorInvalidValue;
+  }
+#undef FA_LS
+}
+
+hipError_t launch_lockstep(const SearchArgs &a, uint32_t *ctl, int dtype, int transport,
+                           int waves_per_block, hipStream_t st) {
+  switch (dtype) {
+    case DT_U8: return launch_lockstep_c<DT_U8>(a, ctl, transport, waves_per_block, st);
+    case DT_I8: return launch_lockstep_c<DT_I8>(a, ctl, transport, waves_per_block, st);
+    case DT_F32: return launch_lockstep_c<DT_F32>(a, ctl, transport, waves_per_block, st);
     default: return hipErrorInvalidValue;
   }
 }

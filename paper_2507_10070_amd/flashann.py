@@ -19,6 +19,7 @@ DTYPE_CODES = {np.dtype(np.uint8): 1, np.dtype(np.int8): 2, np.dtype(np.float32)
 TIER_HBM, TIER_HOST, TIER_FILE = 0, 1, 2
 
 TRANSPORT_AUTO, TRANSPORT_DIRECT, TRANSPORT_AGENT = 0, 1, 2
+SYNC_QUERY, SYNC_KERNEL = 0, 1
 
 EXPORTED = ["ann_index_create", "ann_index_info_get", "ann_search", "ann_index_free",
             "ann_last_error", "ann_device_clock_khz", "ann_save_index", "ann_build_index",
@@ -42,7 +43,7 @@ class SearchOptions(ctypes.Structure):
                 ("d_phases", ctypes.c_void_p), ("transport", ctypes.c_int32),
                 ("spin_limit", ctypes.c_uint32), ("d_L", ctypes.c_void_p),
                 ("d_k", ctypes.c_void_p), ("d_order", ctypes.c_void_p),
-                ("persistent", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("sync_grain", ctypes.c_int32)]
 
 
 class IndexInfo(ctypes.Structure):
@@ -250,7 +251,7 @@ def _ptr(t):
 
 def _prepare(index, queries, k, L, R, delay, beam_width, hash_bits, waves_per_block, stats,
              trace, times, phases, transport, spin_limit, L_per_query, k_per_query, order,
-             persistent, out):
+             persistent, out, sync_grain=0):
     import torch
 
     if queries.dim() != 2 or queries.shape[1] != index.d:
@@ -275,7 +276,7 @@ def _prepare(index, queries, k, L, R, delay, beam_width, hash_bits, waves_per_bl
     opts = SearchOptions(delay, beam_width, hash_bits, waves_per_block, _ptr(stats), _ptr(trace),
                          trace.shape[1] if trace is not None else 0, _ptr(times), _ptr(phases),
                          transport, spin_limit, _ptr(L_per_query), _ptr(k_per_query), _ptr(order),
-                         1 if persistent else 0)
+                         1 if persistent else 0, int(sync_grain))
     return nq, ids, dists, steps, opts
 
 
@@ -283,7 +284,7 @@ def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
            beam_width: int = 1, hash_bits: int = 0, waves_per_block: int = 0, stats=None,
            trace=None, times=None, phases=None, transport: int = TRANSPORT_AUTO,
            spin_limit: int = 0, L_per_query=None, k_per_query=None, order=None,
-           persistent: bool = False, stream=None, out=None):
+           persistent: bool = False, stream=None, out=None, sync_grain: int = SYNC_QUERY):
     """ann_search on torch CUDA tensors.
 
     queries: [nq, d] device tensor of the index dtype (uint8/int8/float32).
@@ -294,6 +295,8 @@ def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
     compute ticks per query;
     L_per_query / k_per_query / order: optional int32 device tensors [nq]
     (uneven batches; L and k are then the batch maxima).
+    sync_grain: SYNC_QUERY (default) or SYNC_KERNEL (lockstep rounds with
+    grid-wide barriers; strict schedule only).
     Returns (ids int32 [nq,k], dists [nq,k] int32-viewed uint32 or float32,
     steps int32-viewed uint32 [nq]), all on the device.
     """
@@ -302,7 +305,7 @@ def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
     nq, ids, dists, steps, opts = _prepare(index, queries, k, L, R, delay, beam_width, hash_bits,
                                            waves_per_block, stats, trace, times, phases,
                                            transport, spin_limit, L_per_query, k_per_query,
-                                           order, persistent, out)
+                                           order, persistent, out, sync_grain)
     st = stream if stream is not None else torch.cuda.current_stream(queries.device)
     _check(load_library().ann_search(index.handle, queries.data_ptr(), nq, k, L, R,
                                      ctypes.byref(opts), ids.data_ptr(), dists.data_ptr(),

@@ -36,3 +36,38 @@ def test_binding_lists_match_header():
     from paper_2507_10070_amd import flashann
 
     assert sorted(flashann.EXPORTED) == declared_functions()
+
+
+STRUCTS = {"ann_search_opts": "SearchOptions", "ann_index_info": "IndexInfo",
+           "ann_server_opts": "ServerOptions", "ann_result": "Result",
+           "ann_server_stats": "ServerStats"}
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every struct of the header has the size and field offsets of its
+    ctypes mirror (gcc compiles the header and prints them)."""
+    import subprocess
+
+    from paper_2507_10070_amd import flashann
+
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "flashann.h"',
+             "int main(void) {"]
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(flashann, pyname)
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in cls._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = dict(line.rsplit(" ", 1) for line in
+               subprocess.run([str(exe)], check=True, capture_output=True, text=True)
+               .stdout.splitlines())
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(flashann, pyname)
+        assert int(out["%s size" % cname]) == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert int(out["%s.%s" % (cname, fname)]) == getattr(cls, fname).offset, (cname, fname)

@@ -314,3 +314,46 @@ def test_generic_exhaustive_equals_bruteforce():
             np.testing.assert_array_equal(g["ids"], bf_ids)
             np.testing.assert_array_equal(g["dists"].astype(np.float64), bf_d)
             assert (g["steps"] == 200).all()
+
+
+# Kernel-grained synchronisation (lockstep rounds with grid barriers): the
+# strict search's results, for one partial group of queries and for several
+# groups of co-resident queries.
+@pytest.mark.parametrize("tier", ["hbm", "host"])
+def test_kernel_grained_parity(cfg1, tier):
+    base, q, adj, entry = cfg1
+    t = fa.TIER_HBM if tier == "hbm" else fa.TIER_HOST
+    ref = oracle.search(base, adj, entry, q, 10, 64, delay=0, trace_cap=400)
+    with fa.Index(base, adj, entry, 256, t) as ix:
+        g = gpu_search(ix, q, 10, 64, delay=0, sync_grain=fa.SYNC_KERNEL, spin_limit=1 << 22,
+                       trace_cap=400)
+    assert_int_parity(g, ref, check_trace=True)
+
+
+def test_kernel_grained_many_groups(cfg1):
+    base, q, adj, entry = cfg1
+    rows = np.random.default_rng(3).integers(0, len(q), 20000)
+    qq = q[rows]
+    Ls = np.random.default_rng(4).choice(np.array([16, 40, 64], np.int32), len(qq))
+    ref = {L: oracle.search(base, adj, entry, q, 10, int(L), delay=0) for L in (16, 40, 64)}
+    with fa.Index(base, adj, entry, 256, fa.TIER_HOST) as ix:
+        for wpb in (1, 4):
+            g = gpu_search(ix, qq, 10, 64, delay=0, sync_grain=fa.SYNC_KERNEL, spin_limit=1 << 22,
+                           waves_per_block=wpb, L_per_query=torch.from_numpy(Ls).to(dev()))
+            for L in (16, 40, 64):
+                sel = Ls == L
+                sub = {key: ref[L][key][rows[sel]] for key in ("ids", "dists", "steps")}
+                assert_int_parity({key: g[key][sel] for key in ("ids", "dists", "steps")}, sub)
+
+
+def test_kernel_grained_validation(cfg1):
+    base, q, adj, entry = cfg1
+    qd = torch.from_numpy(q[:4]).to(dev())
+    with fa.Index(base, adj, entry, 256) as ix:
+        for kw in (dict(delay=1), dict(delay=0, beam_width=2), dict(delay=0, persistent=True)):
+            with pytest.raises(fa.flashann.AnnError) as e:
+                fa.search(ix, qd, k=5, L=16, sync_grain=fa.SYNC_KERNEL, **kw)
+            assert e.value.code == -22
+        with pytest.raises(fa.flashann.AnnError) as e:
+            fa.search(ix, qd, k=5, L=16, delay=0, sync_grain=2)
+        assert e.value.code == -22

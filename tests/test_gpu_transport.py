@@ -195,3 +195,22 @@ def test_agent_deep_pipeline_faults(cfg1):
         g["ids"] = ids.cpu().numpy()
         assert (g["ids"][hit] == -1).all()
         np.testing.assert_array_equal(g["ids"][~hit], ref["ids"][~hit])
+
+
+def test_kernel_grained_agent_parity(cfg1, tmp_path):
+    """Kernel-grained rounds over the agent transport (host DRAM and file):
+    each round's requests all complete before any query computes; results
+    equal the strict search."""
+    base, q, adj, entry = cfg1
+    ref = oracle.search(base, adj, entry, q, 10, 64, delay=0, trace_cap=400)
+    with fa.Index(base, adj, entry, 256, fa.TIER_HOST) as ix:
+        ix.configure_agent(threads=4)
+        g = run(ix, q, 10, 64, delay=0, transport=fa.TRANSPORT_AGENT,
+                sync_grain=fa.SYNC_KERNEL, spin_limit=1 << 22, trace_cap=400)
+        assert_same(g, ref)
+        np.testing.assert_array_equal(g["trace"], ref["trace"])
+    d = str(tmp_path / "ix")
+    fa.save_index(d, base, adj, entry, 512)
+    with fa.Index.load(d, fa.TIER_FILE) as fix:
+        assert_same(run(fix, q, 10, 64, delay=0, sync_grain=fa.SYNC_KERNEL,
+                        spin_limit=1 << 22), ref)
