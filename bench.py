@@ -60,6 +60,26 @@ def recall_at(dists_u32, kth):
     return float(hits.mean() / 10.0)
 
 
+def host_cpu():
+    """CPU model and SMT state of this host (for the CPU baseline)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    smt = None
+    try:
+        with open("/sys/devices/system/cpu/smt/active") as f:
+            smt = f.read().strip() == "1"
+    except OSError:
+        pass
+    return {"model": model, "smt": smt, "online": os.cpu_count()}
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in ("search_kernel.hip", "search_kernel.h"):
@@ -476,7 +496,7 @@ def main():
                 break
         el = time.time() - t
         cpu = {"value": round(passes * m / el, 1), "unit": "queries/s", "cores": thr,
-               "kind": "oracle",
+               "kind": "oracle", "cpu": host_cpu(),
                "sample": "%d passes over the first %d of the %d queries (%.1f s), L=%d, "
                          "delay 1, records in DRAM" % (passes, m, nq, el, op[1])}
         log("oracle: %d x %d queries in %.1fs on %d threads" % (passes, m, el, thr))
