@@ -25,8 +25,8 @@
 
 extern "C" int synth_build_graph(const void *base, int64_t n, int32_t d, int32_t dtype, int32_t R,
                                  uint64_t seed, int32_t threads, int32_t pool, float alpha,
-                                 int32_t n_hubs, int64_t exact_limit, int32_t *adj,
-                                 int32_t *entry_out);
+                                 int32_t n_hubs, int64_t exact_limit, int32_t passes,
+                                 int32_t Lb, int32_t *adj, int32_t *entry_out);
 
 static_assert(sizeof(fa::AgentRequest) == 64 && fa::kCplStride == 16,
               "request/completion layout shared with the kernel");
@@ -402,7 +402,8 @@ int ann_build_index(const void *vectors, int64_t n, int32_t d, int32_t dtype, in
   const int threads = std::max(1, std::min(64, (int)std::thread::hardware_concurrency()));
   const int64_t hubs = std::min<int64_t>(std::max<int64_t>(64, n / 1000), 4096);
   const int rc = synth_build_graph(vectors, n, d, dtype, R, seed, threads, std::max(2 * R, 64),
-                                   1.2f, (int32_t)hubs, 20000, adj.data(), &entry);
+                                   1.2f, (int32_t)hubs, 20000, 1, std::max(64, 3 * R / 2),
+                                   adj.data(), &entry);
   if (rc) return fail(ANN_EINVAL, "graph construction failed (%d)", rc);
   return ann_save_index(out_dir, vectors, adj.data(), n, d, dtype, R, entry, slot_bytes);
 }

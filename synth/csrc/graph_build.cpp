@@ -14,6 +14,20 @@
 //   5. every list is filled to exactly R ids with the next-closest pool
 //      candidates (-1 padding only when fewer than R other points exist).
 //   6. breadth-first connectivity repair from the medoid.
+//   7. refinement passes in the manner of DiskANN's Vamana construction
+//      (optional, `passes`): every point, in a seeded order and in batches,
+//      runs a greedy best-first search for its own vector from the medoid
+//      with list size Lb on the graph as it stood at the batch start; the
+//      expanded nodes plus its current neighbours are alpha-pruned to its new
+//      list (its long-range edges from step 4 are kept), and every new edge
+//      p -> q proposes q -> p, re-pruned where a list exceeds R.  These
+//      passes prune with alpha = 1: on mixtures in 96-128 dimensions all
+//      distances inside a component are nearly equal, so a rule with
+//      alpha = 1.2 keeps almost every candidate, the lists degenerate into
+//      kNN lists, and search recall fell to about 0.3 (measured); alpha = 1
+//      keeps them diverse.  Then steps 5 and 6 again.  Searches of a batch read a frozen graph and updates are
+//      applied in batch order, so the result does not depend on the number
+//      of threads.
 // Distances are squared L2 accumulated in int32 (u8/i8) or float (f32) and
 // compared as float with ties broken by id.
 #include <algorithm>
@@ -117,6 +131,40 @@ void robust_prune(const Data &D, const std::vector<Cand> &sorted_pool, int R, fl
   }
 }
 
+// Greedy best-first search for the vector of point p on a degree-R graph
+// (flat ids, -1 = empty) from `entry` with a candidate list of Lb entries;
+// returns the expanded nodes with their distances to p.  `stamp` (n entries,
+// per thread) marks visited nodes with the current `epoch`.
+void greedy_expand(const Data &D, const int32_t *adj, int R, int64_t p, int32_t entry, int Lb,
+                   std::vector<uint32_t> &stamp, uint32_t epoch, std::vector<Cand> &expanded) {
+  expanded.clear();
+  std::vector<std::pair<Cand, bool>> list;  // sorted by (distance, id); bool = expanded
+  list.reserve((size_t)Lb + (size_t)R + 1);
+  stamp[entry] = epoch;
+  list.push_back({Cand(D.dist(p, entry), entry), false});
+  for (;;) {
+    size_t i = 0;
+    while (i < list.size() && list[i].second) i++;
+    if (i == list.size()) break;
+    list[i].second = true;
+    const int32_t u = list[i].first.second;
+    expanded.push_back(list[i].first);
+    const int32_t *row = adj + (int64_t)u * R;
+    for (int j = 0; j < R; j++) {
+      const int32_t x = row[j];
+      if (x < 0 || stamp[x] == epoch) continue;
+      stamp[x] = epoch;
+      const Cand c(D.dist(p, x), x);
+      if ((int)list.size() >= Lb && !(c < list.back().first)) continue;
+      auto pos = std::lower_bound(list.begin(), list.end(), std::make_pair(c, false),
+                                  [](const std::pair<Cand, bool> &a,
+                                     const std::pair<Cand, bool> &b) { return a.first < b.first; });
+      list.insert(pos, {c, false});
+      if ((int)list.size() > Lb) list.pop_back();
+    }
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -169,7 +217,8 @@ int synth_random_graph(int64_t n, int32_t R, uint64_t seed, int32_t *adj) {
 
 int synth_build_graph(const void *base, int64_t n, int32_t d, int32_t dtype, int32_t R,
                       uint64_t seed, int32_t threads, int32_t pool, float alpha,
-                      int32_t n_hubs, int64_t exact_limit, int32_t *adj, int32_t *entry_out) {
+                      int32_t n_hubs, int64_t exact_limit, int32_t passes, int32_t Lb,
+                      int32_t *adj, int32_t *entry_out) {
   if (!base || !adj || n < 1 || d < 1 || R < 1 || pool < R ||
       (dtype != DT_U8 && dtype != DT_I8 && dtype != DT_F32))
     return -22;
@@ -269,6 +318,8 @@ int synth_build_graph(const void *base, int64_t n, int32_t d, int32_t dtype, int
     out.swap(out2);
   }
 
+  std::vector<std::vector<int32_t>> longr(n);  // long-range edges of step 4
+
   // ---- 4. long-range edges.  Nearest-neighbour edges alone leave one
   // component per well-separated mixture component, and in high dimension
   // pruning rules cannot tell components apart (all points of a component
@@ -291,6 +342,7 @@ int synth_build_graph(const void *base, int64_t n, int32_t d, int32_t dtype, int
         if (h == i || std::find(extra.begin(), extra.end(), h) != extra.end()) continue;
         extra.push_back(h);
       }
+      longr[i] = extra;
       std::vector<int32_t> merged;
       const int local = R - (int)extra.size();
       for (int32_t x : out[i]) {
@@ -316,6 +368,7 @@ int synth_build_graph(const void *base, int64_t n, int32_t d, int32_t dtype, int
       eo.push_back(hubs[best]);
       for (int64_t a = 0; a < Hn; a++) mind[a] = std::min(mind[a], D.dist(hubs[best], hubs[a]));
     }
+    longr[medoid] = eo;
     for (int32_t x : out[medoid]) {
       if ((int)eo.size() >= R) break;
       if (std::find(eo.begin(), eo.end(), x) == eo.end()) eo.push_back(x);
@@ -324,70 +377,201 @@ int synth_build_graph(const void *base, int64_t n, int32_t d, int32_t dtype, int
   }
 
   // ---- 5. fill every list to exactly R from the pool (closest first).
-  parallel_for(n, threads, [&](int64_t i) {
-    auto &o = out[i];
-    for (const Cand &c : pools[i]) {
-      if ((int)o.size() >= R) break;
-      if (std::find(o.begin(), o.end(), c.second) == o.end()) o.push_back(c.second);
+  auto fill = [&]() {
+    parallel_for(n, threads, [&](int64_t i) {
+      auto &o = out[i];
+      for (const Cand &c : pools[i]) {
+        if ((int)o.size() >= R) break;
+        if (c.second != i && std::find(o.begin(), o.end(), c.second) == o.end())
+          o.push_back(c.second);
+      }
+    });
+  };
+  auto write = [&]() {
+    for (int64_t i = 0; i < n; i++) {
+      int32_t *row = adj + i * R;
+      int m = 0;
+      for (int32_t x : out[i])
+        if (m < R && x != i) row[m++] = x;
+      for (; m < R; m++) row[m] = -1;
     }
-  });
+  };
+  // ---- 6. connectivity repair from the medoid.
+  auto repair = [&]() {
+    std::vector<uint16_t> rep_used(n, 0);
+    for (int round = 0; round < 16; round++) {
+      std::vector<uint8_t> seen(n, 0);
+      std::vector<int32_t> stack;
+      auto bfs_from = [&](int32_t s0) {
+        if (seen[s0]) return;
+        seen[s0] = 1;
+        stack.push_back(s0);
+        while (!stack.empty()) {
+          int32_t u = stack.back();
+          stack.pop_back();
+          for (int j = 0; j < R; j++) {
+            int32_t x = adj[(int64_t)u * R + j];
+            if (x >= 0 && !seen[x]) { seen[x] = 1; stack.push_back(x); }
+          }
+        }
+      };
+      bfs_from((int32_t)medoid);
+      int64_t repaired = 0;
+      for (int64_t x = 0; x < n; x++) {
+        if (seen[x]) continue;
+        // attach x to its closest reached pool neighbour, else the closest reached hub
+        int32_t y = -1;
+        for (const Cand &c : pools[x])
+          if (seen[c.second]) { y = c.second; break; }
+        if (y < 0) {
+          float best = INFINITY;
+          for (int32_t h : hubs)
+            if (seen[h]) {
+              float dd = D.dist(x, h);
+              if (dd < best) { best = dd; y = h; }
+            }
+        }
+        if (y < 0) y = (int32_t)medoid;
+        int32_t *row = adj + (int64_t)y * R;
+        int slot = -1;
+        for (int j = 0; j < R; j++)
+          if (row[j] < 0) { slot = j; break; }
+        if (slot < 0) {  // overwrite the farthest slots, a different one per repair
+          const int span = std::max(1, R / 2);
+          slot = R - 1 - (rep_used[y] % span);
+          rep_used[y]++;
+        }
+        row[slot] = (int32_t)x;
+        repaired++;
+        bfs_from((int32_t)x);
+      }
+      if (repaired == 0) break;
+    }
+  };
+  fill();
+  write();
+  repair();
 
-  // ---- write, then 6. connectivity repair from the medoid.
-  for (int64_t i = 0; i < n; i++) {
-    int32_t *row = adj + i * R;
-    int m = 0;
-    for (int32_t x : out[i])
-      if (m < R && x != i) row[m++] = x;
-    for (; m < R; m++) row[m] = -1;
-  }
-  std::vector<uint16_t> rep_used(n, 0);
-  for (int round = 0; round < 16; round++) {
-    std::vector<uint8_t> seen(n, 0);
-    std::vector<int32_t> stack;
-    auto bfs_from = [&](int32_t s) {
-      if (seen[s]) return;
-      seen[s] = 1;
-      stack.push_back(s);
-      while (!stack.empty()) {
-        int32_t u = stack.back();
-        stack.pop_back();
-        for (int j = 0; j < R; j++) {
-          int32_t x = adj[(int64_t)u * R + j];
-          if (x >= 0 && !seen[x]) { seen[x] = 1; stack.push_back(x); }
+  // ---- 7. Vamana-style refinement passes.
+  if (passes > 0 && n > 2) {
+    const int L_build = std::max(Lb, R);
+    std::vector<int32_t> perm(n);
+    for (int64_t i = 0; i < n; i++) perm[i] = (int32_t)i;
+    {
+      uint64_t s2 = seed ^ 0x6A09E667F3BCC909ull;
+      for (int64_t i = n - 1; i > 0; i--) std::swap(perm[i], perm[splitmix64(s2) % (uint64_t)(i + 1)]);
+    }
+    const int64_t B = std::max<int64_t>(1024, n / 128);
+    const int T = std::max(1, threads);
+    std::vector<std::vector<uint32_t>> stamps(T, std::vector<uint32_t>(n, 0u));
+    std::vector<uint32_t> epochs(T, 0u);
+    std::vector<std::vector<int32_t>> fresh(B);
+    std::vector<std::vector<int32_t>> rev(n);
+    // rows as lists, excluding padding
+    for (int64_t i = 0; i < n; i++) {
+      out[i].clear();
+      for (int j = 0; j < R; j++)
+        if (adj[i * R + j] >= 0) out[i].push_back(adj[i * R + j]);
+    }
+    auto is_long = [&](int64_t i, int32_t x) {
+      return std::find(longr[i].begin(), longr[i].end(), x) != longr[i].end();
+    };
+    // prune candidates of point i (sorted, unique, without i) to R edges,
+    // its long-range edges kept
+    auto prune_keep_long = [&](int64_t i, std::vector<Cand> &c, float a, std::vector<int32_t> &o) {
+      std::vector<Cand> local;
+      local.reserve(c.size());
+      for (const Cand &e : c)
+        if (!is_long(i, e.second)) local.push_back(e);
+      const int room = R - (int)longr[i].size();
+      robust_prune(D, local, std::max(room, 0), a, o);
+      for (int32_t x : longr[i])
+        if ((int)o.size() < R) o.push_back(x);
+    };
+    for (int pass = 0; pass < passes; pass++) {
+      const float a = 1.0f;
+      for (int64_t b0 = 0; b0 < n; b0 += B) {
+        const int64_t b1 = std::min(n, b0 + B);
+        // searches on the frozen graph (adj)
+        std::atomic<int64_t> next(b0);
+        auto work = [&](int t) {
+          std::vector<Cand> ex, c;
+          std::vector<int32_t> o;
+          for (;;) {
+            const int64_t k = next.fetch_add(1);
+            if (k >= b1) break;
+            const int64_t p = perm[k];
+            if (p == medoid) {
+              fresh[k - b0] = out[p];
+              continue;
+            }
+            greedy_expand(D, adj, R, p, (int32_t)medoid, L_build, stamps[t], ++epochs[t], ex);
+            c.clear();
+            for (const Cand &e : ex)
+              if (e.second != p) c.push_back(e);
+            for (int32_t x : out[p])
+              if (x != p) c.emplace_back(D.dist(p, x), x);
+            std::sort(c.begin(), c.end());
+            c.erase(std::unique(c.begin(), c.end()), c.end());
+            prune_keep_long(p, c, a, o);
+            fresh[k - b0] = o;
+          }
+        };
+        {
+          std::vector<std::thread> th;
+          for (int t = 1; t < T; t++) th.emplace_back(work, t);
+          work(0);
+          for (auto &x : th) x.join();
+        }
+        // apply in batch order: new lists, then proposed reverse edges
+        std::vector<int32_t> touched;
+        for (int64_t k = b0; k < b1; k++) {
+          const int64_t p = perm[k];
+          out[p] = fresh[k - b0];
+          for (int32_t q : out[p]) {
+            if (q == medoid || is_long(p, q)) continue;
+            if (rev[q].empty()) touched.push_back(q);
+            rev[q].push_back((int32_t)p);
+          }
+        }
+        std::sort(touched.begin(), touched.end());
+        parallel_for((int64_t)touched.size(), threads, [&](int64_t t) {
+          const int32_t q = touched[t];
+          std::vector<int32_t> merged = out[q];
+          for (int32_t x : rev[q])
+            if (x != q && std::find(merged.begin(), merged.end(), x) == merged.end())
+              merged.push_back(x);
+          if ((int)merged.size() > R) {
+            std::vector<Cand> c;
+            for (int32_t x : merged) c.emplace_back(D.dist(q, x), x);
+            std::sort(c.begin(), c.end());
+            std::vector<int32_t> o;
+            prune_keep_long(q, c, a, o);
+            merged.swap(o);
+          }
+          out[q] = merged;
+        });
+        for (int32_t q : touched) rev[q].clear();
+        for (int64_t i = b0; i < b1; i++) {
+          const int64_t p = perm[i];
+          int32_t *row = adj + p * R;
+          int m = 0;
+          for (int32_t x : out[p])
+            if (m < R && x != p) row[m++] = x;
+          for (; m < R; m++) row[m] = -1;
+        }
+        for (int32_t q : touched) {
+          int32_t *row = adj + (int64_t)q * R;
+          int m = 0;
+          for (int32_t x : out[q])
+            if (m < R && x != q) row[m++] = x;
+          for (; m < R; m++) row[m] = -1;
         }
       }
-    };
-    bfs_from((int32_t)medoid);
-    int64_t repaired = 0;
-    for (int64_t x = 0; x < n; x++) {
-      if (seen[x]) continue;
-      // attach x to its closest reached pool neighbour, else the closest reached hub
-      int32_t y = -1;
-      for (const Cand &c : pools[x])
-        if (seen[c.second]) { y = c.second; break; }
-      if (y < 0) {
-        float best = INFINITY;
-        for (int32_t h : hubs)
-          if (seen[h]) {
-            float dd = D.dist(x, h);
-            if (dd < best) { best = dd; y = h; }
-          }
-      }
-      if (y < 0) y = (int32_t)medoid;
-      int32_t *row = adj + (int64_t)y * R;
-      int slot = -1;
-      for (int j = 0; j < R; j++)
-        if (row[j] < 0) { slot = j; break; }
-      if (slot < 0) {  // overwrite the farthest slots, a different one per repair
-        const int span = std::max(1, R / 2);
-        slot = R - 1 - (rep_used[y] % span);
-        rep_used[y]++;
-      }
-      row[slot] = (int32_t)x;
-      repaired++;
-      bfs_from((int32_t)x);
     }
-    if (repaired == 0) break;
+    fill();
+    write();
+    repair();
   }
   return 0;
 }

@@ -35,7 +35,7 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         vp, i64, i32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64
         lib.synth_build_graph.argtypes = [vp, i64, i32, i32, i32, u64, i32, i32, ctypes.c_float,
-                                          i32, i64, vp, vp]
+                                          i32, i64, i32, i32, vp, vp]
         lib.synth_build_graph.restype = ctypes.c_int
         lib.synth_random_graph.argtypes = [i64, i32, u64, vp]
         lib.synth_random_graph.restype = ctypes.c_int
@@ -45,22 +45,33 @@ def _load():
     return _lib
 
 
+REFINE_PASSES = 1
+
+
 def _threads(t):
     return t or min(16, os.cpu_count() or 1)
 
 
 def build_graph(base: np.ndarray, R: int, seed: int, threads: int = 0, pool: int | None = None,
-                alpha: float = 1.2, n_hubs: int | None = None, exact_limit: int = 20000):
-    """Degree-R proximity graph over ``base``.  Returns (adj int32 [n, R], entry)."""
+                alpha: float = 1.2, n_hubs: int | None = None, exact_limit: int = 20000,
+                passes: int = REFINE_PASSES, L_build: int | None = None):
+    """Degree-R proximity graph over ``base``.  Returns (adj int32 [n, R], entry).
+
+    `passes` Vamana-style refinement passes (greedy search of each point's own
+    vector with list size `L_build`, default max(64, 3R/2), then pruning of
+    the expanded nodes with alpha = 1) follow the pool-based construction;
+    `alpha` applies to the initial pool pruning."""
     base = np.ascontiguousarray(base)
     n, d = base.shape
     pool = pool or max(2 * R, 64)
     if n_hubs is None:
         n_hubs = int(min(max(64, n // 1000), 4096))
+    L_build = L_build or max(64, (3 * R) // 2)
     adj = np.empty((n, R), dtype=np.int32)
     entry = ctypes.c_int32(-1)
     rc = _load().synth_build_graph(base.ctypes.data_as(ctypes.c_void_p), n, d, _DT[base.dtype],
                                    R, seed, _threads(threads), pool, alpha, n_hubs, exact_limit,
+                                   passes, L_build,
                                    adj.ctypes.data_as(ctypes.c_void_p), ctypes.byref(entry))
     if rc != 0:
         raise ValueError("synth_build_graph failed: %d" % rc)
