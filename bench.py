@@ -88,16 +88,17 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(workload):
+def stored_traffic(workload, L):
     """HBM traffic per launch measured by rocprofv3 counters, if the kernel
-    has not changed since (profiles/search_traffic.json)."""
+    and the operating L have not changed since (profiles/search_traffic.json)."""
     p = os.path.join(ROOT, "profiles", "search_traffic.json")
     try:
         with open(p) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_hash") != kernel_source_hash() or t.get("workload") != workload:
+    if (t.get("kernel_hash") != kernel_source_hash() or t.get("workload") != workload
+            or t.get("L") != L):
         return None
     return t.get("traffic_bytes_per_launch")
 
@@ -327,7 +328,7 @@ def main():
     roofline = {"bound": "hbm", "binding": "host_link" if link_bytes else "hbm",
                 "achieved": round(hbm_ach, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(hbm_ach / HBM_PEAK_GBS, 5),
-                "traffic": stored_traffic(workload),
+                "traffic": stored_traffic(workload, op[1]),
                 "algorithmic_bytes_per_launch": hbm_bytes,
                 "host_link": {"achieved": round(link_bytes / sec / 1e9, 2),
                               "peak_probe": round(link_peak, 2), "unit": "GB/s",
