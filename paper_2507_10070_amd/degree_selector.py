@@ -123,7 +123,7 @@ def select_fitted(rows):
 
 
 def validate(R_values, n, d, dtype, components, slot, tier, nq, seed=11,
-             L_sweep=(32, 48, 64, 96, 128, 192, 256), tmp=None):
+             L_sweep=(10, 12, 16, 20, 24, 32, 48, 64, 96, 128, 192, 256), tmp=None):
     """QPS at recall@10 >= 0.95 (relaxed) on real graphs of each degree."""
     import torch
 
