@@ -25,7 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-L_SWEEP = (32, 48, 64, 96, 128, 192, 256)
+L_SWEEP = (32, 36, 40, 44, 48, 52, 56, 60, 64, 96, 128, 192, 256)
 # (delta, W) pairs of the schedule sweep; (delta + 1) * W <= 8
 SCHEDULES = ((0, 1), (1, 1), (2, 1), (3, 1), (0, 2), (1, 2), (3, 2), (0, 4), (1, 4), (0, 8))
 
@@ -335,6 +335,33 @@ def main():
                               "frac": round(link_bytes / sec / 1e9 / link_peak, 4),
                               "bytes_per_launch": link_bytes}}
 
+    # ---- relaxed vs strict as the batch shrinks: with fewer queries in flight
+    # the host link is no longer saturated and each query's fetch latency is
+    # exposed, which is where the relaxed pipeline pays (section 4.1)
+    concurrency = None
+    if not args.no_schedule_sweep:
+        concurrency = []
+        for nb in (128, 512, 2048, nq):
+            qsub = qd[:nb].contiguous()
+            ob = (torch.empty((nb, k), dtype=torch.int32, device=dev),
+                  torch.empty((nb, k), dtype=torch.int32, device=dev),
+                  torch.empty((nb,), dtype=torch.int32, device=dev))
+            row = {"queries": nb}
+            for name, delay in (("strict", 0), ("relaxed", 1)):
+                for _ in range(2):
+                    fa.search(ix, qsub, k=k, L=op[1], delay=delay, out=ob, stream=stream)
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+                reps_c = 10
+                ev[0].record(stream)
+                for _ in range(reps_c):
+                    fa.search(ix, qsub, k=k, L=op[1], delay=delay, out=ob, stream=stream)
+                ev[1].record(stream)
+                torch.cuda.synchronize()
+                row[name + "_qps"] = round(nb / (ev[0].elapsed_time(ev[1]) / reps_c / 1e3), 1)
+            row["relaxed_vs_strict"] = round(row["relaxed_qps"] / row["strict_qps"], 4)
+            concurrency.append(row)
+            log("concurrency %s" % row)
+
     # ---- staleness delta and beam width W at the relaxed operating L: steps,
     # recall and throughput of each schedule (direct loads; agent transport
     # too when records are in host DRAM)
@@ -527,6 +554,7 @@ def main():
         "detail": {"strict": detail[0], "relaxed": detail[1]},
         "sweep": {"strict": sweep[0], "relaxed": sweep[1]},
         "roofline": roofline,
+        "concurrency": concurrency,
         "schedules": schedules,
         "batched": batched,
         "transports": transports,
