@@ -198,6 +198,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the autotuned uneven-L batch")
     ap.add_argument("--batched-queries", type=int, default=100000)
+    ap.add_argument("--no-hbm-tier", action="store_true",
+                    help="skip the same search with the records in HBM")
     ap.add_argument("--no-transports", action="store_true",
                     help="skip the agent-transport and file-tier measurements")
     ap.add_argument("--file-queries", type=int, default=1000,
@@ -208,7 +210,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
-              "(the search shards by query across GPUs, see the design notes)" % args.gpus,
+              "(across GPUs the search would shard by query, each GPU holding its own "
+              "navigation copy)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
@@ -429,6 +432,31 @@ def main():
         log("batched: %s" % batched)
         del qb, ob
 
+    # ---- the same index with its records in HBM: the kernel without the host
+    # link in the way (where the HBM roofline applies)
+    hbm_tier = None
+    if tier == fa.TIER_HOST and not args.no_hbm_tier:
+        with fa.Index(base, adj, entry, cfg.slot, fa.TIER_HBM) as hix:
+            hbm_tier = {}
+            for name, delay in (("strict", 0), ("relaxed", 1)):
+                st_ = torch.zeros(3, dtype=torch.int64, device=dev)
+                fa.search(hix, qd, k=k, L=op[1], delay=delay, out=out, stream=stream, stats=st_)
+                torch.cuda.synchronize()
+                s_ = st_.cpu().numpy()
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+                ev[0].record(stream)
+                for _ in range(5):
+                    fa.search(hix, qd, k=k, L=op[1], delay=delay, out=out, stream=stream)
+                ev[1].record(stream)
+                torch.cuda.synchronize()
+                ms_h = ev[0].elapsed_time(ev[1]) / 5
+                byt = int(s_[0]) * info["rec_bytes"] + int(s_[1]) * info["nav_stride"] + \
+                    nq * (cfg.d + 8 * k + 4)
+                hbm_tier[name] = {"qps": round(nq / (ms_h / 1e3), 1), "ms_per_step": round(ms_h, 4),
+                                  "algorithmic_GBps": round(byt / (ms_h / 1e3) / 1e9, 1),
+                                  "hbm_frac": round(byt / (ms_h / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+            log("records in HBM: %s" % hbm_tier)
+
     # ---- the paper's query-grained I/O stack on the same workload: agent
     # transport from pinned DRAM (all queries) and from a file (O_DIRECT)
     transports = None
@@ -557,6 +585,7 @@ def main():
         "concurrency": concurrency,
         "schedules": schedules,
         "batched": batched,
+        "records_in_hbm": hbm_tier,
         "transports": transports,
         "serving": serving,
         "cpu_baseline": cpu,

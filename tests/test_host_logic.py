@@ -50,3 +50,17 @@ def test_autotune_in_flight_limit():
     assert autotune.valid({"delay": 3, "beam_width": 2})
     assert not autotune.valid({"delay": 2, "beam_width": 3})
     assert autotune.valid({"delay": 7, "beam_width": 1})
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU; any other count exits with a message
+    before touching a device."""
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
