@@ -81,10 +81,18 @@ def host_cpu():
 
 
 def kernel_source_hash():
+    """Hash of the source the search kernel is compiled from: the kernel
+    header and search_kernel.hip up to the end of the search kernel itself
+    (the lockstep and server kernels and the host launchers follow it and do
+    not change the profiled code)."""
     h = hashlib.sha256()
-    for f in ("search_kernel.hip", "search_kernel.h"):
-        with open(os.path.join(ROOT, "paper_2507_10070_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_2507_10070_amd", "csrc")
+    with open(os.path.join(csrc, "search_kernel.h"), "rb") as fh:
+        h.update(fh.read())
+    with open(os.path.join(csrc, "search_kernel.hip"), "rb") as fh:
+        src = fh.read()
+    end = src.find(b"__global__ void reset_work(")
+    h.update(src if end < 0 else src[:end])
     return h.hexdigest()[:16]
 
 

@@ -260,12 +260,14 @@ int ann_device_clock_khz(int32_t *khz);
  *   opts (NULL = defaults): k_max (100), L_max (256), delay (1),
  *   waves_per_block (4), hash_bits (10), queue_cap (2^20 waiting arrivals),
  *   idle_polls (50000: empty polls before the kernel leaves; it is started
- *   again when work arrives).
+ *   again when work arrives), beam_width (1); the schedule is that of
+ *   ann_search with the same delay and beam width.
  * Errors: ANN_EINVAL, ANN_ENOMEM (budget too small or allocation), ANN_EIO.
  */
 typedef struct ann_server ann_server;
 typedef struct {
   int32_t k_max, L_max, delay, waves_per_block, hash_bits, queue_cap, idle_polls;
+  int32_t beam_width; /* W (0 = 1); (delay + 1) * W <= 8 */
 } ann_server_opts;
 typedef struct {
   uint64_t tag;          /* the caller's tag */

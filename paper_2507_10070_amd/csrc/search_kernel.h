@@ -76,7 +76,8 @@ struct ServerArgs {
   uint32_t *done;           // host-mapped, nslots x 16 (one 64 B line per slot)
   uint32_t idle_limit;      // empty polls before a wave leaves
 };
-hipError_t launch_server(const ServerArgs &a, int dtype, int delay, int waves_per_block,
+// The schedule follows a.base.delay and a.base.beam, as in launch_search.
+hipError_t launch_server(const ServerArgs &a, int dtype, int waves_per_block,
                          int64_t *resident_waves, hipStream_t st);
 
 // persistent: grid sized to the resident capacity of the GPU; waves take

@@ -1156,30 +1156,31 @@ static hipError_t launch_server_t(const ServerArgs &a, int wpb, int64_t *residen
 }
 
 template <int DT, int CPL>
-static hipError_t launch_server_d(const ServerArgs &a, int delay, int wpb, int64_t *res,
-                                  hipStream_t st) {
-  return delay == 0 ? launch_server_t<DT, CPL, 0>(a, wpb, res, st)
-                    : launch_server_t<DT, CPL, 1>(a, wpb, res, st);
+static hipError_t launch_server_d(const ServerArgs &a, int wpb, int64_t *res, hipStream_t st) {
+  const int delay = a.base.delay, beam = a.base.beam;
+  if (delay < 0 || beam < 1 || (delay + 1) * beam > kMaxPipe) return hipErrorInvalidValue;
+  if (beam == 1 && delay == 0) return launch_server_t<DT, CPL, SCHED_STRICT>(a, wpb, res, st);
+  if (beam == 1 && delay == 1) return launch_server_t<DT, CPL, SCHED_RELAXED>(a, wpb, res, st);
+  return launch_server_t<DT, CPL, SCHED_GENERIC>(a, wpb, res, st);
 }
 
 template <int DT>
-static hipError_t launch_server_c(const ServerArgs &a, int delay, int wpb, int64_t *res,
-                                  hipStream_t st) {
+static hipError_t launch_server_c(const ServerArgs &a, int wpb, int64_t *res, hipStream_t st) {
   switch (a.base.nav_stride / 128) {
-    case 1: return launch_server_d<DT, 1>(a, delay, wpb, res, st);
-    case 2: return launch_server_d<DT, 2>(a, delay, wpb, res, st);
-    case 3: return launch_server_d<DT, 3>(a, delay, wpb, res, st);
-    case 4: return launch_server_d<DT, 4>(a, delay, wpb, res, st);
+    case 1: return launch_server_d<DT, 1>(a, wpb, res, st);
+    case 2: return launch_server_d<DT, 2>(a, wpb, res, st);
+    case 3: return launch_server_d<DT, 3>(a, wpb, res, st);
+    case 4: return launch_server_d<DT, 4>(a, wpb, res, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_server(const ServerArgs &a, int dtype, int delay, int waves_per_block,
+hipError_t launch_server(const ServerArgs &a, int dtype, int waves_per_block,
                          int64_t *resident_waves, hipStream_t st) {
   switch (dtype) {
-    case DT_U8: return launch_server_c<DT_U8>(a, delay, waves_per_block, resident_waves, st);
-    case DT_I8: return launch_server_c<DT_I8>(a, delay, waves_per_block, resident_waves, st);
-    case DT_F32: return launch_server_c<DT_F32>(a, delay, waves_per_block, resident_waves, st);
+    case DT_U8: return launch_server_c<DT_U8>(a, waves_per_block, resident_waves, st);
+    case DT_I8: return launch_server_c<DT_I8>(a, waves_per_block, resident_waves, st);
+    case DT_F32: return launch_server_c<DT_F32>(a, waves_per_block, resident_waves, st);
     default: return hipErrorInvalidValue;
   }
 }

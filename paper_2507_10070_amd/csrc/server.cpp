@@ -103,7 +103,7 @@ struct ann_server {
   std::string error_msg;
 
   int launch_kernel() {
-    hipError_t e = fa::launch_server(args, dtype, delay, wpb, nullptr, st_kernel);
+    hipError_t e = fa::launch_server(args, dtype, wpb, nullptr, st_kernel);
     if (e == hipSuccess) e = hipEventRecord(ev_kernel, st_kernel);
     if (e != hipSuccess) {
       error_msg = std::string("server kernel launch: ") + hipGetErrorString(e);
@@ -313,10 +313,14 @@ int ann_server_open(ann_index *ix, size_t hbm_budget_bytes, const ann_server_opt
   if (o.hash_bits == 0) o.hash_bits = 10;
   if (o.queue_cap == 0) o.queue_cap = 1 << 20;
   if (o.idle_polls == 0) o.idle_polls = 50000;
+  if (o.beam_width == 0) o.beam_width = 1;
   if (o.k_max < 1 || o.k_max > 0xFFFF || o.L_max < o.k_max || o.L_max > 1024 ||
-      o.delay < 0 || o.delay > 1 || o.waves_per_block < 1 || o.waves_per_block > 4 ||
+      o.delay < 0 || o.beam_width < 1 || o.waves_per_block < 1 || o.waves_per_block > 4 ||
       o.queue_cap < 1)
     return ann_internal_fail(ANN_EINVAL, "bad server options");
+  if ((int64_t)(o.delay + 1) * o.beam_width > fa::kMaxPipe)
+    return ann_internal_fail(ANN_ENOTSUP, "(delay+1)*beam_width exceeds the 8 nodes a query "
+                                          "may hold in flight");
   ann_server *s = new (std::nothrow) ann_server();
   if (!s) return ann_internal_fail(ANN_ENOMEM, "server handle");
   s->ix = ix;
@@ -330,6 +334,8 @@ int ann_server_open(ann_index *ix, size_t hbm_budget_bytes, const ann_server_opt
     server_free(s);
     return rc;
   }
+  s->args.base.delay = o.delay;
+  s->args.base.beam = o.beam_width;
   s->nav_stride = s->args.base.nav_stride;
   s->qbytes = s->args.base.qbytes;
   // Per admitted query the device holds one ring entry (control + query);
@@ -337,7 +343,7 @@ int ann_server_open(ann_index *ix, size_t hbm_budget_bytes, const ann_server_opt
   // has room for every admitted query plus one claim per resident wave.
   const int64_t eb = 16 + s->nav_stride;
   int64_t resident = 0;
-  hipError_t e = fa::launch_server(s->args, s->dtype, s->delay, s->wpb, &resident, nullptr);
+  hipError_t e = fa::launch_server(s->args, s->dtype, s->wpb, &resident, nullptr);
   if (e != hipSuccess) {
     server_free(s);
     return ann_internal_fail(ANN_EIO, "server occupancy query failed");

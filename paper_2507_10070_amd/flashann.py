@@ -57,7 +57,8 @@ class IndexInfo(ctypes.Structure):
 class ServerOptions(ctypes.Structure):
     _fields_ = [("k_max", ctypes.c_int32), ("L_max", ctypes.c_int32), ("delay", ctypes.c_int32),
                 ("waves_per_block", ctypes.c_int32), ("hash_bits", ctypes.c_int32),
-                ("queue_cap", ctypes.c_int32), ("idle_polls", ctypes.c_int32)]
+                ("queue_cap", ctypes.c_int32), ("idle_polls", ctypes.c_int32),
+                ("beam_width", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -361,13 +362,13 @@ class Server:
 
     def __init__(self, index: Index, hbm_budget_bytes: int, k_max: int = 100, L_max: int = 256,
                  delay: int = 1, waves_per_block: int = 0, hash_bits: int = 0,
-                 queue_cap: int = 0, idle_polls: int = 0):
+                 queue_cap: int = 0, idle_polls: int = 0, beam_width: int = 1):
         self.index = index
         self.dtype = index.dtype
         self.d = index.d
         self.k_max = k_max
         opts = ServerOptions(k_max, L_max, delay, waves_per_block, hash_bits, queue_cap,
-                             idle_polls)
+                             idle_polls, beam_width)
         h = ctypes.c_void_p()
         _check(load_library().ann_server_open(index.handle, int(hbm_budget_bytes),
                                               ctypes.byref(opts), ctypes.byref(h)))

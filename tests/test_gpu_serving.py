@@ -114,3 +114,30 @@ def test_server_rejects_bad_requests(cfg1):
         with pytest.raises(fa.AnnError) as e:
             fa.Server(ix, hbm_budget_bytes=1000)
         assert e.value.code == -12
+
+
+@pytest.mark.parametrize("delay,beam", [(2, 2), (0, 4), (3, 1)])
+def test_server_generic_schedules(cfg1, delay, beam):
+    """The server runs any (delay, beam width) the batch search runs; every
+    result equals the oracle's at its own k and L."""
+    base, q, adj, entry = cfg1
+    ks, Ls = plan(len(q), 7)
+    with fa.Index(base, adj, entry, 256, fa.TIER_HOST) as ix:
+        with fa.Server(ix, hbm_budget_bytes=64 << 20, delay=delay, beam_width=beam) as srv:
+            for i in range(len(q)):
+                srv.submit(q[i], int(ks[i]), int(Ls[i]), i)
+            got = collect(srv, len(q))
+    for i in range(len(q)):
+        ref = oracle.search(base, adj, entry, q[i:i + 1], int(ks[i]), int(Ls[i]), delay=delay,
+                            beam=beam)
+        np.testing.assert_array_equal(got[i]["ids"], ref["ids"][0])
+        np.testing.assert_array_equal(got[i]["dists"].astype(np.float64), ref["dists"][0])
+        assert got[i]["steps"] == ref["steps"][0]
+
+
+def test_server_rejects_too_deep_a_pipeline(cfg1):
+    base, q, adj, entry = cfg1
+    with fa.Index(base, adj, entry, 256, fa.TIER_HOST) as ix:
+        with pytest.raises(fa.AnnError) as e:
+            fa.Server(ix, hbm_budget_bytes=64 << 20, delay=2, beam_width=3)
+        assert e.value.code == -95
