@@ -22,6 +22,10 @@
  *     delay = 0 is the strict best-first search.  The staleness is read as
  *     exact (a FIFO of `delay` in-flight nodes), so results never depend on
  *     timing.
+ *   - Beam width W (one node per step in the paper, W = 1 by default): each
+ *     iteration selects up to W unexpanded candidates into the FIFO and
+ *     processes the oldest while more than delay * W are in flight, or the
+ *     oldest min(W, in flight) when nothing was selected.
  *   - Keys are (distance, id) compared lexicographically, so every key is
  *     unique and ties go to the smaller id.
  *   - The visited set is exact.
