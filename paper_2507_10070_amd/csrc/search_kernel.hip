@@ -9,7 +9,7 @@
 //   stage[64]   the record being processed (16 B per lane)
 //   qbuf        the query, zero-padded to the navigation row stride
 //   ids/dsc     per-batch neighbour ids and their distances
-//   hash[H]     visited set: exact ids, linear probing, may forget
+//   hash[H]     visited set: exact ids in buckets of 8 slots, may forget
 //   fifo[8]     generic schedule: keys of the nodes in flight, oldest first
 // Forgetting is harmless: a forgotten node is either still in the list (its
 // recomputed key is identical and is dropped as a duplicate) or its key is
@@ -96,21 +96,28 @@ __device__ __forceinline__ int lower_bound(const uint64_t *a, int cnt, uint64_t 
 }
 
 // Visited set probe: true if x was not recorded (and is recorded now).
+// The table is 2^bits slots in buckets of 8 (32 B): one bucket read answers
+// the lookup, and x goes into an empty slot of its bucket by compare-and-swap
+// (a slot taken meanwhile by another lane moves it to the next one).  A full
+// bucket forgets one of its ids, which never changes results (see the head
+// of this file); it only lets a node be scored again.
 __device__ __forceinline__ bool hash_insert(uint32_t *tab, int bits, uint32_t x) {
-  const uint32_t mask = (1u << bits) - 1u;
-  const uint32_t h = (x * 2654435761u) >> (32 - bits);
-#pragma unroll 1
-  for (int p = 0; p < 8; p++) {
-    const uint32_t s = (h + (uint32_t)p) & mask;
-    uint32_t cur = tab[s];
+  const uint32_t b = (x * 2654435761u) >> (32 - (bits - 3));
+  uint32_t *bk = tab + 8 * b;
+  const uint4 lo = *(const uint4 *)bk;
+  const uint4 hi = *(const uint4 *)(bk + 4);
+  if (lo.x == x || lo.y == x || lo.z == x || lo.w == x || hi.x == x || hi.y == x ||
+      hi.z == x || hi.w == x)
+    return false;
+  const uint32_t slots[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+  for (int e = 0; e < 8; e++) {
+    if (slots[e] != kEmpty) continue;
+    const uint32_t cur = atomicCAS(&bk[e], kEmpty, x);
+    if (cur == kEmpty) return true;
     if (cur == x) return false;
-    if (cur == kEmpty) {
-      cur = atomicCAS(&tab[s], kEmpty, x);
-      if (cur == kEmpty) return true;
-      if (cur == x) return false;
-    }
   }
-  atomicExch(&tab[h & mask], x);  // neighbourhood full: forget one id
+  atomicExch(&bk[x & 7u], x);  // bucket full: forget one id
   return true;
 }
 
