@@ -62,11 +62,13 @@ __device__ __forceinline__ uint64_t shfl_xor64(uint64_t x, int m) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// Ascending bitonic sort of one u64 per lane across the wave.
-__device__ __forceinline__ uint64_t wave_sort64(uint64_t x) {
+// Ascending bitonic sort of one u64 per lane within each aligned block of P
+// lanes (P a power of two <= 64; P = 64 sorts the whole wave).
+template <int P>
+__device__ __forceinline__ uint64_t block_sort(uint64_t x) {
   const int lane = lane_id();
 #pragma unroll
-  for (int k = 2; k <= 64; k <<= 1) {
+  for (int k = 2; k <= P; k <<= 1) {
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
       const uint64_t o = shfl_xor64(x, j);
@@ -77,6 +79,20 @@ __device__ __forceinline__ uint64_t wave_sort64(uint64_t x) {
     }
   }
   return x;
+}
+
+__device__ __forceinline__ uint64_t wave_sort64(uint64_t x) { return block_sort<64>(x); }
+
+// Sort the first `cnt` lanes' keys (the other lanes hold kNoKey) with the
+// smallest network that covers them.
+__device__ __forceinline__ uint64_t sort_prefix(uint64_t x, int cnt) {
+  if (cnt <= 1) return x;
+  if (cnt <= 2) return block_sort<2>(x);
+  if (cnt <= 4) return block_sort<4>(x);
+  if (cnt <= 8) return block_sort<8>(x);
+  if (cnt <= 16) return block_sort<16>(x);
+  if (cnt <= 32) return block_sort<32>(x);
+  return block_sort<64>(x);
 }
 
 __device__ __forceinline__ uint32_t mbcnt(uint64_t mask) {
@@ -505,16 +521,28 @@ struct Searcher {
   }
 
   // Merge the m scored ids into the candidate list (first L of the union).
+  // Keys at or above the L-th key of a full list cannot enter it: one
+  // broadcast read drops them (most keys, late in a search) before the
+  // duplicate check; the survivors are compacted to the first lanes and
+  // sorted with the smallest network that covers them.
   __device__ __forceinline__ void merge(int m) {
     uint64_t key = kNoKey;
     if (lane < m) key = ((uint64_t)S.dsc[lane] << 32) | S.ids[lane];
+    if (nc >= L && key != kNoKey && key >= kmask(S.cand[L - 1])) key = kNoKey;
     if (key != kNoKey) {
       const int r = lower_bound(S.cand, nc, key);
       const bool dup = r < nc && kmask(S.cand[r]) == key;
       if (dup || r >= L) key = kNoKey;
     }
-    if (__ballot(key != kNoKey) == 0) return;
-    key = wave_sort64(key);
+    const uint64_t live = __ballot(key != kNoKey);
+    if (live == 0) return;
+    const int cnt = __popcll((unsigned long long)live);
+    __builtin_amdgcn_wave_barrier();
+    if (key != kNoKey) S.nk[mbcnt(live)] = key;
+    __builtin_amdgcn_wave_barrier();
+    key = lane < cnt ? S.nk[lane] : kNoKey;
+    __builtin_amdgcn_wave_barrier();
+    key = sort_prefix(key, cnt);
     // Equal keys in one batch are possible only when the hash forgot an id
     // that occurs twice in one neighbour list: keep the first.
     {
