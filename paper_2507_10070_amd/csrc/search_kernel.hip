@@ -5,7 +5,7 @@
 // One wavefront (64 lanes) runs one query.  Per wave, LDS holds
 //   cand[Lcap]  the candidate list: u64 keys (distance << 32 | id), sorted
 //               ascending; bit 31 of the id word is the "expanded" flag
-//   nk[64]      sorted keys of the batch being merged
+//   nk[64]      new keys of the batch being merged, compacted
 //   stage[64]   the record being processed (16 B per lane)
 //   qbuf        the query, zero-padded to the navigation row stride
 //   ids/dsc     per-batch neighbour ids and their distances
@@ -55,44 +55,10 @@ __device__ __forceinline__ float group8_sum(float v) {
   return v;
 }
 
-__device__ __forceinline__ uint64_t shfl_xor64(uint64_t x, int m) {
-  const int addr = ((lane_id() ^ m) << 2);
-  uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)x);
-  uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(x >> 32));
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
   return ((uint64_t)hi << 32) | lo;
-}
-
-// Ascending bitonic sort of one u64 per lane within each aligned block of P
-// lanes (P a power of two <= 64; P = 64 sorts the whole wave).
-template <int P>
-__device__ __forceinline__ uint64_t block_sort(uint64_t x) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int k = 2; k <= P; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      const uint64_t o = shfl_xor64(x, j);
-      const bool up = (lane & k) == 0;
-      const bool lower = (lane & j) == 0;
-      const bool take_min = (lower == up);
-      x = take_min ? (o < x ? o : x) : (o > x ? o : x);
-    }
-  }
-  return x;
-}
-
-__device__ __forceinline__ uint64_t wave_sort64(uint64_t x) { return block_sort<64>(x); }
-
-// Sort the first `cnt` lanes' keys (the other lanes hold kNoKey) with the
-// smallest network that covers them.
-__device__ __forceinline__ uint64_t sort_prefix(uint64_t x, int cnt) {
-  if (cnt <= 1) return x;
-  if (cnt <= 2) return block_sort<2>(x);
-  if (cnt <= 4) return block_sort<4>(x);
-  if (cnt <= 8) return block_sort<8>(x);
-  if (cnt <= 16) return block_sort<16>(x);
-  if (cnt <= 32) return block_sort<32>(x);
-  return block_sort<64>(x);
 }
 
 __device__ __forceinline__ uint32_t mbcnt(uint64_t mask) {
@@ -522,45 +488,51 @@ struct Searcher {
 
   // Merge the m scored ids into the candidate list (first L of the union).
   // Keys at or above the L-th key of a full list cannot enter it: one
-  // broadcast read drops them (most keys, late in a search) before the
-  // duplicate check; the survivors are compacted to the first lanes and
-  // sorted with the smallest network that covers them.
+  // broadcast read drops them (most keys, late in a search).  The rest are
+  // checked against the list (binary search: duplicate, or rank r >= L) and
+  // compacted to the first lanes with their rank.  No sort is needed: a new
+  // key lands at r + (new keys below it), an old entry at i + (new keys below
+  // it), both counted with broadcast reads of the compacted keys.
   __device__ __forceinline__ void merge(int m) {
     uint64_t key = kNoKey;
     if (lane < m) key = ((uint64_t)S.dsc[lane] << 32) | S.ids[lane];
     if (nc >= L && key != kNoKey && key >= kmask(S.cand[L - 1])) key = kNoKey;
+    int r = 0;
     if (key != kNoKey) {
-      const int r = lower_bound(S.cand, nc, key);
+      r = lower_bound(S.cand, nc, key);
       const bool dup = r < nc && kmask(S.cand[r]) == key;
       if (dup || r >= L) key = kNoKey;
     }
-    const uint64_t live = __ballot(key != kNoKey);
+    uint64_t live = __ballot(key != kNoKey);
     if (live == 0) return;
-    const int cnt = __popcll((unsigned long long)live);
-    __builtin_amdgcn_wave_barrier();
-    if (key != kNoKey) S.nk[mbcnt(live)] = key;
-    __builtin_amdgcn_wave_barrier();
-    key = lane < cnt ? S.nk[lane] : kNoKey;
-    __builtin_amdgcn_wave_barrier();
-    key = sort_prefix(key, cnt);
-    // Equal keys in one batch are possible only when the hash forgot an id
-    // that occurs twice in one neighbour list: keep the first.
-    {
-      const int addr = ((lane - 1) & 63) << 2;
-      const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)key);
-      const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(key >> 32));
-      const uint64_t left = ((uint64_t)hi << 32) | lo;
-      const bool dupl = lane > 0 && key != kNoKey && left == key;
-      if (__ballot(dupl)) {
-        if (dupl) key = kNoKey;
-        key = wave_sort64(key);
+    int cnt, below;
+    for (;;) {
+      // compact (key, r) into lanes [0, cnt); S.ids is free once the keys are built
+      cnt = __popcll((unsigned long long)live);
+      __builtin_amdgcn_wave_barrier();
+      if (key != kNoKey) {
+        const uint32_t p = mbcnt(live);
+        S.nk[p] = key;
+        S.ids[p] = (uint32_t)r;
       }
+      __builtin_amdgcn_wave_barrier();
+      key = lane < cnt ? S.nk[lane] : kNoKey;
+      r = lane < cnt ? (int)S.ids[lane] : 0;
+      // rank among the new keys; an equal key in a lower lane is a duplicate
+      // (possible only when a forgotten id occurs twice in one neighbour list)
+      below = 0;
+      bool dupl = false;
+      for (int j = 0; j < cnt; j++) {
+        const uint64_t kj = S.nk[j];
+        below += kj < key ? 1 : 0;
+        dupl |= (kj == key) && (j < lane);
+      }
+      dupl = dupl && lane < cnt;
+      const uint64_t drop = __ballot(dupl);
+      if (drop == 0) break;
+      if (dupl) key = kNoKey;
+      live = __ballot(key != kNoKey);
     }
-    const int m2 = __popcll((unsigned long long)__ballot(key != kNoKey));
-    int rnew = 0;
-    if (lane < m2) rnew = lower_bound(S.cand, nc, key);
-    S.nk[lane] = key;
-    __builtin_amdgcn_wave_barrier();
     // old entries move right by the number of smaller new keys; walk chunks
     // from the top so that no unread entry is overwritten
     const int nchunks = (nc + 63) >> 6;
@@ -570,14 +542,55 @@ struct Searcher {
       int pos = L;
       if (i < nc) {
         e = S.cand[i];
-        pos = i + lower_bound(S.nk, m2, kmask(e));
+        const uint64_t ek = kmask(e);
+        int shift = 0;
+        for (int j = 0; j < cnt; j++) shift += S.nk[j] < ek ? 1 : 0;
+        pos = i + shift;
       }
       __builtin_amdgcn_wave_barrier();
       if (i < nc && pos < L) S.cand[pos] = e;
       __builtin_amdgcn_wave_barrier();
     }
-    if (lane < m2 && lane + rnew < L) S.cand[lane + rnew] = key;
-    nc = nc + m2 < L ? nc + m2 : L;
+    if (lane < cnt && r + below < L) S.cand[r + below] = key;
+    nc = nc + cnt < L ? nc + cnt : L;
+    __builtin_amdgcn_wave_barrier();
+  }
+
+  // merge() for lists of at most 64 entries: the list is held one entry per
+  // lane, so every comparison is a register compare and a ballot.  The new
+  // keys are visited in lane order; key j is dropped if it equals a list entry
+  // or ranks at L or beyond, else it survives (and later equal keys are
+  // dropped).  A survivor lands at (list entries below it) + (survivors below
+  // it); a list entry moves right by the survivors below it.
+  __device__ __forceinline__ void merge_small(int m) {
+    const uint64_t cf = lane < nc ? S.cand[lane] : kNoKey;  // entry with its flag
+    const uint64_t c = lane < nc ? kmask(cf) : kNoKey;
+    uint64_t key = kNoKey;
+    if (lane < m) key = ((uint64_t)S.dsc[lane] << 32) | S.ids[lane];
+    if (nc >= L && key >= readlane64(c, L - 1)) key = kNoKey;
+    uint64_t todo = __ballot(key != kNoKey);
+    if (todo == 0) return;
+    int shift = 0, below = 0, r = 0;
+    uint64_t taken = 0;
+    while (todo) {
+      const int j = __ffsll((unsigned long long)todo) - 1;
+      todo &= todo - 1;
+      const uint64_t kj = readlane64(key, j);
+      if (__ballot(c == kj) != 0) continue;                 // already listed
+      const int rj = __popcll((unsigned long long)__ballot(c < kj));
+      if (rj >= L) continue;                                 // beyond the first L
+      todo &= ~__ballot(key == kj);                          // later equal keys
+      taken |= 1ull << j;
+      if (lane == j) r = rj;
+      shift += kj < c ? 1 : 0;
+      below += kj < key ? 1 : 0;
+    }
+    const bool surv = (taken >> lane) & 1ull;
+    __builtin_amdgcn_wave_barrier();
+    if (lane < nc && lane + shift < L) S.cand[lane + shift] = cf;
+    if (surv && r + below < L) S.cand[r + below] = key;
+    const int added = __popcll((unsigned long long)taken);
+    nc = nc + added < L ? nc + added : L;
     __builtin_amdgcn_wave_barrier();
   }
 
@@ -605,7 +618,8 @@ struct Searcher {
     for (int p0 = p_start; p0 < m; p0 += 8 * PB) gather_block<false>(m, p0, 0u, false, unused);
     __builtin_amdgcn_wave_barrier();
     rows += (uint32_t)m;
-    merge(m);
+    if (L <= 64) merge_small(m);
+    else merge(m);
   }
 
   // Process node u whose record handle is `rec`: stage, filter, gather,
