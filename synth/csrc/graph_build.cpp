@@ -105,13 +105,16 @@ void parallel_for(int64_t n, int threads, const std::function<void(int64_t)> &fn
   for (auto &t : th) t.join();
 }
 
-// Keep the K smallest (distance, id) of `v` sorted ascending.
+// Keep the K smallest (distance, id) of `v` sorted ascending, in a buffer of
+// exactly that size (the lists are kept per point, so the scan buffer's
+// capacity must not come with them).
 void keep_smallest(std::vector<Cand> &v, size_t K) {
   if (v.size() > K) {
     std::nth_element(v.begin(), v.begin() + K, v.end());
     v.resize(K);
   }
   std::sort(v.begin(), v.end());
+  std::vector<Cand>(v.begin(), v.end()).swap(v);
 }
 
 // alpha-pruning: scan candidates in ascending order and keep c unless some
