@@ -183,6 +183,87 @@ def serving_leg(fa, ix, queries, kth, budget, L_op):
     return out
 
 
+def batched_file_leg(fa, torch, dev, n, nq_total):
+    """Batched form at scale: n int8 vectors of d = 100 (4,096-component
+    mixture), degree-48 graph, 512 B records in a file read with O_DIRECT by
+    the host agents, nq_total queries with L uniform over {32, 64, 128, 256}
+    in one persistent launch; schedule and tiles chosen by the autotuner on a
+    10,000-query sample.  Recall@10 on the first 1,000 queries."""
+    import shutil
+    import tempfile
+
+    import numpy as np
+
+    import synth
+    from paper_2507_10070_amd import autotune
+
+    t = time.time()
+    base = synth.make_base(n, 100, "i8", 4096, 1004)
+    q = synth.make_queries(nq_total, 100, "i8", 4096, 1004, 2004)
+    log("batched-file: %d x 100 i8 vectors, %d queries in %.1fs" % (n, nq_total, time.time() - t))
+    os.environ["FLASHANN_BUILD_PROGRESS"] = "1"
+    t = time.time()
+    adj, entry = synth.build_graph(base, 48, 3004, threads=min(16, os.cpu_count() or 1))
+    t_graph = time.time() - t
+    log("batched-file: graph R=48 in %.1fs" % t_graph)
+    # exact 10th-neighbour distance of the first 1,000 queries (fp32 GEMM,
+    # exact for int8 data: every partial sum is an integer below 2^24)
+    x = torch.from_numpy(base).to(dev).float()
+    xx = (x * x).sum(1)
+    kth = []
+    for s0 in range(0, 1000, 50):
+        qq = torch.from_numpy(q[s0:s0 + 50]).to(dev).float()
+        dd = (qq * qq).sum(1, keepdim=True) + xx[None] - 2.0 * (qq @ x.T)
+        kth.append(torch.topk(dd, 10, dim=1, largest=False).values[:, 9].cpu())
+    kth = torch.cat(kth).numpy().astype(np.float64)
+    del x, xx, dd
+    torch.cuda.empty_cache()
+    tmpd = tempfile.mkdtemp(prefix="flashann_batched_", dir=os.environ.get("TMPDIR", "/tmp"))
+    try:
+        t = time.time()
+        fa.save_index(tmpd, base, adj, entry, 512)
+        t_save = time.time() - t
+        del adj
+        log("batched-file: index files written in %.1fs" % t_save)
+        ix = fa.Index.load(tmpd, fa.TIER_FILE)
+        qd = torch.from_numpy(q).to(dev)
+        Lq = np.random.default_rng(19).choice(np.array([32, 64, 128, 256], np.int32), nq_total)
+        Lt = torch.from_numpy(Lq).to(dev)
+
+        def score(i_, d_, s_):
+            return recall_at(d_[:1000].cpu().numpy().view(np.uint32), kth)
+
+        ns = min(10000, nq_total)
+        t = time.time()
+        tuned = autotune.tune(ix, qd[:ns].contiguous(), 10, 256, cache_path=None, reps=1,
+                              passes=1, score=score,
+                              space={"delay": (0, 1, 2), "beam_width": (1, 2),
+                                     "persistent": (False, True)},
+                              progress=lambda row: log("batched-file tune %s" % row),
+                              L_per_query=Lt[:ns].contiguous())
+        t_tune = time.time() - t
+        kw = autotune.search_kwargs(tuned["params"], {"L_per_query": Lt})
+        t = time.perf_counter()
+        ids, dists, steps = fa.search(ix, qd, k=10, L=256, **kw)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        out = {"workload": "%d x 100 i8, R=48, 512 B records in a file (O_DIRECT)" % n,
+               "queries": nq_total, "L": [32, 64, 128, 256], "k": 10,
+               "params": tuned["params"], "qps": round(nq_total / el, 1),
+               "seconds": round(el, 2),
+               "recall@10_first_1000": round(score(ids, dists, steps), 4),
+               "mean_steps": round(float(steps.cpu().numpy().view(np.uint32).mean()), 1),
+               "default_sample_qps": round(ns / (tuned["default"]["ms"] / 1e3), 1),
+               "tuned_sample_qps": round(ns / (tuned["ms"] / 1e3), 1),
+               "tune_s": round(t_tune, 1), "graph_build_s": round(t_graph, 1),
+               "write_s": round(t_save, 1), "direct_io": ix.info()["direct_io"]}
+        ix.close()
+    finally:
+        shutil.rmtree(tmpd, ignore_errors=True)
+    log("batched-file: %s" % out)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,6 +287,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the autotuned uneven-L batch")
     ap.add_argument("--batched-queries", type=int, default=100000)
+    ap.add_argument("--batched-file-n", type=int, default=0,
+                    help="also run the batched form at scale: this many int8/100 vectors, "
+                         "records in a file (off by default: minutes of graph build)")
     ap.add_argument("--no-hbm-tier", action="store_true",
                     help="skip the same search with the records in HBM")
     ap.add_argument("--no-transports", action="store_true",
@@ -440,6 +524,10 @@ def main():
         log("batched: %s" % batched)
         del qb, ob
 
+    batched_file = None
+    if args.batched_file_n:
+        batched_file = batched_file_leg(fa, torch, dev, args.batched_file_n, args.batched_queries)
+
     # ---- the same index with its records in HBM: the kernel without the host
     # link in the way (where the HBM roofline applies)
     hbm_tier = None
@@ -593,6 +681,7 @@ def main():
         "concurrency": concurrency,
         "schedules": schedules,
         "batched": batched,
+        "batched_file": batched_file,
         "records_in_hbm": hbm_tier,
         "transports": transports,
         "serving": serving,

@@ -92,11 +92,12 @@ def measure(index, queries, k, L, params, reps=3, score=None, **extra):
 
 
 def tune(index, queries, k, L, space=None, reps=3, cache_path=DEFAULT_CACHE, use_cache=True,
-         score=None, score_slack=0.001, passes=2, start=None, **extra):
+         score=None, score_slack=0.001, passes=2, start=None, progress=None, **extra):
     """Coordinate descent over `space` from `start` (default DEFAULT).
     Returns {"params", "ms", "score", "key", "table"}; `table` lists every
     setting tried with its time and score (None where the launch failed,
-    e.g. a tile whose LDS need exceeds the CU)."""
+    e.g. a tile whose LDS need exceeds the CU).  `progress`, if given, is
+    called with each new table row."""
     uneven = extra.get("L_per_query") is not None or extra.get("k_per_query") is not None
     key = cache_key(index, L, queries.shape[0], uneven)
     cache = {}
@@ -127,6 +128,8 @@ def tune(index, queries, k, L, space=None, reps=3, cache_path=DEFAULT_CACHE, use
                 seen[t] = {"params": dict(p), "ms": round(ms, 4), "score": q}
             except Exception as e:  # noqa: BLE001 -- recorded, setting skipped
                 seen[t] = {"params": dict(p), "ms": None, "score": None, "error": str(e)}
+            if progress is not None:
+                progress(seen[t])
         return seen[t]
 
     base = run(cur)

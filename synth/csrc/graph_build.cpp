@@ -32,6 +32,9 @@
 // compared as float with ties broken by id.
 #include <algorithm>
 #include <atomic>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -87,9 +90,27 @@ uint64_t splitmix64(uint64_t &s) {
   return z ^ (z >> 31);
 }
 
-void parallel_for(int64_t n, int threads, const std::function<void(int64_t)> &fn) {
+// Phase reports on stderr when FLASHANN_BUILD_PROGRESS is set (long builds
+// print as they go).
+struct Progress {
+  bool on = std::getenv("FLASHANN_BUILD_PROGRESS") != nullptr;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  void operator()(const char *what, long long a = -1, long long b = -1) const {
+    if (!on) return;
+    const double s =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (a >= 0) std::fprintf(stderr, "[graph %7.1fs] %s %lld/%lld\n", s, what, a, b);
+    else std::fprintf(stderr, "[graph %7.1fs] %s\n", s, what);
+    std::fflush(stderr);
+  }
+};
+
+// Run fn(0..n-1) on `threads` threads in chunks; with a label, the thread
+// that completes each tenth of the items reports it.
+void parallel_for(int64_t n, int threads, const std::function<void(int64_t)> &fn,
+                  const Progress *progress = nullptr, const char *label = nullptr) {
   if (threads < 1) threads = 1;
-  std::atomic<int64_t> next(0);
+  std::atomic<int64_t> next(0), done(0);
   const int64_t chunk = 64;
   auto work = [&]() {
     for (;;) {
@@ -97,6 +118,10 @@ void parallel_for(int64_t n, int threads, const std::function<void(int64_t)> &fn
       if (s >= n) break;
       int64_t e = std::min(n, s + chunk);
       for (int64_t i = s; i < e; i++) fn(i);
+      if (progress && label) {
+        const int64_t before = done.fetch_add(e - s), after = before + (e - s);
+        if (after * 10 / n != before * 10 / n) (*progress)(label, after, n);
+      }
     }
   };
   std::vector<std::thread> th;
@@ -226,6 +251,7 @@ int synth_build_graph(const void *base, int64_t n, int32_t d, int32_t dtype, int
       (dtype != DT_U8 && dtype != DT_I8 && dtype != DT_F32))
     return -22;
   const Data D{base, n, d, dtype};
+  const Progress progress;
   const int64_t medoid = synth_medoid(base, n, d, dtype);
   if (entry_out) *entry_out = (int32_t)medoid;
   if (n == 1) {
@@ -262,7 +288,9 @@ int synth_build_graph(const void *base, int64_t n, int32_t d, int32_t dtype, int
     for (int64_t p = 0; p < Hn; p++) v.emplace_back(D.dist(i, hubs[p]), (int32_t)p);
     keep_smallest(v, M);
     hub_near[i] = std::move(v);
-  });
+  }, &progress, "nearest hubs");
+
+  progress("nearest hubs");
 
   // ---- 1. kNN pools.
   std::vector<std::vector<Cand>> pools(n);
@@ -274,7 +302,7 @@ int synth_build_graph(const void *base, int64_t n, int32_t d, int32_t dtype, int
         if (j != i) v.emplace_back(D.dist(i, j), (int32_t)j);
       keep_smallest(v, K);
       pools[i] = std::move(v);
-    });
+    }, &progress, "kNN pools");
   } else {
     std::vector<std::vector<int32_t>> members(Hn);
     for (int64_t i = 0; i < n; i++) members[hub_near[i][0].second].push_back((int32_t)i);
@@ -293,12 +321,15 @@ int synth_build_graph(const void *base, int64_t n, int32_t d, int32_t dtype, int
           if (j != i) v.emplace_back(D.dist(i, j), j);
       keep_smallest(v, K);
       pools[i] = std::move(v);
-    });
+    }, &progress, "kNN pools");
   }
+
+  progress("kNN pools");
 
   // ---- 2. alpha-pruning.
   std::vector<std::vector<int32_t>> out(n);
-  parallel_for(n, threads, [&](int64_t i) { robust_prune(D, pools[i], R, alpha, out[i]); });
+  parallel_for(n, threads, [&](int64_t i) { robust_prune(D, pools[i], R, alpha, out[i]); },
+               &progress, "pruning");
 
   // ---- 3. reverse edges (lists built in id order), re-pruned when too long.
   {
@@ -454,6 +485,7 @@ int synth_build_graph(const void *base, int64_t n, int32_t d, int32_t dtype, int
   fill();
   write();
   repair();
+  progress("pool graph");
 
   // ---- 7. Vamana-style refinement passes.
   if (passes > 0 && n > 2) {
@@ -570,11 +602,14 @@ int synth_build_graph(const void *base, int64_t n, int32_t d, int32_t dtype, int
             if (m < R && x != q) row[m++] = x;
           for (; m < R; m++) row[m] = -1;
         }
+        const int64_t nb = (n + B - 1) / B, bi = b0 / B + 1;
+        if (bi % 16 == 0 || bi == nb) progress("refinement batch", bi, nb);
       }
     }
     fill();
     write();
     repair();
+    progress("refined graph");
   }
   return 0;
 }
