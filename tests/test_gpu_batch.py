@@ -123,3 +123,40 @@ def test_graph_replays_match_eager(cfg1):
                 check(*got, oracle_uneven(base, adj, entry, q[perm], ks, Ls, 10, 1))
         finally:
             g.close()
+
+
+def test_autotuner_picks_a_valid_setting(cfg1):
+    """The tuner's choice runs, stays within the in-flight limit, and its
+    results-neutral parameters leave the results unchanged."""
+    from paper_2507_10070_amd import autotune
+
+    base, q, adj, entry = cfg1
+    dev = "cuda:0"
+    qd = torch.from_numpy(q).to(dev)
+    ks, Ls = uneven(len(q), 31)
+    Lt = torch.from_numpy(Ls).to(dev)
+    ref = oracle_uneven(base, adj, entry, q, np.full(len(q), 10, np.int32), Ls, 10, 1)
+    kth = ref[1][:, 9]
+
+    def score(ids, dists, steps):
+        d = dists.cpu().numpy().view(np.uint32).astype(np.float64)
+        return float(np.minimum((d <= kth[:, None]).sum(1), 10).mean() / 10)
+
+    with fa.Index(base, adj, entry, 256, fa.TIER_HOST) as ix:
+        res = autotune.tune(ix, qd, 10, 128, cache_path=None, reps=1, passes=1, score=score,
+                            space={"delay": (0, 1, 2), "beam_width": (1, 2),
+                                   "waves_per_block": (1, 4), "persistent": (False, True)},
+                            L_per_query=Lt)
+        p = res["params"]
+        assert autotune.valid(p)
+        assert res["score"] >= res["default"]["score"] - 0.001
+        assert all(r["ms"] is not None for r in res["table"])
+        # tiles that do not change results: the same search with other tiles
+        kw = autotune.search_kwargs(p, {"L_per_query": Lt})
+        a = fa.search(ix, qd, k=10, L=128, **kw)
+        kw2 = dict(kw, waves_per_block=3, persistent=not p.get("persistent", False))
+        kw2.pop("order", None)
+        b = fa.search(ix, qd, k=10, L=128, **kw2)
+        torch.cuda.synchronize()
+        for x, y in zip(a, b):
+            assert torch.equal(x, y)
