@@ -6,5 +6,5 @@ unspecified) and random-link sample graphs -- and none of the search method's
 arithmetic: there is no best-first search, no candidate list and no result
 selection here.  Both the GPU path and the oracle consume what it produces.
 """
-from .gmm import CONFIGS, WorkloadConfig, make_base, make_queries, make_dataset  # noqa: F401
+from .gmm import WORKLOADS, Workload, make_base, make_queries, make_dataset  # noqa: F401
 from .graph import build_graph, random_graph, medoid  # noqa: F401

@@ -7,8 +7,9 @@ Recipes (component weights uniform; numpy PCG64):
   u8  : centres ~ U[40, 215]^d, x = rint(c + 20 z), clipped to [0, 255]
   i8  : centres ~ U[-88, 87]^d, x = rint(c + 20 z), clipped to [-128, 127]
   f32 : centres = normalize(N(0, I)), x = normalize(c + 0.1 z), in fp64, cast
-Seeds: base 1000 + c, queries 2000 + c for workload c; the centres come from
-the base seed's first draws so that base and queries share them.
+Seeds: base 1000 + o, queries 2000 + o (graphs 3000 + o) for a workload with
+seed offset o; the centres come from the base seed's first draws so that base
+and queries share them.
 """
 from __future__ import annotations
 
@@ -18,8 +19,8 @@ import numpy as np
 
 
 @dataclasses.dataclass(frozen=True)
-class WorkloadConfig:
-    cid: int
+class Workload:
+    seed_offset: int
     name: str
     n: int
     d: int
@@ -37,17 +38,18 @@ class WorkloadConfig:
         return {"u8": np.uint8, "i8": np.int8, "f32": np.float32}[self.dtype]
 
 
-CONFIGS = {
-    1: WorkloadConfig(1, "strict in-HBM, 10k u8/128", 10_000, 128, "u8", 16, 32, 256, "hbm",
-                      100, 10, (64,)),
-    2: WorkloadConfig(2, "1M u8/128 records in pinned host DRAM", 1_000_000, 128, "u8", 256, 64,
-                      512, "host", 10_000, 10, (32, 48, 64, 96, 128, 192, 256)),
-    3: WorkloadConfig(3, "10M f32/96 records on NVMe", 10_000_000, 96, "f32", 1024, 64, 4096,
-                      "nvme", 10_000, 10, (128,)),
-    4: WorkloadConfig(4, "100M i8/100 batched, uneven L", 100_000_000, 100, "i8", 4096, 48, 512,
-                      "nvme", 100_000, 10, (32, 64, 128, 256)),
-    5: WorkloadConfig(5, "100M u8/128 serving", 100_000_000, 128, "u8", 4096, 64, 512, "nvme",
-                      100_000, 10, (32, 64, 128, 256)),
+# The workloads of the measurements, named by what they are.
+WORKLOADS = {
+    "10k-u8-128": Workload(1, "10k u8/128, records in HBM", 10_000, 128, "u8", 16, 32, 256,
+                           "hbm", 100, 10, (64,)),
+    "1m-u8-128": Workload(2, "1M u8/128, records in pinned host DRAM", 1_000_000, 128, "u8",
+                          256, 64, 512, "host", 10_000, 10, (32, 48, 64, 96, 128, 192, 256)),
+    "10m-f32-96": Workload(3, "10M f32/96, 4 KB records in a file", 10_000_000, 96, "f32",
+                           1024, 64, 4096, "nvme", 10_000, 10, (128,)),
+    "100m-i8-100": Workload(4, "100M i8/100 batched, uneven L", 100_000_000, 100, "i8", 4096,
+                            48, 512, "nvme", 100_000, 10, (32, 64, 128, 256)),
+    "100m-u8-128": Workload(5, "100M u8/128 serving", 100_000_000, 128, "u8", 4096, 64, 512,
+                            "nvme", 100_000, 10, (32, 64, 128, 256)),
 }
 
 
@@ -90,10 +92,10 @@ def make_queries(nq: int, d: int, dtype: str, components: int, base_seed: int,
     return _points(np.random.Generator(np.random.PCG64(query_seed)), centres, nq, dtype)
 
 
-def make_dataset(cfg: WorkloadConfig, n: int | None = None, nq: int | None = None):
+def make_dataset(cfg: Workload, n: int | None = None, nq: int | None = None):
     """Base vectors and queries of workload ``cfg`` (optionally truncated sizes)."""
     n = cfg.n if n is None else n
     nq = cfg.nq if nq is None else nq
-    base = make_base(n, cfg.d, cfg.dtype, cfg.components, 1000 + cfg.cid)
-    queries = make_queries(nq, cfg.d, cfg.dtype, cfg.components, 1000 + cfg.cid, 2000 + cfg.cid)
+    base = make_base(n, cfg.d, cfg.dtype, cfg.components, 1000 + cfg.seed_offset)
+    queries = make_queries(nq, cfg.d, cfg.dtype, cfg.components, 1000 + cfg.seed_offset, 2000 + cfg.seed_offset)
     return base, queries

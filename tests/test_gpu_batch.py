@@ -16,7 +16,7 @@ fa = pytest.importorskip("paper_2507_10070_amd")
 
 @pytest.fixture(scope="module")
 def cfg1():
-    cfg = synth.CONFIGS[1]
+    cfg = synth.WORKLOADS["10k-u8-128"]
     base, q = synth.make_dataset(cfg)
     adj, entry = synth.build_graph(base, cfg.R, 3001, threads=8)
     return base, q, adj, entry
@@ -75,7 +75,7 @@ def test_uneven_batch_parity(cfg1, persistent, delay, ordered):
     check(ids, dists, steps, oracle_uneven(base, adj, entry, q, ks, Ls, kmax, delay))
 
 
-def test_uneven_batch_i8_config4_shape():
+def test_uneven_batch_i8_d100_r48():
     """i8, d = 100, R = 48, 512 B records, L uniform over {32, 64, 128, 256} in
     one persistent kernel (the batched workload's shape at a reduced N)."""
     base = synth.make_base(30000, 100, "i8", 64, 1004)

@@ -20,17 +20,17 @@ SAMPLE = 256
 
 
 @pytest.fixture(scope="module")
-def config2():
-    cfg = synth.CONFIGS[2]
+def w1m():
+    cfg = synth.WORKLOADS["1m-u8-128"]
     base, q = synth.make_dataset(cfg)
-    adj, entry = synth.build_graph(base, cfg.R, 3000 + cfg.cid, threads=16)
+    adj, entry = synth.build_graph(base, cfg.R, 3000 + cfg.seed_offset, threads=16)
     sample = np.sort(np.random.default_rng(12345).choice(cfg.nq, SAMPLE, replace=False))
     return cfg, base, q, adj, entry, sample
 
 
 @pytest.mark.parametrize("transport", ["direct", "agent"])
-def test_config2_sampled_parity(config2, transport):
-    cfg, base, q, adj, entry, sample = config2
+def test_1m_sampled_parity(w1m, transport):
+    cfg, base, q, adj, entry, sample = w1m
     tr = fa.TRANSPORT_DIRECT if transport == "direct" else fa.TRANSPORT_AGENT
     qd = torch.from_numpy(q).to("cuda:0")
     with fa.Index(base, adj, entry, cfg.slot, fa.TIER_HOST) as ix:

@@ -26,7 +26,7 @@ def dev():
 
 @pytest.fixture(scope="module")
 def cfg1():
-    cfg = synth.CONFIGS[1]
+    cfg = synth.WORKLOADS["10k-u8-128"]
     base, q = synth.make_dataset(cfg)
     adj, entry = synth.build_graph(base, cfg.R, 3001, threads=8)
     return base, q, adj, entry
@@ -62,7 +62,7 @@ def assert_int_parity(g, ref, check_trace=False):
 @pytest.mark.parametrize("tier", ["hbm", "host"])
 @pytest.mark.parametrize("delay", [0, 1])
 @pytest.mark.parametrize("L", [16, 64, 100, 200])
-def test_config1_parity(cfg1, tier, delay, L):
+def test_10k_u8_parity(cfg1, tier, delay, L):
     base, q, adj, entry = cfg1
     t = fa.TIER_HBM if tier == "hbm" else fa.TIER_HOST
     with fa.Index(base, adj, entry, 256, t) as ix:

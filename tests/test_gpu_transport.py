@@ -21,7 +21,7 @@ fa = pytest.importorskip("paper_2507_10070_amd")
 
 @pytest.fixture(scope="module")
 def cfg1():
-    cfg = synth.CONFIGS[1]
+    cfg = synth.WORKLOADS["10k-u8-128"]
     base, q = synth.make_dataset(cfg)
     adj, entry = synth.build_graph(base, cfg.R, 3001, threads=8)
     return base, q, adj, entry
