@@ -268,10 +268,17 @@ typedef struct ann_server ann_server;
 typedef struct {
   int32_t k_max, L_max, delay, waves_per_block, hash_bits, queue_cap, idle_polls;
   int32_t beam_width; /* W (0 = 1); (delay + 1) * W <= 8 */
+  int32_t transport;  /* ann_transport: AUTO (0) = AGENT for a FILE tier, else
+                         DIRECT.  With AGENT the server runs its own host
+                         agents and each resident GPU wave owns one request
+                         line for all the queries it serves (section 4.2) */
+  uint32_t spin_limit; /* AGENT: polls of a completion word before a query
+                          gives up with ANN_ETIMEDOUT (0 = 2^24) */
 } ann_server_opts;
 typedef struct {
   uint64_t tag;          /* the caller's tag */
-  int32_t status;        /* ANN_OK */
+  int32_t status;        /* ANN_OK, or ANN_EIO / ANN_ETIMEDOUT when a record read
+                            failed or never completed (AGENT; ids are then -1) */
   int32_t k;             /* results in ids/dists */
   const int32_t *ids;    /* host, valid until the next ann_server_poll */
   const void *dists;     /* host, uint32 (u8/i8) or float (f32), same lifetime */
@@ -300,10 +307,10 @@ int ann_server_poll(ann_server *s, ann_result *out, int32_t max, int32_t *n_out,
                     int32_t timeout_us);
 /* Bulk form of ann_server_poll into caller-owned host arrays of `max` rows:
  * tags, ks, ids (max x k_max, padded with -1), dists (max x k_max, padded
- * with 0xFFFFFFFF bits), and optional steps, submit_us, done_us. */
+ * with 0xFFFFFFFF bits), and optional steps, submit_us, done_us, status. */
 int ann_server_poll_into(ann_server *s, int32_t max, uint64_t *tags, int32_t *ks, int32_t *ids,
                          void *dists, uint32_t *steps, double *submit_us, double *done_us,
-                         int32_t *n_out, int32_t timeout_us);
+                         int32_t *status, int32_t *n_out, int32_t timeout_us);
 int ann_server_stats_get(ann_server *s, ann_server_stats *out);
 /* Finish every admitted and waiting query, stop the kernel, release all. */
 int ann_server_close(ann_server *s);

@@ -35,14 +35,14 @@ Agent::~Agent() {
 }
 
 void Agent::arm(AgentRequest *req, uint32_t *cpl, uint8_t *stage, int64_t nq,
-                int64_t stage_stride, int slots) {
+                int64_t stage_stride, int slots, uint32_t start_seq) {
   slots_ = slots < 1 ? 1 : (slots > kMaxSlots ? kMaxSlots : slots);
   req_ = req;
   cpl_ = cpl;
   stage_ = stage;
   nq_ = nq;
   stage_stride_ = stage_stride;
-  done_.assign((size_t)nq, 0u);
+  done_.assign((size_t)nq, start_seq);
   armed_.store(true);  // seq_cst: publishes the fields above
 }
 
@@ -99,10 +99,10 @@ void Agent::run(int t) {
     for (int64_t q = q0; q < q1; q++) {
       uint32_t d = done_[(size_t)q];
       for (;;) {
-        const uint64_t w =
-            __atomic_load_n(&req_[q].slot[(d + 1) % (uint32_t)slots_], __ATOMIC_ACQUIRE);
-        if ((uint32_t)w != d + 1) break;
-        d++;
+        const uint32_t nx = next_seq(d, slots_);
+        const uint64_t w = __atomic_load_n(&req_[q].slot[nx % (uint32_t)slots_], __ATOMIC_ACQUIRE);
+        if ((uint32_t)w != nx) break;
+        d = nx;
         serve(q, d, (uint32_t)(w >> 32), bounce);
         any = true;
       }

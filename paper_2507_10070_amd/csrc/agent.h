@@ -24,6 +24,15 @@ namespace fa {
 // consuming the request that held it.  One 64 B line per query, so that no
 // two queries (and no GPU wave and agent thread pair) share a cache line.
 constexpr int kMaxSlots = 8;
+
+// Request numbers run 1, 2, ..., M, 1, 2, ... with M the largest multiple of
+// the slot count below 2^30 (0 means "no request"; bit 31 of a completion word
+// is the error flag; s % slots stays continuous across the wrap).  The GPU
+// side steps through the same sequence.
+inline uint32_t next_seq(uint32_t s, int slots) {
+  const uint32_t M = (0x40000000u / (uint32_t)slots) * (uint32_t)slots;
+  return s >= M ? 1u : s + 1u;
+}
 struct alignas(64) AgentRequest {
   uint64_t slot[kMaxSlots];
 };
@@ -67,8 +76,10 @@ class Agent {
   // kCplStride x nq completion words and `stage` `slots` staging slots of
   // `stage_stride` bytes per query (slot s % slots for request s, slots in
   // [1, kMaxSlots]).  The caller zeroes req/cpl.
+  // `start_seq` is the request number each line has already used (0 for
+  // fresh lines).
   void arm(AgentRequest *req, uint32_t *cpl, uint8_t *stage, int64_t nq, int64_t stage_stride,
-           int slots);
+           int slots, uint32_t start_seq = 0);
   // Stop serving; returns once no agent thread touches the arrays any more.
   void disarm();
 

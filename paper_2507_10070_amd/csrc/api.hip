@@ -769,10 +769,38 @@ int ann_graph_free(ann_graph *g) {
 // Shared with server.cpp: error reporting and the index fields of a search.
 int ann_internal_fail(int code, const char *msg) { return fail(code, "%s", msg); }
 
+// Transport of a server over this index (AUTO: AGENT for a FILE tier, else
+// DIRECT) and, for AGENT, an agent of its own reading the index's records;
+// *stage_stride is the staging slot size it needs.
+int ann_internal_server_transport(ann_index *ix, int32_t requested, int32_t *tr,
+                                  fa::Agent **agent, int64_t *stage_stride) {
+  int t = requested;
+  if (t == ANN_TRANSPORT_AUTO)
+    t = ix->tier == ANN_TIER_FILE ? ANN_TRANSPORT_AGENT : ANN_TRANSPORT_DIRECT;
+  if (t != ANN_TRANSPORT_DIRECT && t != ANN_TRANSPORT_AGENT)
+    return fail(ANN_EINVAL, "transport=%d", requested);
+  if (t == ANN_TRANSPORT_DIRECT && ix->tier == ANN_TIER_FILE)
+    return fail(ANN_EINVAL, "a file tier is served through the agent transport only");
+  if (t == ANN_TRANSPORT_AGENT && ix->tier == ANN_TIER_HBM)
+    return fail(ANN_EINVAL, "HBM records are read directly by the kernel");
+  *tr = t == ANN_TRANSPORT_AGENT ? fa::TR_AGENT : fa::TR_DIRECT;
+  *agent = nullptr;
+  *stage_stride = 0;
+  if (t == ANN_TRANSPORT_AGENT) {
+    const bool file = ix->tier == ANN_TIER_FILE;
+    const int32_t io = file && ix->direct_io ? (int32_t)round_up(ix->rec_bytes, 512) : ix->rec_bytes;
+    const int th = ix->agent_threads > 0 ? ix->agent_threads : default_agent_threads(file);
+    *agent = new (std::nothrow) fa::Agent(file ? nullptr : (const uint8_t *)ix->rec_host, ix->fd,
+                                          ix->direct_io, ix->slot, ix->rec_bytes, io, th);
+    if (!*agent) return fail(ANN_ENOMEM, "server agent");
+    (*agent)->faults = ix->faults;
+    *stage_stride = round_up(io, 512);
+  }
+  return ANN_OK;
+}
+
 int ann_internal_server_args(ann_index *ix, int32_t k_max, int32_t L_max, int32_t hash_bits,
                              fa::SearchArgs *base, int32_t *dtype) {
-  if (ix->tier == ANN_TIER_FILE)
-    return fail(ANN_EINVAL, "the server reads records directly: HBM or HOST tier");
   if (hash_bits < 6 || hash_bits > 14) return fail(ANN_EINVAL, "hash_bits=%d", hash_bits);
   fa::SearchArgs &a = *base;
   a = fa::SearchArgs{};

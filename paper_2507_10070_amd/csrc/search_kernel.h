@@ -44,6 +44,8 @@ struct SearchArgs {
   int32_t pslots;          // request slots per query: at least the requests in flight
   uint32_t spin_limit;     // polls of a completion word before the query times out
   int32_t *status;         // nq per-query status, device: 0, -5 (read error), -110 (timeout)
+  uint32_t *line_seq;      // optional, device: last request number per transport line, kept
+                           // across the queries a line serves (persistent server waves)
   int32_t trace_cap;
   int64_t nq, n, slot;
   int32_t nav_stride, qbytes, vec_pad, ids_off, rec_chunks;
@@ -74,6 +76,9 @@ struct ServerArgs {
   uint32_t *res_dists;      // host-mapped, nslots x k_max
   uint32_t *res_steps;      // host-mapped, nslots
   uint32_t *done;           // host-mapped, nslots x 16 (one 64 B line per slot)
+  int32_t *res_status;      // host-mapped, nslots: written only when a record read fails
+                            // (-5) or times out (-110); the host clears it per use
+  int32_t transport;        // TR_DIRECT, or TR_AGENT: transport line = resident wave index
   uint32_t idle_limit;      // empty polls before a wave leaves
 };
 // The schedule follows a.base.delay and a.base.beam, as in launch_search.

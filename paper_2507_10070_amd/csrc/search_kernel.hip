@@ -213,6 +213,8 @@ struct QueryIO {
   uint32_t *dists;    // row of `width` distances
   uint32_t *steps;    // optional
   int L, k, width;    // list size, results, row width (entries k..width-1 padded)
+  int64_t line;       // TR_AGENT: request / completion / staging line
+  int32_t *status;    // TR_AGENT: where a failed read is reported (may be host memory)
 };
 
 __device__ __forceinline__ QueryIO batch_io(const SearchArgs &A, int64_t qi) {
@@ -234,6 +236,8 @@ __device__ __forceinline__ QueryIO batch_io(const SearchArgs &A, int64_t qi) {
   io.L = L;
   io.k = k > L ? L : k;
   io.width = A.k_stride;
+  io.line = qi;
+  io.status = A.status ? A.status + qi : nullptr;
   return io;
 }
 
@@ -291,7 +295,8 @@ struct Searcher {
     }
     qq = group8_sum(a);
     steps = rows = mismatches = 0;
-    seq = 0;
+    // request numbers continue per line when lines outlive queries
+    seq = A.line_seq ? A.line_seq[io.line] : 0u;
     failed = false;
     t_fetch = t_comp = 0;
   }
@@ -369,6 +374,15 @@ struct Searcher {
     return s % (uint32_t)A.pslots;
   }
 
+  // Request numbers run 1, 2, ..., M, 1, 2, ... with M the largest multiple
+  // of pslots below 2^30: 0 stays "no request", bit 31 of a completion word
+  // stays free for the error flag, and s % pslots stays continuous across the
+  // wrap.  The host agents step through the same sequence.
+  __device__ __forceinline__ uint32_t next_seq(uint32_t s) const {
+    const uint32_t M = (0x40000000u / (uint32_t)A.pslots) * (uint32_t)A.pslots;
+    return s >= M ? 1u : s + 1u;
+  }
+
   // Start obtaining the record of v.  TR_DIRECT: the load itself (in flight
   // until used); `real` is ignored so that the load is unconditional.
   // TR_AGENT: post request seq+1 for v as one 64-bit system-scope store of
@@ -380,9 +394,9 @@ struct Searcher {
   __device__ __forceinline__ uint4 issue(uint32_t v, bool real) {
     if (TR == TR_DIRECT) return fetch(v);
     if (!real || failed) return make_uint4(0, 0, 0, 0);
-    seq++;
+    seq = next_seq(seq);
     if (lane == 0)
-      __hip_atomic_store(A.req + 8 * qi + pslot(seq), ((uint64_t)v << 32) | seq, __ATOMIC_RELAXED,
+      __hip_atomic_store(A.req + 8 * io.line + pslot(seq), ((uint64_t)v << 32) | seq, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_SYSTEM);
     return make_uint4(seq, 0, 0, 0);
   }
@@ -397,7 +411,7 @@ struct Searcher {
     if (failed || s == 0) return make_uint4(0, 0, 0, 0);
     uint32_t c = 0;
     if (lane == 0) {
-      const uint32_t *w = A.cpl + 16 * qi + pslot(s);
+      const uint32_t *w = A.cpl + 16 * io.line + pslot(s);
       uint32_t spins = 0, nap = 1;
       for (;;) {
         c = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -415,7 +429,9 @@ struct Searcher {
     c = (uint32_t)__builtin_amdgcn_readfirstlane((int)c);
     if (c == kTimedOut || (c & kCplErr)) {
       failed = true;
-      if (lane == 0) A.status[qi] = c == kTimedOut ? -110 : -5;
+      if (lane == 0 && io.status)
+        __hip_atomic_store(io.status, c == kTimedOut ? -110 : -5, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
       return make_uint4(0, 0, 0, 0);
     }
     // The staged bytes are read with system-scope loads, issued after the
@@ -423,7 +439,7 @@ struct Searcher {
     // fence (which would invalidate the whole L2 on every record) is needed.
     const int ch = lane < A.rec_chunks ? lane : A.rec_chunks - 1;
     const uint32_t *src =
-        (const uint32_t *)(A.stage + (qi * A.pslots + pslot(s)) * A.stage_stride + 16 * ch);
+        (const uint32_t *)(A.stage + (io.line * A.pslots + pslot(s)) * A.stage_stride + 16 * ch);
     uint4 r;
     r.x = __hip_atomic_load(src + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     r.y = __hip_atomic_load(src + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -673,6 +689,7 @@ struct Searcher {
       }
     }
     if (lane == 0) {
+      if (A.line_seq) A.line_seq[io.line] = seq;
       if (io.steps) {
         if (io.coherent)
           __hip_atomic_store(io.steps, steps, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -711,7 +728,7 @@ __device__ __forceinline__ void run_query(const SearchArgs &A, uint8_t *lds, int
     const int W = A.beam, lim = A.delay * A.beam;
     const uint32_t dummy = (uint32_t)A.entry;
     int head = 0, len = 0;
-    uint32_t cseq = 0;  // TR_AGENT: requests consumed so far
+    uint32_t cseq = s.seq;  // TR_AGENT: request number of the last one consumed
     uint4 nxt = make_uint4(0, 0, 0, 0);
     bool have_nxt = false;
     for (;;) {
@@ -742,7 +759,8 @@ __device__ __forceinline__ void run_query(const SearchArgs &A, uint8_t *lds, int
           have_nxt = more;
         } else {
           uint4 unused;
-          s.template process<false>(u, make_uint4(++cseq, 0, 0, 0), 0u, false, unused);
+          cseq = s.next_seq(cseq);
+          s.template process<false>(u, make_uint4(cseq, 0, 0, 0), 0u, false, unused);
         }
       }
     }
@@ -982,7 +1000,7 @@ __global__ void reset_ctl(uint32_t *ctl, uint32_t words) {
 // while idle holds no ticket (see the claim loop).  The entry is read with
 // system-scope loads because ring memory is rewritten by host copies; results
 // go to host-mapped rows, then the slot's done word tells the host.
-template <int DT, int CPL, int DELAY>
+template <int DT, int CPL, int DELAY, int TR>
 __global__ void __launch_bounds__(256) server_kernel(ServerArgs S) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int wave = threadIdx.x >> 6;
@@ -1048,7 +1066,11 @@ __global__ void __launch_bounds__(256) server_kernel(ServerArgs S) {
     io.L = L;
     io.k = k;
     io.width = k;
-    run_query<DT, CPL, DELAY, TR_DIRECT>(S.base, lds, (int64_t)slot, io);
+    // TR_AGENT: each resident wave owns one transport line for all the
+    // queries it serves (its request numbers continue in line_seq)
+    io.line = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    io.status = S.res_status ? S.res_status + slot : nullptr;
+    run_query<DT, CPL, DELAY, TR>(S.base, lds, (int64_t)slot, io);
     // The result rows were written with system-scope (write-through) stores:
     // once they have completed, the done word may follow.  This avoids a
     // release fence, which would write back the whole L2 for every query.
@@ -1184,14 +1206,14 @@ hipError_t launch_search(const SearchArgs &a, int dtype, int transport, int wave
   }
 }
 
-template <int DT, int CPL, int DELAY>
+template <int DT, int CPL, int DELAY, int TR>
 static hipError_t launch_server_t(const ServerArgs &a, int wpb, int64_t *resident,
                                   hipStream_t st) {
   const size_t lds = (size_t)a.base.lds_per_wave * wpb;
   const int threads = 64 * wpb;
   int per_cu = 0, dev = 0, cus = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per_cu, (const void *)server_kernel<DT, CPL, DELAY>, threads, lds);
+      &per_cu, (const void *)server_kernel<DT, CPL, DELAY, TR>, threads, lds);
   if (e != hipSuccess) return e;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
   if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
@@ -1199,18 +1221,25 @@ static hipError_t launch_server_t(const ServerArgs &a, int wpb, int64_t *residen
   const int64_t blocks = (int64_t)(per_cu > 0 ? per_cu : 1) * cus;
   if (resident) *resident = blocks * wpb;
   if (!st) return hipSuccess;  // size query only
-  hipLaunchKernelGGL((server_kernel<DT, CPL, DELAY>), dim3((unsigned)blocks), dim3(threads), lds,
-                     st, a);
+  hipLaunchKernelGGL((server_kernel<DT, CPL, DELAY, TR>), dim3((unsigned)blocks), dim3(threads),
+                     lds, st, a);
   return hipGetLastError();
+}
+
+template <int DT, int CPL, int TR>
+static hipError_t launch_server_s(const ServerArgs &a, int wpb, int64_t *res, hipStream_t st) {
+  const int delay = a.base.delay, beam = a.base.beam;
+  if (delay < 0 || beam < 1 || (delay + 1) * beam > kMaxPipe) return hipErrorInvalidValue;
+  if (beam == 1 && delay == 0) return launch_server_t<DT, CPL, SCHED_STRICT, TR>(a, wpb, res, st);
+  if (beam == 1 && delay == 1)
+    return launch_server_t<DT, CPL, SCHED_RELAXED, TR>(a, wpb, res, st);
+  return launch_server_t<DT, CPL, SCHED_GENERIC, TR>(a, wpb, res, st);
 }
 
 template <int DT, int CPL>
 static hipError_t launch_server_d(const ServerArgs &a, int wpb, int64_t *res, hipStream_t st) {
-  const int delay = a.base.delay, beam = a.base.beam;
-  if (delay < 0 || beam < 1 || (delay + 1) * beam > kMaxPipe) return hipErrorInvalidValue;
-  if (beam == 1 && delay == 0) return launch_server_t<DT, CPL, SCHED_STRICT>(a, wpb, res, st);
-  if (beam == 1 && delay == 1) return launch_server_t<DT, CPL, SCHED_RELAXED>(a, wpb, res, st);
-  return launch_server_t<DT, CPL, SCHED_GENERIC>(a, wpb, res, st);
+  return a.transport == TR_AGENT ? launch_server_s<DT, CPL, TR_AGENT>(a, wpb, res, st)
+                                 : launch_server_s<DT, CPL, TR_DIRECT>(a, wpb, res, st);
 }
 
 template <int DT>

@@ -11,12 +11,15 @@
 // overlap on the device.
 #include <hip/hip_runtime.h>
 
+#include "agent.h"
+
 #include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -30,6 +33,8 @@
 int ann_internal_server_args(ann_index *ix, int32_t k_max, int32_t L_max, int32_t hash_bits,
                              fa::SearchArgs *base, int32_t *dtype);
 int ann_internal_fail(int code, const char *msg);
+int ann_internal_server_transport(ann_index *ix, int32_t requested, int32_t *tr,
+                                  fa::Agent **agent, int64_t *stage_stride);
 
 namespace {
 
@@ -57,6 +62,7 @@ struct Inflight {
 struct Done {
   uint64_t tag;
   int32_t k;
+  int32_t status;
   uint32_t steps;
   double submit_us, done_us;
   std::vector<int32_t> ids;
@@ -78,6 +84,14 @@ struct ann_server {
   uint8_t *h_stage = nullptr;
   int32_t *h_ids = nullptr;
   uint32_t *h_dists = nullptr, *h_steps = nullptr, *h_done = nullptr;
+  int32_t *h_status = nullptr;      // per slot, written by the GPU only on a failed read
+  // AGENT transport: one request line per resident wave, served by agents of
+  // this server's own for its whole life
+  std::unique_ptr<fa::Agent> agent;
+  fa::AgentRequest *h_req = nullptr;
+  uint32_t *h_cpl = nullptr;
+  uint8_t *h_tstage = nullptr;
+  uint32_t *d_line_seq = nullptr;
   hipStream_t st_kernel = nullptr, st_copy = nullptr;
   hipEvent_t ev_kernel = nullptr;
   bool kernel_live = false;
@@ -226,6 +240,8 @@ struct ann_server {
         d.submit_us = f.submit_us;
         d.done_us = now_us();
         d.steps = h_steps[s];
+        d.status = __atomic_load_n(&h_status[s], __ATOMIC_RELAXED);
+        if (d.status) __atomic_store_n(&h_status[s], 0, __ATOMIC_RELAXED);  // for the next use
         d.ids.assign(h_ids + (int64_t)s * k_max, h_ids + (int64_t)s * k_max + f.k);
         d.dists.assign(h_dists + (int64_t)s * k_max, h_dists + (int64_t)s * k_max + f.k);
         fresh.push_back(std::move(d));
@@ -272,6 +288,12 @@ namespace {
 
 void server_free(ann_server *s) {
   if (!s) return;
+  s->agent.reset();  // joins the agents before their arrays go
+  if (s->h_req) (void)hipHostFree(s->h_req);
+  if (s->h_cpl) (void)hipHostFree(s->h_cpl);
+  if (s->h_tstage) (void)hipHostFree(s->h_tstage);
+  if (s->d_line_seq) (void)hipFree(s->d_line_seq);
+  if (s->h_status) (void)hipHostFree(s->h_status);
   if (s->ev_kernel) (void)hipEventDestroy(s->ev_kernel);
   if (s->st_kernel) (void)hipStreamDestroy(s->st_kernel);
   if (s->st_copy) (void)hipStreamDestroy(s->st_copy);
@@ -336,6 +358,20 @@ int ann_server_open(ann_index *ix, size_t hbm_budget_bytes, const ann_server_opt
   }
   s->args.base.delay = o.delay;
   s->args.base.beam = o.beam_width;
+  s->args.base.pslots = std::max(2, (o.delay + 1) * o.beam_width);
+  {
+    int32_t tr = 0;
+    fa::Agent *ag = nullptr;
+    int64_t sstride = 0;
+    rc = ann_internal_server_transport(ix, o.transport, &tr, &ag, &sstride);
+    if (rc) {
+      server_free(s);
+      return rc;
+    }
+    s->agent.reset(ag);
+    s->args.transport = tr;
+    s->args.base.stage_stride = sstride;
+  }
   s->nav_stride = s->args.base.nav_stride;
   s->qbytes = s->args.base.qbytes;
   // Per admitted query the device holds one ring entry (control + query);
@@ -368,6 +404,7 @@ int ann_server_open(ann_index *ix, size_t hbm_budget_bytes, const ann_server_opt
       (e = hipHostMalloc((void **)&s->h_dists, slots * o.k_max * 4, fl)) != hipSuccess ||
       (e = hipHostMalloc((void **)&s->h_steps, slots * 4, fl)) != hipSuccess ||
       (e = hipHostMalloc((void **)&s->h_done, slots * 64, fl)) != hipSuccess ||
+      (e = hipHostMalloc((void **)&s->h_status, slots * 4, fl)) != hipSuccess ||
       (e = hipMemset(s->d_ctl, 0, 64 * sizeof(uint32_t))) != hipSuccess ||
       (e = hipStreamCreateWithFlags(&s->st_kernel, hipStreamNonBlocking)) != hipSuccess ||
       (e = hipStreamCreateWithFlags(&s->st_copy, hipStreamNonBlocking)) != hipSuccess ||
@@ -377,6 +414,33 @@ int ann_server_open(ann_index *ix, size_t hbm_budget_bytes, const ann_server_opt
                              "server buffers / streams");
   }
   std::memset(s->h_done, 0, (size_t)slots * 64);
+  std::memset(s->h_status, 0, (size_t)slots * 4);
+  s->args.res_status = mapped(s->h_status);
+  if (s->agent) {
+    // one line per resident wave (the transport line of wave w is w)
+    const int64_t G = resident, P = s->args.base.pslots, ss = s->args.base.stage_stride;
+    if ((e = hipHostMalloc((void **)&s->h_req, sizeof(fa::AgentRequest) * G, fl)) != hipSuccess ||
+        (e = hipHostMalloc((void **)&s->h_cpl, sizeof(uint32_t) * fa::kCplStride * G, fl)) !=
+            hipSuccess ||
+        (e = hipHostMalloc((void **)&s->h_tstage, G * P * ss, fl)) != hipSuccess ||
+        (e = hipMalloc(&s->d_line_seq, sizeof(uint32_t) * G)) != hipSuccess ||
+        (e = hipMemset(s->d_line_seq, 0, sizeof(uint32_t) * G)) != hipSuccess) {
+      server_free(s);
+      return ann_internal_fail(ANN_ENOMEM, "server transport buffers");
+    }
+    std::memset(s->h_req, 0, sizeof(fa::AgentRequest) * G);
+    std::memset(s->h_cpl, 0, sizeof(uint32_t) * fa::kCplStride * G);
+    s->args.base.req = mapped((uint64_t *)s->h_req);
+    s->args.base.cpl = mapped(s->h_cpl);
+    s->args.base.stage = mapped(s->h_tstage);
+    s->args.base.spin_limit = o.spin_limit ? o.spin_limit : (1u << 24);
+    s->args.base.line_seq = s->d_line_seq;
+    if (!s->args.base.req || !s->args.base.cpl || !s->args.base.stage) {
+      server_free(s);
+      return ann_internal_fail(ANN_EIO, "server transport buffers not mapped");
+    }
+    s->agent->arm(s->h_req, s->h_cpl, s->h_tstage, G, ss, (int)P);
+  }
   s->args.ring = s->d_ring;
   s->args.next = s->d_ctl;
   s->args.published = s->d_ctl + 16;
@@ -385,7 +449,8 @@ int ann_server_open(ann_index *ix, size_t hbm_budget_bytes, const ann_server_opt
   s->args.res_dists = mapped(s->h_dists);
   s->args.res_steps = mapped(s->h_steps);
   s->args.done = mapped(s->h_done);
-  if (!s->args.res_ids || !s->args.res_dists || !s->args.res_steps || !s->args.done) {
+  if (!s->args.res_ids || !s->args.res_dists || !s->args.res_steps || !s->args.done ||
+      !s->args.res_status) {
     server_free(s);
     return ann_internal_fail(ANN_EIO, "result rows not mapped");
   }
@@ -477,7 +542,7 @@ int ann_server_poll(ann_server *s, ann_result *out, int32_t max, int32_t *n_out,
   for (size_t i = 0; i < s->last_poll.size(); i++) {
     const Done &d = s->last_poll[i];
     out[i].tag = d.tag;
-    out[i].status = ANN_OK;
+    out[i].status = d.status;
     out[i].k = d.k;
     out[i].steps = d.steps;
     out[i].ids = d.ids.data();
@@ -492,7 +557,7 @@ int ann_server_poll(ann_server *s, ann_result *out, int32_t max, int32_t *n_out,
 
 int ann_server_poll_into(ann_server *s, int32_t max, uint64_t *tags, int32_t *ks, int32_t *ids,
                          void *dists, uint32_t *steps, double *submit_us, double *done_us,
-                         int32_t *n_out, int32_t timeout_us) {
+                         int32_t *status, int32_t *n_out, int32_t timeout_us) {
   if (!s || !n_out || max < 0 || (max > 0 && (!tags || !ks || !ids || !dists)))
     return ann_internal_fail(ANN_EINVAL, "NULL argument");
   *n_out = 0;
@@ -514,6 +579,7 @@ int ann_server_poll_into(ann_server *s, int32_t max, uint64_t *tags, int32_t *ks
     if (steps) steps[n] = d.steps;
     if (submit_us) submit_us[n] = d.submit_us;
     if (done_us) done_us[n] = d.done_us;
+    if (status) status[n] = d.status;
     s->done_q.pop_front();
     n++;
   }
@@ -555,6 +621,7 @@ int ann_server_close(ann_server *s) {
   if (e == hipSuccess) e = hipStreamSynchronize(s->st_copy);
   if (e == hipSuccess) e = hipStreamSynchronize(s->st_kernel);
   if (e != hipSuccess) rc = ann_internal_fail(ANN_EIO, hipGetErrorString(e));
+  if (s->agent) s->agent->disarm();
   server_free(s);
   return rc;
 }

@@ -58,7 +58,8 @@ class ServerOptions(ctypes.Structure):
     _fields_ = [("k_max", ctypes.c_int32), ("L_max", ctypes.c_int32), ("delay", ctypes.c_int32),
                 ("waves_per_block", ctypes.c_int32), ("hash_bits", ctypes.c_int32),
                 ("queue_cap", ctypes.c_int32), ("idle_polls", ctypes.c_int32),
-                ("beam_width", ctypes.c_int32)]
+                ("beam_width", ctypes.c_int32), ("transport", ctypes.c_int32),
+                ("spin_limit", ctypes.c_uint32)]
 
 
 class Result(ctypes.Structure):
@@ -121,7 +122,7 @@ def load_library(path: str = LIB_PATH):
     lib.ann_server_submit.restype = ctypes.c_int
     lib.ann_server_submit_batch.argtypes = [vp, vp, i64, vp, vp, vp, vp]
     lib.ann_server_submit_batch.restype = ctypes.c_int
-    lib.ann_server_poll_into.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp,
+    lib.ann_server_poll_into.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp,
                                          ctypes.POINTER(i32), i32]
     lib.ann_server_poll_into.restype = ctypes.c_int
     lib.ann_server_poll.argtypes = [vp, ctypes.POINTER(Result), i32, ctypes.POINTER(i32), i32]
@@ -362,13 +363,14 @@ class Server:
 
     def __init__(self, index: Index, hbm_budget_bytes: int, k_max: int = 100, L_max: int = 256,
                  delay: int = 1, waves_per_block: int = 0, hash_bits: int = 0,
-                 queue_cap: int = 0, idle_polls: int = 0, beam_width: int = 1):
+                 queue_cap: int = 0, idle_polls: int = 0, beam_width: int = 1,
+                 transport: int = TRANSPORT_AUTO, spin_limit: int = 0):
         self.index = index
         self.dtype = index.dtype
         self.d = index.d
         self.k_max = k_max
         opts = ServerOptions(k_max, L_max, delay, waves_per_block, hash_bits, queue_cap,
-                             idle_polls, beam_width)
+                             idle_polls, beam_width, transport, spin_limit)
         h = ctypes.c_void_p()
         _check(load_library().ann_server_open(index.handle, int(hbm_budget_bytes),
                                               ctypes.byref(opts), ctypes.byref(h)))
@@ -412,7 +414,8 @@ class Server:
 
     def drain(self, n_expected: int, timeout_s: float = 120.0, chunk: int = 8192):
         """Collect n_expected results with the bulk poll; returns numpy arrays
-        (tags, ks, ids [n, k_max], dists [n, k_max], steps, submit_us, done_us)."""
+        (tags, ks, ids [n, k_max], dists [n, k_max], steps, submit_us, done_us,
+        status: 0, or -5 / -110 for a failed or timed-out record read)."""
         import time
 
         dt = np.float32 if self.dtype == np.float32 else np.uint32
@@ -420,7 +423,8 @@ class Server:
                "ids": np.zeros((n_expected, self.k_max), np.int32),
                "dists": np.zeros((n_expected, self.k_max), np.uint32),
                "steps": np.zeros(n_expected, np.uint32),
-               "submit_us": np.zeros(n_expected), "done_us": np.zeros(n_expected)}
+               "submit_us": np.zeros(n_expected), "done_us": np.zeros(n_expected),
+               "status": np.zeros(n_expected, np.int32)}
         got = 0
         nn = ctypes.c_int32()
         end = time.time() + timeout_s
@@ -431,7 +435,8 @@ class Server:
                 self._h, m, out["tags"][got:].ctypes.data, out["ks"][got:].ctypes.data,
                 out["ids"][got:].ctypes.data, out["dists"][got:].ctypes.data,
                 out["steps"][got:].ctypes.data, out["submit_us"][got:].ctypes.data,
-                out["done_us"][got:].ctypes.data, ctypes.byref(nn), 2000))
+                out["done_us"][got:].ctypes.data, out["status"][got:].ctypes.data,
+                ctypes.byref(nn), 2000))
             got += nn.value
         for key in out:
             out[key] = out[key][:got]

@@ -28,6 +28,9 @@ int main(int argc, char **argv) {
   const int64_t n = 5000, slot = 512, copy = 384;
   const int64_t nq = argc > 1 ? atoll(argv[1]) : 64;
   const int agents = argc > 2 ? atoi(argv[2]) : 3;
+  // request numbers already used per line: "wrap" starts just below the
+  // point where they wrap around, so every line crosses it
+  const bool wrap = argc > 3 && std::strcmp(argv[3], "wrap") == 0;
   const int steps = 200;
   std::vector<uint8_t> records(n * slot);
   for (int64_t i = 0; i < n * slot; i++) records[i] = (uint8_t)((i * 2654435761ull) >> 13);
@@ -43,14 +46,16 @@ int main(int argc, char **argv) {
   const int P = 5;
   std::vector<uint8_t> stage(nq * P * stride, 0);
   std::memset(req.data(), 0, sizeof(AgentRequest) * nq);
-  agent.arm(req.data(), cpl.data(), stage.data(), nq, stride, P);
+  const uint32_t M = (0x40000000u / P) * P;
+  const uint32_t start = wrap ? M - 37 : 0u;
+  agent.arm(req.data(), cpl.data(), stage.data(), nq, stride, P, start);
 
   std::atomic<int> errors{0}, failures_seen{0};
   auto wave = [&](int64_t q) {
     std::mt19937 rng((unsigned)q * 7919u + 1u);
-    uint32_t seq = 0;
+    uint32_t seq = start;
     auto issue = [&](uint32_t node) {
-      seq++;
+      seq = fa::next_seq(seq, P);
       // release: this thread's reads of the slot's previous staging data are
       // ordered before the agent may overwrite it (on the GPU the wave has
       // consumed that data into LDS before it issues the next request)

@@ -30,3 +30,11 @@ def test_agent_protocol_asan(tmp_path):
     exe = _build(tmp_path, "address")
     r = subprocess.run([exe, "64", "4"], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stdout + r.stderr
+
+
+def test_agent_protocol_sequence_wrap(tmp_path):
+    """Lines that outlive their queries (server waves) run their request
+    numbers past the wrap point; the agent follows them across it."""
+    exe = _build(tmp_path, "address")
+    r = subprocess.run([exe, "32", "3", "wrap"], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr

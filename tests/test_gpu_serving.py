@@ -141,3 +141,74 @@ def test_server_rejects_too_deep_a_pipeline(cfg1):
         with pytest.raises(fa.AnnError) as e:
             fa.Server(ix, hbm_budget_bytes=64 << 20, delay=2, beam_width=3)
         assert e.value.code == -95
+
+
+# Serving through the agent transport: records in a file (or host DRAM) read
+# by the server's own host agents, one request line per resident wave.
+def _file_index(tmp_path, base, adj, entry):
+    d = str(tmp_path / "ix")
+    fa.save_index(d, base, adj, entry, 512)
+    return fa.Index.load(d, fa.TIER_FILE)
+
+
+@pytest.mark.parametrize("delay,beam", [(1, 1), (2, 2)])
+def test_server_file_tier_matches_oracle(cfg1, tmp_path, delay, beam):
+    base, q, adj, entry = cfg1
+    ks, Ls = plan(len(q), 11)
+    with _file_index(tmp_path, base, adj, entry) as ix:
+        with fa.Server(ix, hbm_budget_bytes=64 << 20, delay=delay, beam_width=beam) as srv:
+            for i in range(len(q)):
+                srv.submit(q[i], int(ks[i]), int(Ls[i]), i)
+            got = collect(srv, len(q))
+    for i in range(len(q)):
+        assert got[i]["status"] == 0
+        ref = oracle.search(base, adj, entry, q[i:i + 1], int(ks[i]), int(Ls[i]), delay=delay,
+                            beam=beam)
+        np.testing.assert_array_equal(got[i]["ids"], ref["ids"][0])
+        np.testing.assert_array_equal(got[i]["dists"].astype(np.float64), ref["dists"][0])
+        assert got[i]["steps"] == ref["steps"][0]
+
+
+def test_server_agent_host_tier_and_relaunch(cfg1):
+    """AGENT over host DRAM; the kernel leaves between two bursts (short idle
+    limit) and the relaunched waves continue their lines' request numbers."""
+    base, q, adj, entry = cfg1
+    ref = oracle.search(base, adj, entry, q, 10, 64, delay=1)
+    with fa.Index(base, adj, entry, 256, fa.TIER_HOST) as ix:
+        with fa.Server(ix, hbm_budget_bytes=64 << 20, transport=fa.TRANSPORT_AGENT,
+                       idle_polls=200) as srv:
+            for burst in range(3):
+                for i in range(len(q)):
+                    srv.submit(q[i], 10, 64, 1000 * burst + i)
+                got = collect(srv, len(q))
+                for i in range(len(q)):
+                    r = got[1000 * burst + i]
+                    assert r["status"] == 0
+                    np.testing.assert_array_equal(r["ids"], ref["ids"][i])
+                    np.testing.assert_array_equal(r["dists"].astype(np.float64), ref["dists"][i])
+                time.sleep(0.3)  # long enough for the idle waves to leave
+            st = srv.stats()
+    assert st["relaunches"] >= 1
+
+
+def test_server_agent_read_failure_is_per_query(cfg1, tmp_path):
+    base, q, adj, entry = cfg1
+    ref = oracle.search(base, adj, entry, q, 10, 64, delay=1, trace_cap=400)
+    ids, cnt = np.unique(ref["trace"][ref["trace"] >= 0], return_counts=True)
+    cand = ids[(cnt >= 2) & (cnt < len(q)) & (ids != entry)]
+    bad = int(cand[0])
+    hit = np.array([(row == bad).any() for row in ref["trace"]])
+    assert 0 < hit.sum() < len(q)
+    with _file_index(tmp_path, base, adj, entry) as ix:
+        ix.configure_agent(threads=4, fail_node=bad)
+        with fa.Server(ix, hbm_budget_bytes=64 << 20) as srv:
+            for i in range(len(q)):
+                srv.submit(q[i], 10, 64, i)
+            got = collect(srv, len(q))
+    for i in range(len(q)):
+        if hit[i]:
+            assert got[i]["status"] == -5
+            assert (got[i]["ids"] == -1).all()
+        else:
+            assert got[i]["status"] == 0
+            np.testing.assert_array_equal(got[i]["ids"], ref["ids"][i])
