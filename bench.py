@@ -183,6 +183,48 @@ def serving_leg(fa, ix, queries, kth, budget, L_op):
     return out
 
 
+def serving_file(fa, ix, queries, kth, L_op, m=2000):
+    """Continuous batching with the records in a file: the server's own host
+    agents read them (O_DIRECT), one request line per resident wave.  The
+    operating mix of the serving leg; saturation from an m-query burst, then
+    Poisson arrivals at half of it."""
+    import numpy as np
+
+    rng = np.random.default_rng(23)
+    nq = queries.shape[0]
+    Lset = [L for L in L_SWEEP if L >= L_op]
+    ks = rng.choice(np.array([10, 100], np.int32), 2 * m)
+    Ls = np.array([rng.choice([L for L in Lset if L >= k]) for k in ks], np.int32)
+
+    def recall(res):
+        qi = (res["tags"] % nq).astype(np.int64)
+        d10 = res["dists"][:, :10].astype(np.float64)
+        return float((np.minimum((d10 <= kth[qi][:, None]).sum(1), 10) / 10.0).mean())
+
+    out = {"workload": "records in a file, k in {10, 100}, L in %s with L >= k" % Lset}
+    with fa.Server(ix, hbm_budget_bytes=256 << 20) as srv:
+        idx = np.arange(m) % nq
+        t0 = fa.clock_us()
+        srv.submit_batch(queries[idx], ks[:m], Ls[:m], idx.astype(np.uint64))
+        res = srv.drain(m)
+        qmax = m / ((res["done_us"].max() - t0) / 1e6)
+        out["saturation_qps"] = round(qmax, 1)
+        out["failed_reads"] = int((res["status"] != 0).sum())
+        lam = 0.5 * qmax
+        idx = rng.integers(0, nq, m)
+        start = fa.clock_us() + 20000.0
+        arr = start + np.cumsum(rng.exponential(1e6 / lam, m))
+        srv.submit_batch(queries[idx], ks[m:], Ls[m:], idx.astype(np.uint64), arr)
+        res = srv.drain(m)
+        lat = (res["done_us"] - res["submit_us"]) / 1e3
+        out["half_load"] = {"offered_qps": round(lam, 1), "queries": int(len(lat)),
+                            "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
+                            "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
+                            "recall@10": round(recall(res), 4)}
+    log("file-tier serving: %s" % out)
+    return out
+
+
 def batched_file_leg(fa, torch, dev, n, nq_total):
     """Batched form at scale: n int8 vectors of d = 100 (4,096-component
     mixture), degree-48 graph, 512 B records in a file read with O_DIRECT by
@@ -618,6 +660,8 @@ def main():
             fa.search(fix, qsub, k=k, L=op[1])  # warm-up pass
             transports["file"] = {"queries": mq, "L": op[1], "direct_io": fix.info()["direct_io"],
                                   "write_s": round(t_save, 1), **compare(fix, qsub, 1, 2)}
+            if not args.no_serving:
+                transports["file"]["serving"] = serving_file(fa, fix, queries, kth, op[1])
             fix.close()
             log("file tier: %s" % transports["file"])
         finally:
