@@ -10,6 +10,11 @@ paper section 4.1.1 and the dependency-relaxed schedule of section 4.1.2 with
 an exact staleness ``delay``, (distance, id) keys, exact visited set, squared
 L2 in int64 (u8/i8) or fp64 (f32).  Distances are returned as float64 for
 every dtype (exact for the integer types).
+
+With ``codebooks`` the search uses compressed navigation (paper section 2.2):
+product-quantisation distances order the candidate list, and the answer is
+the first k expanded nodes by exact distance.  The PQ arithmetic is fp32 in
+the fixed order stated in ``oracle.c``.
 """
 from __future__ import annotations
 
@@ -50,6 +55,12 @@ def bind(path: str):
     lib.oracle_search.argtypes = [vp, i64, i32, i32, vp, i32, i32, vp, i64,
                                   i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, i32]
     lib.oracle_search.restype = ctypes.c_int
+    lib.oracle_search_pq.argtypes = lib.oracle_search.argtypes + [vp, i32]
+    lib.oracle_search_pq.restype = ctypes.c_int
+    lib.oracle_pq_encode.argtypes = [vp, i64, i32, i32, vp, i32, vp]
+    lib.oracle_pq_encode.restype = ctypes.c_int
+    lib.oracle_pq_table.argtypes = [vp, i32, i32, vp, i32, vp]
+    lib.oracle_pq_table.restype = ctypes.c_int
     return lib
 
 
@@ -107,10 +118,46 @@ def bruteforce(base: np.ndarray, queries: np.ndarray, k: int, threads: int = 0):
     return ids, dists
 
 
+def _check_codebooks(codebooks, d):
+    cb = np.ascontiguousarray(codebooks, dtype=np.float32)
+    if cb.ndim != 3 or cb.shape[1] != 256 or cb.shape[0] * cb.shape[2] != d:
+        raise ValueError("codebooks must be [M, 256, d / M] float32")
+    return cb
+
+
+def pq_encode(base: np.ndarray, codebooks: np.ndarray) -> np.ndarray:
+    """PQ codes [n, M] uint8 of every base row (nearest centroid per subspace)."""
+    base, _ = _check_vectors(base, base[:1])
+    cb = _check_codebooks(codebooks, base.shape[1])
+    codes = np.empty((base.shape[0], cb.shape[0]), dtype=np.uint8)
+    rc = _load().oracle_pq_encode(_ptr(base), base.shape[0], base.shape[1], DTYPES[base.dtype],
+                                  _ptr(cb), cb.shape[0], _ptr(codes))
+    if rc != 0:
+        raise ValueError("oracle_pq_encode failed: %d" % rc)
+    return codes
+
+
+def pq_table(query: np.ndarray, codebooks: np.ndarray, dtype=None) -> np.ndarray:
+    """Distance table [M, 256] float32 of one query."""
+    q = np.ascontiguousarray(query if dtype is None else np.asarray(query, dtype=dtype))
+    if q.dtype not in DTYPES or q.ndim != 1:
+        raise ValueError("query must be a 1-D uint8, int8 or float32 array")
+    cb = _check_codebooks(codebooks, q.shape[0])
+    tab = np.empty((cb.shape[0], 256), dtype=np.float32)
+    rc = _load().oracle_pq_table(_ptr(q), q.shape[0], DTYPES[q.dtype], _ptr(cb), cb.shape[0],
+                                 _ptr(tab))
+    if rc != 0:
+        raise ValueError("oracle_pq_table failed: %d" % rc)
+    return tab
+
+
 def search(base: np.ndarray, adj: np.ndarray, entry: int, queries: np.ndarray, k: int,
            L: int, R: int | None = None, delay: int = 1, beam: int = 1, threads: int = 0,
-           trace_cap: int = 0):
+           trace_cap: int = 0, codebooks: np.ndarray | None = None):
     """Best-first search, strict (delay=0) or dependency-relaxed (delay>=1).
+
+    With ``codebooks`` ([M, 256, d/M] float32) navigation uses PQ distances and
+    the answer is re-ranked by exact distance (theta then holds PQ distances).
 
     Returns a dict with ids [nq,k] int32, dists [nq,k] float64, steps [nq] uint32
     and, when trace_cap > 0, trace [nq,trace_cap] int32 (selected ids, -1
@@ -131,10 +178,14 @@ def search(base: np.ndarray, adj: np.ndarray, entry: int, queries: np.ndarray, k
         trace = np.empty((nq, trace_cap), dtype=np.int32)
         theta = np.empty((nq, trace_cap), dtype=np.float64)
     threads = threads or (os.cpu_count() or 1)
-    rc = _load().oracle_search(_ptr(base), base.shape[0], base.shape[1], DTYPES[base.dtype],
-                               _ptr(adj), adj.shape[1], int(entry), _ptr(queries), nq,
-                               k, L, R, delay, beam, threads, _ptr(ids), _ptr(dists),
-                               _ptr(steps), _ptr(trace), _ptr(theta), trace_cap)
+    args = (_ptr(base), base.shape[0], base.shape[1], DTYPES[base.dtype], _ptr(adj),
+            adj.shape[1], int(entry), _ptr(queries), nq, k, L, R, delay, beam, threads,
+            _ptr(ids), _ptr(dists), _ptr(steps), _ptr(trace), _ptr(theta), trace_cap)
+    if codebooks is None:
+        rc = _load().oracle_search(*args)
+    else:
+        cb = _check_codebooks(codebooks, base.shape[1])
+        rc = _load().oracle_search_pq(*args, _ptr(cb), cb.shape[0])
     if rc != 0:
         raise ValueError("oracle_search failed: %d" % rc)
     out = {"ids": ids, "dists": dists, "steps": steps}

@@ -32,6 +32,13 @@
  *   - Squared L2 distance: integer vectors in 64-bit integers (exact), fp32
  *     vectors in fp64 from the fp32 inputs.
  *
+ * Compressed navigation (paper section 2.2, the in-memory quantised vectors of
+ * graph-indexing systems; section 8 of the oracle below): neighbours are
+ * scored by a product-quantisation (PQ) distance, the candidate list is
+ * ordered by it, and each expanded node's exact distance, from the
+ * full-precision vector of its record, goes to a result set whose first k
+ * (by exact distance, then id) are the answer.
+ *
  * Parity status: pinned (see tests/test_oracle_*.py): hand-derived traces of
  * a worked example, exhaustive search on tiny inputs (L >= N gives the exact
  * top-k), a textbook heap formulation of the strict search, library
@@ -101,6 +108,101 @@ int oracle_distances(const void *base, int64_t n, int32_t d, int32_t dtype,
     return ORC_EINVAL;
   for (int64_t i = 0; i < n; i++) out[i] = orc_dist(base, i, d, dtype, query);
   return 0;
+}
+
+/* ------------------------------------------------------ product quantisation */
+
+/* Codebooks: M subspaces, subspace m holding dimensions [m*dsub, (m+1)*dsub)
+ * with dsub = d / M; 256 centroids of dsub floats each, laid out
+ * codebooks[(m * 256 + c) * dsub + j].
+ *
+ * All PQ arithmetic is fp32 in one fixed order (the paper does not state a
+ * precision; a code or a candidate's place in the list is an integer decision
+ * that the GPU must take identically):
+ *   sub-distance(x, centroid) = acc after acc = fmaf(t, t, acc), t = x_j - c_j,
+ *                               for j = 0 .. dsub-1 in order, from acc = 0,
+ *                               vector components converted to float (exact
+ *                               for u8 and i8)
+ *   code of x, subspace m     = the centroid with the smallest sub-distance,
+ *                               the lowest index among equals
+ *   table of a query          = tab[m * 256 + c] = sub-distance(q_m, centroid c)
+ *   PQ distance of a code     = sum over m = 0 .. M-1 in order of
+ *                               tab[m * 256 + code_m], in float, from 0   */
+
+#define ORC_KSUB 256
+
+static void orc_row_float(const void *base, int64_t row, int32_t d, int32_t dtype, float *out) {
+  for (int32_t j = 0; j < d; j++) {
+    if (dtype == ORC_U8)
+      out[j] = (float)((const uint8_t *)base)[row * (int64_t)d + j];
+    else if (dtype == ORC_I8)
+      out[j] = (float)((const int8_t *)base)[row * (int64_t)d + j];
+    else
+      out[j] = ((const float *)base)[row * (int64_t)d + j];
+  }
+}
+
+static float orc_pq_sub(const float *x, const float *c, int32_t dsub) {
+  float acc = 0.0f;
+  for (int32_t j = 0; j < dsub; j++) {
+    const float t = x[j] - c[j];
+    acc = fmaf(t, t, acc);
+  }
+  return acc;
+}
+
+static int orc_pq_check(int32_t d, int32_t M) { return M >= 1 && M <= d && d % M == 0; }
+
+/* Codes of n base rows: codes[i * M + m]. */
+int oracle_pq_encode(const void *base, int64_t n, int32_t d, int32_t dtype,
+                     const float *codebooks, int32_t M, uint8_t *codes) {
+  if (!base || !codebooks || !codes || n < 0 || !orc_pq_check(d, M) ||
+      (dtype != ORC_U8 && dtype != ORC_I8 && dtype != ORC_F32))
+    return ORC_EINVAL;
+  const int32_t dsub = d / M;
+  float *x = (float *)malloc(sizeof(float) * (size_t)d);
+  if (!x) return ORC_ENOMEM;
+  for (int64_t i = 0; i < n; i++) {
+    orc_row_float(base, i, d, dtype, x);
+    for (int32_t m = 0; m < M; m++) {
+      int32_t best = 0;
+      float bd = 0.0f;
+      for (int32_t c = 0; c < ORC_KSUB; c++) {
+        const float s = orc_pq_sub(x + m * dsub, codebooks + ((int64_t)m * ORC_KSUB + c) * dsub, dsub);
+        if (c == 0 || s < bd) {
+          bd = s;
+          best = c;
+        }
+      }
+      codes[i * M + m] = (uint8_t)best;
+    }
+  }
+  free(x);
+  return 0;
+}
+
+/* Distance table of one query (d elements of `dtype`): tab[m * 256 + c]. */
+int oracle_pq_table(const void *query, int32_t d, int32_t dtype, const float *codebooks,
+                    int32_t M, float *tab) {
+  if (!query || !codebooks || !tab || !orc_pq_check(d, M) ||
+      (dtype != ORC_U8 && dtype != ORC_I8 && dtype != ORC_F32))
+    return ORC_EINVAL;
+  const int32_t dsub = d / M;
+  float *x = (float *)malloc(sizeof(float) * (size_t)d);
+  if (!x) return ORC_ENOMEM;
+  orc_row_float(query, 0, d, dtype, x);
+  for (int32_t m = 0; m < M; m++)
+    for (int32_t c = 0; c < ORC_KSUB; c++)
+      tab[m * ORC_KSUB + c] =
+          orc_pq_sub(x + m * dsub, codebooks + ((int64_t)m * ORC_KSUB + c) * dsub, dsub);
+  free(x);
+  return 0;
+}
+
+static float orc_pq_dist(const float *tab, const uint8_t *code, int32_t M) {
+  float s = 0.0f;
+  for (int32_t m = 0; m < M; m++) s += tab[m * ORC_KSUB + code[m]];
+  return s;
 }
 
 /* ------------------------------------------------------------- keys, lists */
@@ -240,11 +342,31 @@ typedef struct {
   int32_t trace_cap;
   orc_counter *ctr;
   int err;
+  /* compressed navigation (optional): codes n x pq_m, codebooks */
+  const uint8_t *pq_codes;
+  const float *pq_cb;
+  int32_t pq_m;
 } orc_search_job;
 
+/* Work buffers of one worker thread. */
+typedef struct {
+  uint8_t *visited;
+  orc_entry *cand, *merged, *res;
+  int32_t *fifo;
+  float *tab;
+} orc_work;
+
+/* Navigation distance of node x: exact, or the PQ distance of its code. */
+static double orc_nav_dist(const orc_search_job *J, const orc_work *w, const void *q, int32_t x) {
+  if (J->pq_codes) return (double)orc_pq_dist(w->tab, J->pq_codes + (int64_t)x * J->pq_m, J->pq_m);
+  return orc_dist(J->base, x, J->d, J->dtype, q);
+}
+
 /* One query of the search.  Work buffers are owned by the caller. */
-static void orc_search_one(const orc_search_job *J, int64_t qi, uint8_t *visited,
-                           orc_entry *cand, orc_entry *merged, int32_t *fifo) {
+static void orc_search_one(const orc_search_job *J, int64_t qi, const orc_work *w) {
+  uint8_t *visited = w->visited;
+  orc_entry *cand = w->cand, *merged = w->merged, *res = w->res;
+  int32_t *fifo = w->fifo;
   const size_t qbytes = (size_t)J->d * orc_elem_bytes(J->dtype);
   const void *q = (const char *)J->queries + qi * qbytes;
   const int32_t L = J->L, W = J->beam;
@@ -257,9 +379,11 @@ static void orc_search_one(const orc_search_job *J, int64_t qi, uint8_t *visited
     for (int32_t i = 0; i < J->trace_cap; i++) th[i] = NAN;
 
   memset(visited, 0, (size_t)J->n);
+  if (J->pq_codes) oracle_pq_table(q, J->d, J->dtype, J->pq_cb, J->pq_m, w->tab);
+  int64_t nres = 0; /* compressed navigation: exact distances of expanded nodes */
   /* Init: the candidate list holds the entry node only; it is visited. */
   int32_t nc = 1;
-  cand[0].dist = orc_dist(J->base, J->entry, J->d, J->dtype, q);
+  cand[0].dist = orc_nav_dist(J, w, q, J->entry);
   cand[0].id = J->entry;
   cand[0].expanded = 0;
   visited[J->entry] = 1;
@@ -291,6 +415,12 @@ static void orc_search_one(const orc_search_job *J, int64_t qi, uint8_t *visited
       int32_t u = fifo[f_head];
       f_head = (f_head + 1) % fifo_cap;
       f_len--;
+      if (J->pq_codes) { /* u's record holds its full vector: exact distance */
+        res[nres].dist = orc_dist(J->base, u, J->d, J->dtype, q);
+        res[nres].id = u;
+        res[nres].expanded = 1;
+        nres++;
+      }
       /* Neighbours: the first R ids of u's list that are not yet visited. */
       int32_t m = 0;
       for (int32_t i = 0; i < nc; i++) merged[m++] = cand[i];
@@ -300,7 +430,7 @@ static void orc_search_one(const orc_search_job *J, int64_t qi, uint8_t *visited
         if (x < 0 || (int64_t)x >= J->n) continue; /* padding slot */
         if (visited[x]) continue;
         visited[x] = 1;
-        merged[m].dist = orc_dist(J->base, x, J->d, J->dtype, q);
+        merged[m].dist = orc_nav_dist(J, w, q, x);
         merged[m].id = x;
         merged[m].expanded = 0;
         m++;
@@ -315,10 +445,19 @@ static void orc_search_one(const orc_search_job *J, int64_t qi, uint8_t *visited
     }
   }
 
+  /* The answer: the first k of the list, or with compressed navigation the
+   * first k of the expanded nodes by exact distance. */
+  const orc_entry *out = cand;
+  int64_t nout = nc;
+  if (J->pq_codes) {
+    qsort(res, (size_t)nres, sizeof(orc_entry), orc_cmp);
+    out = res;
+    nout = nres;
+  }
   for (int32_t j = 0; j < J->k; j++) {
-    if (j < nc) {
-      J->ids[qi * J->k + j] = cand[j].id;
-      J->dists[qi * J->k + j] = cand[j].dist;
+    if (j < nout) {
+      J->ids[qi * J->k + j] = out[j].id;
+      J->dists[qi * J->k + j] = out[j].dist;
     } else {
       J->ids[qi * J->k + j] = -1;
       J->dists[qi * J->k + j] = INFINITY;
@@ -330,24 +469,29 @@ static void orc_search_one(const orc_search_job *J, int64_t qi, uint8_t *visited
 static void *orc_search_worker(void *arg) {
   orc_search_job *J = (orc_search_job *)arg;
   const int32_t W = J->beam;
-  uint8_t *visited = (uint8_t *)malloc((size_t)(J->n > 0 ? J->n : 1));
-  orc_entry *cand = (orc_entry *)malloc(sizeof(orc_entry) * (size_t)J->L);
-  orc_entry *merged =
-      (orc_entry *)malloc(sizeof(orc_entry) * (size_t)(J->L + J->R + 1));
-  int32_t *fifo = (int32_t *)malloc(sizeof(int32_t) * (size_t)((J->delay + 2) * W));
-  if (!visited || !cand || !merged || !fifo) {
+  orc_work w;
+  w.visited = (uint8_t *)malloc((size_t)(J->n > 0 ? J->n : 1));
+  w.cand = (orc_entry *)malloc(sizeof(orc_entry) * (size_t)J->L);
+  w.merged = (orc_entry *)malloc(sizeof(orc_entry) * (size_t)(J->L + J->R + 1));
+  w.fifo = (int32_t *)malloc(sizeof(int32_t) * (size_t)((J->delay + 2) * W));
+  /* each node is expanded at most once: n result entries suffice */
+  w.res = J->pq_codes ? (orc_entry *)malloc(sizeof(orc_entry) * (size_t)J->n) : NULL;
+  w.tab = J->pq_codes ? (float *)malloc(sizeof(float) * (size_t)J->pq_m * ORC_KSUB) : NULL;
+  if (!w.visited || !w.cand || !w.merged || !w.fifo || (J->pq_codes && (!w.res || !w.tab))) {
     J->err = ORC_ENOMEM;
   } else {
     for (;;) {
       int64_t qi = orc_take(J->ctr);
       if (qi >= J->nq) break;
-      orc_search_one(J, qi, visited, cand, merged, fifo);
+      orc_search_one(J, qi, &w);
     }
   }
-  free(visited);
-  free(cand);
-  free(merged);
-  free(fifo);
+  free(w.visited);
+  free(w.cand);
+  free(w.merged);
+  free(w.fifo);
+  free(w.res);
+  free(w.tab);
   return NULL;
 }
 
@@ -368,12 +512,13 @@ static void *orc_search_worker(void *arg) {
  *             (+inf while fewer than L candidates), optional
  * Returns 0, -22 on invalid arguments, -12 on allocation failure.
  */
-int oracle_search(const void *base, int64_t n, int32_t d, int32_t dtype,
-                  const int32_t *adj, int32_t adj_stride, int32_t entry,
-                  const void *queries, int64_t nq, int32_t k, int32_t L, int32_t R,
-                  int32_t delay, int32_t beam, int32_t threads, int32_t *ids,
-                  double *dists, uint32_t *steps, int32_t *trace, double *theta,
-                  int32_t trace_cap) {
+static int orc_search_all(const void *base, int64_t n, int32_t d, int32_t dtype,
+                          const int32_t *adj, int32_t adj_stride, int32_t entry,
+                          const void *queries, int64_t nq, int32_t k, int32_t L, int32_t R,
+                          int32_t delay, int32_t beam, int32_t threads, int32_t *ids,
+                          double *dists, uint32_t *steps, int32_t *trace, double *theta,
+                          int32_t trace_cap, const uint8_t *pq_codes, const float *pq_cb,
+                          int32_t pq_m) {
   if (!base || !adj || n < 1 || d < 1 || nq < 0 ||
       (dtype != ORC_U8 && dtype != ORC_I8 && dtype != ORC_F32))
     return ORC_EINVAL;
@@ -391,12 +536,47 @@ int oracle_search(const void *base, int64_t n, int32_t d, int32_t dtype,
     orc_search_job j = {base,  n,     d,     dtype, adj,   adj_stride, entry,
                         queries, nq,  k,     L,     R,     delay,      beam,
                         ids,   dists, steps, trace, theta, trace_cap,  &ctr,
-                        0};
+                        0,     pq_codes, pq_cb, pq_m};
     jobs[t] = j;
   }
   int rc = orc_run_threads(orc_search_worker, jobs, sizeof(orc_search_job), threads);
   for (int32_t t = 0; t < threads && rc == 0; t++)
     if (jobs[t].err) rc = jobs[t].err;
   free(jobs);
+  return rc;
+}
+
+int oracle_search(const void *base, int64_t n, int32_t d, int32_t dtype,
+                  const int32_t *adj, int32_t adj_stride, int32_t entry,
+                  const void *queries, int64_t nq, int32_t k, int32_t L, int32_t R,
+                  int32_t delay, int32_t beam, int32_t threads, int32_t *ids,
+                  double *dists, uint32_t *steps, int32_t *trace, double *theta,
+                  int32_t trace_cap) {
+  return orc_search_all(base, n, d, dtype, adj, adj_stride, entry, queries, nq, k, L, R, delay,
+                        beam, threads, ids, dists, steps, trace, theta, trace_cap, NULL, NULL, 0);
+}
+
+/*
+ * oracle_search_pq: the same search with compressed navigation.  The base is
+ * encoded with `codebooks` (M subspaces, see oracle_pq_encode); the list is
+ * ordered by PQ distance (`theta` then holds the L-th PQ distance); ids and
+ * dists are the first k of the expanded nodes by exact distance (float64,
+ * exact for u8/i8), padded with -1 / +inf.  Other arguments as oracle_search.
+ */
+int oracle_search_pq(const void *base, int64_t n, int32_t d, int32_t dtype,
+                     const int32_t *adj, int32_t adj_stride, int32_t entry,
+                     const void *queries, int64_t nq, int32_t k, int32_t L, int32_t R,
+                     int32_t delay, int32_t beam, int32_t threads, int32_t *ids,
+                     double *dists, uint32_t *steps, int32_t *trace, double *theta,
+                     int32_t trace_cap, const float *codebooks, int32_t M) {
+  if (!base || !codebooks || n < 1 || !orc_pq_check(d, M)) return ORC_EINVAL;
+  uint8_t *codes = (uint8_t *)malloc((size_t)n * (size_t)M);
+  if (!codes) return ORC_ENOMEM;
+  int rc = oracle_pq_encode(base, n, d, dtype, codebooks, M, codes);
+  if (rc == 0)
+    rc = orc_search_all(base, n, d, dtype, adj, adj_stride, entry, queries, nq, k, L, R, delay,
+                        beam, threads, ids, dists, steps, trace, theta, trace_cap, codes,
+                        codebooks, M);
+  free(codes);
   return rc;
 }

@@ -37,6 +37,27 @@ def main(path):
     for delay in (0, 1, 2):
         I.test_invariants(wl, delay, 16)
     I.test_relaxed_step_bound(wl)
+
+    import test_oracle_pq as Q
+    for dt in (np.uint8, np.int8):
+        Q.test_identity_codebook_codes_are_the_vectors(dt)
+    for dt in ("u8", "i8"):
+        for delay, beam in ((0, 1), (1, 1), (2, 2)):
+            Q.test_identity_codebook_search_equals_exact_search(dt, delay, beam)
+    for dt, M in ((np.float32, 4), (np.uint8, 8), (np.int8, 3)):
+        Q.test_table_is_squared_distance_to_decoded_vector(dt, M)
+    for dt in (np.uint8, np.float32):
+        Q.test_codes_name_the_nearest_centroid(dt)
+    for L, R in ((1, 6), (4, 6), (10, 6), (25, 3)):
+        Q.test_strict_pq_equals_heap_formulation(L, R)
+    sbase = synth.make_base(2000, 16, "u8", 8, 901)
+    sq = synth.make_queries(12, 16, "u8", 8, 901, 902)
+    sadj, sentry = synth.build_graph(sbase, 8, 903, threads=2)
+    sm = (sbase, sq, sadj, sentry)
+    for delay, beam in ((0, 1), (1, 1), (3, 2)):
+        Q.test_answer_is_exact_topk_of_expanded(sm, delay, beam)
+    Q.test_degenerate_codebook_still_reranks(sm)
+    Q.test_L_covering_graph_gives_exact_topk()
     print("ALL PINS HOLD")
 
 

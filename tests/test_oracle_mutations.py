@@ -2,8 +2,9 @@
 
 Each mutant is a copy of oracle.c with one plausible mistake -- a reversed
 tie-break, an off-by-one staleness, a dropped visited mark, a dropped
-dimension or neighbour, a short candidate list, a wrong sign -- compiled into
-a temporary library.  The pin battery (tests/oracle_battery.py) must fail on
+dimension or neighbour, a short candidate list, a wrong sign, and in the PQ
+navigation a dropped subspace, a reversed code tie-break, a shifted centroid,
+an exact entry key or a missing re-rank -- compiled into a temporary library.  The pin battery (tests/oracle_battery.py) must fail on
 every mutant and pass on the unmodified source.
 """
 import os
@@ -30,6 +31,16 @@ MUTANTS = {
     "list_one_short": ("nc = m < L ? m : L;", "nc = m < L - 1 ? m : (L > 1 ? L - 1 : 1);"),
     "f32_sign_error": ("double t = (double)a[j] - (double)b[j];\n      s += t * t;",
                        "double t = (double)a[j] + (double)b[j];\n      s += t * t;"),
+    "pq_sum_skips_last_subspace": ("for (int32_t m = 0; m < M; m++) s += tab[",
+                                   "for (int32_t m = 0; m + 1 < M; m++) s += tab["),
+    "pq_code_ties_to_highest": ("if (c == 0 || s < bd) {", "if (c == 0 || s <= bd) {"),
+    "pq_sub_distance_sign": ("const float t = x[j] - c[j];", "const float t = x[j] + c[j];"),
+    "pq_table_shifted_centroid": (
+        "orc_pq_sub(x + m * dsub, codebooks + ((int64_t)m * ORC_KSUB + c) * dsub, dsub);\n  free(x);\n  return 0;\n}\n\nstatic float",
+        "orc_pq_sub(x + m * dsub, codebooks + ((int64_t)m * ORC_KSUB + (c ^ 1)) * dsub, dsub);\n  free(x);\n  return 0;\n}\n\nstatic float"),
+    "pq_entry_keyed_exactly": ("cand[0].dist = orc_nav_dist(J, w, q, J->entry);",
+                               "cand[0].dist = orc_dist(J->base, J->entry, J->d, J->dtype, q);"),
+    "pq_answer_not_reranked": ("out = res;\n    nout = nres;", "out = cand;\n    nout = nc;"),
     "selects_second_unexpanded": ("if (cand[i].expanded) continue;",
                                   "if (cand[i].expanded || (nsel == 0 && i == 0 && nc > 1 && !cand[1].expanded)) continue;"),
 }
