@@ -63,6 +63,16 @@ typedef enum {
   ANN_TRANSPORT_AGENT = 2
 } ann_transport;
 
+/* How neighbours are scored (ann_search_opts.navigation). */
+typedef enum {
+  ANN_NAV_FULL = 0, /* exact distance against the full-precision HBM copy */
+  ANN_NAV_PQ = 1    /* product-quantisation codes in HBM, expanded nodes
+                       re-ranked exactly from their records (ann_index_set_pq) */
+} ann_navigation;
+
+/* ann_index_set_pq flags */
+#define ANN_PQ_DROP_NAV 1 /* release the full-precision navigation copy */
+
 typedef struct ann_index ann_index; /* opaque, owned by the library */
 
 typedef struct {
@@ -77,6 +87,8 @@ typedef struct {
   int32_t rec_bytes;  /* bytes of each record fetched per step */
   int64_t hbm_bytes;  /* device memory held by the index */
   int32_t direct_io;  /* ANN_TIER_FILE: 1 if the file is read with O_DIRECT */
+  int32_t pq_m;       /* PQ subspaces of the codes in HBM (0 = none) */
+  int32_t nav_full;   /* 1 while the full-precision navigation copy is held */
 } ann_index_info;
 
 /* Search options; a NULL pointer means {delay = 1, beam_width = 1, defaults}. */
@@ -133,6 +145,15 @@ typedef struct {
                               results equal the strict search.  spin_limit
                               bounds each barrier wait (0 = 2^24 polls), else
                               ANN_ETIMEDOUT. */
+  int32_t navigation;      /* ann_navigation (0 = full precision).  ANN_NAV_PQ
+                              (paper section 2.2: quantised vectors in memory,
+                              full-precision vectors with the neighbour lists
+                              in storage): the list is ordered by PQ distance,
+                              each expanded node's exact distance comes from
+                              the vector in its record, and ids / dists are
+                              the first k expanded nodes by exact distance.
+                              Needs ann_index_set_pq; sync_grain 0 only;
+                              d_stats[2] stays 0. */
 } ann_search_opts;
 
 /*
@@ -199,6 +220,29 @@ int ann_agent_configure(ann_index *ix, int32_t threads, int32_t delay_node, int3
  * or read, failed reads (host integers, caller-owned). */
 int ann_agent_stats(const ann_index *ix, uint64_t *requests, uint64_t *bytes, uint64_t *errors);
 
+/*
+ * ann_index_set_pq -- compressed navigation (paper section 2.2: the
+ * in-memory quantised vectors of graph-indexing systems, while the
+ * full-precision vectors stay in the records).  Encodes every base vector
+ * on the GPU into a 32 B code row in HBM, replacing earlier codes.
+ *   codebooks  host, m x 256 x (d / m) float32: subspace s covers dimensions
+ *              [s * d/m, (s+1) * d/m); centroid c of subspace s at
+ *              codebooks[(s * 256 + c) * (d/m)]; copied, caller keeps ownership
+ *   m          subspaces, 1 <= m <= 32, d % m == 0, d / m <= 32
+ *   flags      ANN_PQ_DROP_NAV: free the full-precision navigation copy
+ *              afterwards (searches must then use ANN_NAV_PQ; the server and
+ *              a later ann_index_set_pq need the copy)
+ * Code of a vector, per subspace: the centroid of smallest fp32 squared
+ * distance, accumulated with fused multiply-adds over the subspace's
+ * dimensions in order; the lowest index among equals.  Synchronous.
+ * Errors: ANN_EINVAL (sizes, or no navigation copy to encode), ANN_ENOMEM.
+ */
+int ann_index_set_pq(ann_index *ix, const float *codebooks, int32_t m, int32_t flags);
+/* ann_index_pq_codes -- copy the PQ codes to `host_codes` (caller-owned,
+ * n x m bytes, row i = the m subspace codes of node i).  Synchronous.
+ * Errors: ANN_EINVAL (NULL, or no codes). */
+int ann_index_pq_codes(const ann_index *ix, uint8_t *host_codes);
+
 /* ann_index_info -- sizes and layout of an index (host struct, caller-owned). */
 int ann_index_info_get(const ann_index *ix, ann_index_info *out);
 
@@ -261,7 +305,8 @@ int ann_device_clock_khz(int32_t *khz);
  *   waves_per_block (4), hash_bits (10), queue_cap (2^20 waiting arrivals),
  *   idle_polls (50000: empty polls before the kernel leaves; it is started
  *   again when work arrives), beam_width (1); the schedule is that of
- *   ann_search with the same delay and beam width.
+ *   ann_search with the same delay and beam width.  The server scores with
+ *   the full-precision navigation copy (not after ANN_PQ_DROP_NAV).
  * Errors: ANN_EINVAL, ANN_ENOMEM (budget too small or allocation), ANN_EIO.
  */
 typedef struct ann_server ann_server;

@@ -55,6 +55,10 @@ struct ann_index {
   int32_t tslots = 0;               // staging slots per query
   uint32_t *d_work = nullptr;       // persistent launches: device work counter
   uint32_t *d_ctl = nullptr;        // kernel-grained launches: barrier state (16 u32)
+  // compressed navigation
+  uint8_t *pq_codes = nullptr;      // device, n x kPqStride
+  float *pq_cb = nullptr;           // device, pq_m x 256 x (d / pq_m)
+  int32_t pq_m = 0;
 };
 
 struct ann_graph {
@@ -107,6 +111,8 @@ void release(ann_index *ix) {
   if (ix->d_work) (void)hipFree(ix->d_work);
   if (ix->d_ctl) (void)hipFree(ix->d_ctl);
   if (ix->nav) (void)hipFree(ix->nav);
+  if (ix->pq_codes) (void)hipFree(ix->pq_codes);
+  if (ix->pq_cb) (void)hipFree(ix->pq_cb);
   if (ix->rec_hbm) (void)hipFree(ix->rec_hbm);
   if (ix->rec_host) (void)hipHostFree(ix->rec_host);
   if (ix->fd >= 0) close(ix->fd);
@@ -489,6 +495,60 @@ int ann_index_info_get(const ann_index *ix, ann_index_info *out) {
   out->entry = ix->entry; out->slot_bytes = ix->slot; out->tier = ix->tier;
   out->nav_stride = ix->nav_stride; out->rec_bytes = ix->rec_bytes; out->hbm_bytes = ix->hbm_bytes;
   out->direct_io = ix->direct_io ? 1 : 0;
+  out->pq_m = ix->pq_m;
+  out->nav_full = ix->nav ? 1 : 0;
+  return ANN_OK;
+}
+
+int ann_index_set_pq(ann_index *ix, const float *codebooks, int32_t m, int32_t flags) {
+  if (!ix || !codebooks) return fail(ANN_EINVAL, "NULL argument");
+  if (m < 1 || m > fa::kPqMaxM || ix->d % m != 0 || ix->d / m > 32)
+    return fail(ANN_EINVAL, "m=%d: need 1 <= m <= %d, d %% m == 0 and d / m <= 32 (d=%d)", m,
+                fa::kPqMaxM, ix->d);
+  if (flags & ~ANN_PQ_DROP_NAV) return fail(ANN_EINVAL, "flags=%d", flags);
+  if (!ix->nav) return fail(ANN_EINVAL, "the navigation copy was released; nothing to encode");
+  const size_t cb_bytes = sizeof(float) * (size_t)m * fa::kPqKsub * (size_t)(ix->d / m);
+  const size_t code_bytes = (size_t)ix->n * fa::kPqStride;
+  uint8_t *codes = nullptr;
+  float *cb = nullptr;
+  hipError_t e = hipMalloc(&codes, code_bytes);
+  if (e == hipSuccess) e = hipMalloc(&cb, cb_bytes);
+  if (e == hipSuccess) e = hipMemcpy(cb, codebooks, cb_bytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = fa::launch_pq_encode(ix->nav, ix->n, ix->nav_stride, ix->dtype, ix->d, cb, m, codes,
+                             nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    if (codes) (void)hipFree(codes);
+    if (cb) (void)hipFree(cb);
+    return hip_fail(e, "PQ encoding");
+  }
+  if (ix->pq_codes) {
+    (void)hipFree(ix->pq_codes);
+    ix->hbm_bytes -= (int64_t)ix->n * fa::kPqStride;
+  }
+  if (ix->pq_cb) {
+    (void)hipFree(ix->pq_cb);
+    ix->hbm_bytes -= (int64_t)sizeof(float) * ix->pq_m * fa::kPqKsub * (ix->d / ix->pq_m);
+  }
+  ix->pq_codes = codes;
+  ix->pq_cb = cb;
+  ix->pq_m = m;
+  ix->hbm_bytes += (int64_t)(code_bytes + cb_bytes);
+  if (flags & ANN_PQ_DROP_NAV) {
+    (void)hipFree(ix->nav);
+    ix->nav = nullptr;
+    ix->hbm_bytes -= ix->n * (int64_t)ix->nav_stride;
+  }
+  return ANN_OK;
+}
+
+int ann_index_pq_codes(const ann_index *ix, uint8_t *host_codes) {
+  if (!ix || !host_codes) return fail(ANN_EINVAL, "NULL argument");
+  if (!ix->pq_codes) return fail(ANN_EINVAL, "the index has no PQ codes");
+  hipError_t e = hipMemcpy2D(host_codes, (size_t)ix->pq_m, ix->pq_codes, fa::kPqStride,
+                             (size_t)ix->pq_m, (size_t)ix->n, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "PQ code copy");
   return ANN_OK;
 }
 
@@ -572,6 +632,14 @@ int prepare_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, 
                             o.d_phases))
     return fail(ANN_EINVAL, "kernel-grained search runs the strict schedule (delay 0, beam 1) "
                             "without persistent waves, order or phase times");
+  if (o.navigation != ANN_NAV_FULL && o.navigation != ANN_NAV_PQ)
+    return fail(ANN_EINVAL, "navigation=%d", o.navigation);
+  if (o.navigation == ANN_NAV_PQ && !ix->pq_codes)
+    return fail(ANN_EINVAL, "PQ navigation needs codes (ann_index_set_pq)");
+  if (o.navigation == ANN_NAV_FULL && !ix->nav)
+    return fail(ANN_EINVAL, "the full-precision navigation copy was released; use ANN_NAV_PQ");
+  if (o.navigation == ANN_NAV_PQ && o.sync_grain)
+    return fail(ANN_ENOTSUP, "kernel-grained search scores with the full-precision copy only");
   if (nq > 0x7FFFFFFFll) return fail(ANN_EINVAL, "nq=%lld too large", (long long)nq);
   *o_out = o;
   *transport_out = transport;
@@ -615,7 +683,14 @@ int prepare_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, 
   a.delay = o.delay;
   a.beam = o.beam_width;
   a.pslots = std::max(2, (o.delay + 1) * o.beam_width);
-  a.lds_per_wave = fa::search_lds_bytes(a.Lcap, a.nav_stride, a.hash_bits);
+  if (o.navigation == ANN_NAV_PQ) {
+    a.pq_codes = ix->pq_codes;
+    a.pq_cb = ix->pq_cb;
+    a.pq_m = ix->pq_m;
+    a.pq_dsub = ix->d / ix->pq_m;
+  }
+  a.lds_per_wave = fa::search_lds_bytes(a.Lcap, a.nav_stride, a.hash_bits,
+                                        a.pq_m ? a.k : 0, a.pq_m);
   if ((int64_t)a.lds_per_wave * o.waves_per_block > 160 * 1024)
     return fail(ANN_EINVAL, "LDS need %u B per query x %d exceeds 160 KiB", a.lds_per_wave,
                 o.waves_per_block);
@@ -802,6 +877,9 @@ int ann_internal_server_transport(ann_index *ix, int32_t requested, int32_t *tr,
 int ann_internal_server_args(ann_index *ix, int32_t k_max, int32_t L_max, int32_t hash_bits,
                              fa::SearchArgs *base, int32_t *dtype) {
   if (hash_bits < 6 || hash_bits > 14) return fail(ANN_EINVAL, "hash_bits=%d", hash_bits);
+  if (!ix->nav)
+    return fail(ANN_EINVAL, "the server scores with the full-precision navigation copy, "
+                            "which was released");
   fa::SearchArgs &a = *base;
   a = fa::SearchArgs{};
   a.nav = ix->nav;

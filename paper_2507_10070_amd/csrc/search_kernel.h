@@ -19,9 +19,19 @@ enum { TR_DIRECT = 0, TR_AGENT = 1 };
 enum { SCHED_STRICT = 0, SCHED_RELAXED = 1, SCHED_GENERIC = 2 };
 constexpr int kMaxPipe = 8;
 
+// Navigation: neighbours scored exactly against the full-precision HBM copy,
+// or by product-quantisation codes in HBM with the expanded nodes re-ranked
+// exactly from their records (compressed navigation).  PQ: M <= kPqMaxM
+// subspaces of 256 centroids; code rows of kPqStride bytes (byte m = code of
+// subspace m, the rest zero).
+enum { NAV_FULL = 0, NAV_PQ = 1 };
+constexpr int kPqStride = 32;
+constexpr int kPqMaxM = 32;
+constexpr int kPqKsub = 256;
+
 // Byte offsets of one wave's LDS region.
 struct LdsLayout {
-  uint32_t cand, nk, stage, qbuf, ids, dsc, hash, fifo, bytes;
+  uint32_t cand, nk, stage, qbuf, ids, dsc, hash, fifo, res, tab, bytes;
 };
 
 struct SearchArgs {
@@ -56,10 +66,16 @@ struct SearchArgs {
   const int32_t *order;    // optional processing order (persistent launches)
   uint32_t *work;          // persistent launches: device work counter, zero at launch
   int32_t delay, beam;     // SCHED_GENERIC: staleness and beam width, (delay+1)*beam <= kMaxPipe
+  // NAV_PQ (pq_m > 0): codes n x kPqStride (HBM), codebooks pq_m x 256 x pq_dsub f32
+  const uint8_t *pq_codes;
+  const float *pq_cb;
+  int32_t pq_m, pq_dsub;
   uint32_t lds_per_wave;
 };
 
-uint32_t search_lds_bytes(int Lcap, int nav_stride, int hash_bits);
+// Per-wave LDS bytes; kcap (result capacity, the batch k) and pq_m only for
+// compressed navigation.
+uint32_t search_lds_bytes(int Lcap, int nav_stride, int hash_bits, int kcap = 0, int pq_m = 0);
 // Continuous-batching server: a persistent kernel whose waves take queries
 // from a ring in device memory as the host publishes them.
 //   ring entry (entry_bytes): u32 seq+1, u32 result slot, u32 k | L << 16,
@@ -88,9 +104,18 @@ hipError_t launch_server(const ServerArgs &a, int dtype, int waves_per_block,
 // persistent: grid sized to the resident capacity of the GPU; waves take
 // queries from a->work (which must be zero at launch) until all are done.
 // The schedule follows a.delay and a.beam: strict or one-step-stale kernels
-// for beam 1 and delay <= 1, the generic FIFO kernel otherwise.
+// for beam 1 and delay <= 1, the generic FIFO kernel otherwise.  a.pq_m > 0
+// selects compressed navigation (launch_search_pq).
 hipError_t launch_search(const SearchArgs &a, int dtype, int transport, int waves_per_block,
                          bool persistent, hipStream_t st);
+hipError_t launch_search_pq(const SearchArgs &a, int dtype, int transport, int waves_per_block,
+                            bool persistent, hipStream_t st);
+// PQ codes of n rows of the navigation copy (rows of nav_stride bytes, d
+// elements of dtype; M <= 32 subspaces of d / M <= 32 dimensions):
+// codes[i * kPqStride + m] = nearest centroid of subspace m (fp32, fixed
+// order, lowest index among equals); bytes M..31 zero.
+hipError_t launch_pq_encode(const uint8_t *nav, int64_t n, int nav_stride, int dtype, int d,
+                            const float *codebooks, int M, uint8_t *codes, hipStream_t st);
 // Kernel-grained synchronisation (ablation): a cooperative grid advances
 // groups of co-resident queries one strict step per round, with grid-wide
 // barriers after the record fetches and after the compute.  `ctl` is

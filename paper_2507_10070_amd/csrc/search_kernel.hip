@@ -25,6 +25,16 @@
 //
 // Distances: u8/i8 exactly as |q|^2 + |x|^2 - 2 q.x with 4-byte dot products
 // (v_dot4), f32 as a sum of squared differences in fp32.
+//
+// Compressed navigation (NAV_PQ; the in-memory quantised vectors of graph
+// indexes, paper section 2.2): neighbours are scored by product-quantisation
+// codes (one 32 B row per node in HBM) against a per-query distance table in
+// LDS, so the candidate list is ordered by PQ distance; each expanded node's
+// exact distance, from the full-precision vector in its record, goes to a
+// sorted result list res[k] in LDS, which is the answer.  The PQ arithmetic
+// is fp32 in one fixed order (table entry: fmaf over the subspace's
+// dimensions in order; PQ distance: sum over subspaces in order), so the
+// list order, and with it the search path, is reproducible exactly.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -187,9 +197,12 @@ struct WaveLds {
   uint32_t *dsc;
   uint32_t *hash;
   uint64_t *fifo;
+  uint64_t *res;   // NAV_PQ: exact (distance << 32 | id) keys, sorted, up to k
+  float *tab;      // NAV_PQ: distance table, pq_m x 256
 };
 
-__host__ __device__ inline LdsLayout lds_layout(int Lcap, int nav_stride, int hash_bits) {
+__host__ __device__ inline LdsLayout lds_layout(int Lcap, int nav_stride, int hash_bits,
+                                                int kcap, int pq_m) {
   LdsLayout o;
   uint32_t off = 0;
   o.cand = off; off += 8u * (uint32_t)Lcap;
@@ -200,6 +213,8 @@ __host__ __device__ inline LdsLayout lds_layout(int Lcap, int nav_stride, int ha
   o.dsc = off; off += 4u * 64u;
   o.hash = off; off += 4u << hash_bits;
   o.fifo = off; off += 8u * (uint32_t)kMaxPipe;
+  o.res = off; off += 8u * (uint32_t)kcap;
+  o.tab = off; off += 4u * (uint32_t)kPqKsub * (uint32_t)pq_m;
   o.bytes = (off + 15u) & ~15u;
   return o;
 }
@@ -241,7 +256,15 @@ __device__ __forceinline__ QueryIO batch_io(const SearchArgs &A, int64_t qi) {
   return io;
 }
 
-template <int DT, int CPL, int TR>
+// Component i of the query in LDS as a float (exact for u8 and i8).
+template <int DT>
+__device__ __forceinline__ float query_elem(const uint8_t *qbuf, int i) {
+  if (DT == DT_U8) return (float)qbuf[i];
+  if (DT == DT_I8) return (float)(int8_t)qbuf[i];
+  return ((const float *)qbuf)[i];
+}
+
+template <int DT, int CPL, int TR, int NAV = NAV_FULL>
 struct Searcher {
   using D = Dist<DT>;
   using Acc = typename D::Acc;
@@ -252,6 +275,7 @@ struct Searcher {
   uint4 qv[CPL];
   Acc qq;
   int nc;
+  int nres;       // NAV_PQ: entries of S.res
   int L, k;       // this query's list size and result count
   QueryIO io;
   int64_t qi;
@@ -265,7 +289,8 @@ struct Searcher {
     lane = lane_id();
     sub = lane & 7;
     grp = lane >> 3;
-    const LdsLayout lay = lds_layout(A.Lcap, A.nav_stride, A.hash_bits);
+    const LdsLayout lay = lds_layout(A.Lcap, A.nav_stride, A.hash_bits,
+                                     NAV == NAV_PQ ? A.k : 0, NAV == NAV_PQ ? A.pq_m : 0);
     S.cand = (uint64_t *)(base + lay.cand);
     S.nk = (uint64_t *)(base + lay.nk);
     S.stage = (uint4 *)(base + lay.stage);
@@ -274,6 +299,8 @@ struct Searcher {
     S.dsc = (uint32_t *)(base + lay.dsc);
     S.hash = (uint32_t *)(base + lay.hash);
     S.fifo = (uint64_t *)(base + lay.fifo);
+    S.res = (uint64_t *)(base + lay.res);
+    S.tab = (float *)(base + lay.tab);
     L = io.L;
     k = io.k;
     // query -> LDS, zero padded to the row stride
@@ -294,6 +321,23 @@ struct Searcher {
       a = D::self(qv[c], a);
     }
     qq = group8_sum(a);
+    nres = 0;
+    if (NAV == NAV_PQ) {
+      // distance table: entry m*256 + c is the squared distance of query
+      // subspace m to centroid c (fmaf over its dimensions in order)
+      const int ds = A.pq_dsub;
+      for (int e = lane; e < A.pq_m * kPqKsub; e += 64) {
+        const int q0 = (e >> 8) * ds;
+        const float *c = A.pq_cb + (int64_t)e * ds;
+        float acc = 0.0f;
+        for (int j = 0; j < ds; j++) {
+          const float t = query_elem<DT>(S.qbuf, q0 + j) - c[j];
+          acc = fmaf(t, t, acc);
+        }
+        S.tab[e] = acc;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
     steps = rows = mismatches = 0;
     // request numbers continue per line when lines outlive queries
     seq = A.line_seq ? A.line_seq[io.line] : 0u;
@@ -322,9 +366,28 @@ struct Searcher {
     return D::finish(qq, group8_sum(a));
   }
 
+  // PQ distance of a code row held in two 16 B registers: the table entries
+  // of its pq_m bytes summed in subspace order.
+  __device__ __forceinline__ float pq_sum(const uint4 c0, const uint4 c1) const {
+    const uint32_t w[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+    float s = 0.0f;
+#pragma unroll
+    for (int m = 0; m < kPqMaxM; m++) {
+      if (m < A.pq_m) s += S.tab[m * kPqKsub + ((w[m >> 2] >> (8 * (m & 3))) & 0xFFu)];
+    }
+    return s;
+  }
+
+  __device__ __forceinline__ float pq_dist(uint32_t id) const {
+    const uint4 *p = (const uint4 *)(A.pq_codes + (int64_t)id * kPqStride);
+    return pq_sum(p[0], p[1]);
+  }
+
   __device__ void init_entry() {
     const uint32_t e = (uint32_t)A.entry;
-    uint32_t dist = row_dist(A.nav + (int64_t)e * A.nav_stride);
+    uint32_t dist;
+    if (NAV == NAV_PQ) dist = __float_as_uint(pq_dist(e));
+    else dist = row_dist(A.nav + (int64_t)e * A.nav_stride);
     if (lane == 0) {
       S.cand[0] = ((uint64_t)dist << 32) | e;
       hash_insert(S.hash, A.hash_bits, e);
@@ -502,6 +565,20 @@ struct Searcher {
     }
   }
 
+  // NAV_PQ scoring of S.ids[0..m) (m <= 64): one neighbour per lane, its
+  // 32 B code row in two loads, then pq_m table reads.  Lanes past m re-read
+  // row 0 so that no load sits under a branch; WITH_FETCH issues the record
+  // fetch after the code loads, as gather_block does.
+  template <bool WITH_FETCH>
+  __device__ __forceinline__ void gather_pq(int m, uint32_t fid, bool freal, uint4 &frec) {
+    const uint32_t id = S.ids[lane < m ? lane : 0];
+    const uint4 *p = (const uint4 *)(A.pq_codes + (int64_t)id * kPqStride);
+    const uint4 c0 = p[0], c1 = p[1];
+    if (WITH_FETCH) frec = issue(fid, freal);
+    const float d = pq_sum(c0, c1);
+    if (lane < m) S.dsc[lane] = __float_as_uint(d);
+  }
+
   // Merge the m scored ids into the candidate list (first L of the union).
   // Keys at or above the L-th key of a full list cannot enter it: one
   // broadcast read drops them (most keys, late in a search).  The rest are
@@ -627,11 +704,65 @@ struct Searcher {
     if (dist != (uint32_t)(key >> 32)) mismatches++;
   }
 
+  // NAV_PQ: the staged record's vector gives the node's exact distance,
+  // which enters the sorted result list (first k by (distance, id)).
+  __device__ __forceinline__ void rerank(uint64_t key) {
+    Acc a = Acc(0);
+    if (grp == 0) {
+#pragma unroll
+      for (int c = 0; c < CPL; c++) {
+        const int chunk = sub + 8 * c;
+        uint4 r = make_uint4(0, 0, 0, 0);
+        if (16 * chunk < A.vec_pad) r = S.stage[chunk];
+        a = D::partial(qv[c], r, a);
+      }
+    }
+    const uint32_t dist =
+        (uint32_t)__builtin_amdgcn_readfirstlane((int)D::finish(qq, group8_sum(a)));
+    res_insert(((uint64_t)dist << 32) | ((uint32_t)key & ~kFlag));
+  }
+
+  // Insert a wave-uniform key into S.res[0..nres), capacity k: entries at
+  // and above its rank move up one (the last drops out of a full list).
+  __device__ __forceinline__ void res_insert(uint64_t key) {
+    if (nres >= k && key >= S.res[k - 1]) return;
+    int pos = 0;
+    bool dup = false;
+    for (int b = 0; b < nres; b += 64) {
+      const int i = b + lane;
+      const uint64_t e = i < nres ? S.res[i] : kNoKey;
+      pos += __popcll((unsigned long long)__ballot(e < key));
+      dup |= __ballot(e == key) != 0;
+    }
+    if (dup) return;
+    const int top = nres < k ? nres : k - 1;  // entries [pos, top) move to [pos+1, top+1)
+    for (int t = (top - 1) >> 6; t >= 0 && 64 * t + 63 >= pos; t--) {
+      const int i = 64 * t + lane;
+      const bool mv = i >= pos && i < top;
+      uint64_t e = 0;
+      if (mv) e = S.res[i];
+      __builtin_amdgcn_wave_barrier();
+      if (mv) S.res[i + 1] = e;
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (lane == 0) S.res[pos] = key;
+    nres = nres < k ? nres + 1 : k;
+    __builtin_amdgcn_wave_barrier();
+  }
+
+  // Gather blocks the caller scores before finish_batch: NAV_FULL one block
+  // of 8 * PB rows, NAV_PQ the whole batch.
+  static constexpr int kFirst = NAV == NAV_PQ ? 64 : 8 * PB;
+
   // Score and merge neighbours [b0, b0 + 64) of the staged record, starting
   // at gather block p_start (earlier blocks were done by the caller).
   __device__ __forceinline__ void finish_batch(int m, int p_start) {
     uint4 unused;
-    for (int p0 = p_start; p0 < m; p0 += 8 * PB) gather_block<false>(m, p0, 0u, false, unused);
+    if (NAV == NAV_PQ) {
+      if (p_start == 0) gather_pq<false>(m, 0u, false, unused);
+    } else {
+      for (int p0 = p_start; p0 < m; p0 += 8 * PB) gather_block<false>(m, p0, 0u, false, unused);
+    }
     __builtin_amdgcn_wave_barrier();
     rows += (uint32_t)m;
     if (L <= 64) merge_small(m);
@@ -654,11 +785,13 @@ struct Searcher {
   template <bool RELAXED>
   __device__ __forceinline__ void process_staged(uint64_t ukey, uint32_t fid, bool freal,
                                                  uint4 &frec) {
-    if (A.stats) check_record(ukey);
+    if (NAV == NAV_PQ) rerank(ukey);
+    else if (A.stats) check_record(ukey);
     const int m = filter(0);
     if (m > 0) {
-      gather_block<RELAXED>(m, 0, fid, freal, frec);
-      finish_batch(m, 8 * PB);
+      if (NAV == NAV_PQ) gather_pq<RELAXED>(m, fid, freal, frec);
+      else gather_block<RELAXED>(m, 0, fid, freal, frec);
+      finish_batch(m, kFirst);
     } else if (RELAXED) {
       frec = issue(fid, freal);
     }
@@ -669,11 +802,13 @@ struct Searcher {
   }
 
   __device__ void finish_query() {
+    const uint64_t *out = NAV == NAV_PQ ? S.res : S.cand;
+    const int nout = NAV == NAV_PQ ? nres : nc;
     for (int j = lane; j < io.width; j += 64) {
       int32_t id = -1;
       uint32_t dist = DT == DT_F32 ? 0x7F800000u : 0xFFFFFFFFu;
-      if (j < nc && j < k && !failed) {
-        const uint64_t e = S.cand[j];
+      if (j < nout && j < k && !failed) {
+        const uint64_t e = out[j];
         id = (int32_t)((uint32_t)e & ~kFlag);
         dist = (uint32_t)(e >> 32);
       }
@@ -709,11 +844,11 @@ struct Searcher {
 // in-flight record registers have static names; a slot whose id word holds
 // kNoKey is an empty pipeline slot.
 // One query, start to finish, in the wave's LDS region.
-template <int DT, int CPL, int DELAY, int TR>
+template <int DT, int CPL, int DELAY, int TR, int NAV = NAV_FULL>
 __device__ __forceinline__ void run_query(const SearchArgs &A, uint8_t *lds, int64_t qi,
                                           const QueryIO &io) {
   const unsigned long long t_start = A.times ? __builtin_amdgcn_s_memrealtime() : 0ull;
-  Searcher<DT, CPL, TR> s(A, lds, qi, io);
+  Searcher<DT, CPL, TR, NAV> s(A, lds, qi, io);
   s.init_entry();
   if (DELAY == SCHED_GENERIC) {
     // Any staleness delta and beam width W (section 4.1.2, with W nodes taken
@@ -823,7 +958,7 @@ __device__ __forceinline__ void run_query(const SearchArgs &A, uint8_t *lds, int
   }
 }
 
-template <int DT, int CPL, int DELAY, int TR, bool PERSIST>
+template <int DT, int CPL, int DELAY, int TR, bool PERSIST, int NAV>
 __global__ void __launch_bounds__(256) search_kernel(SearchArgs A) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int wave = threadIdx.x >> 6;
@@ -831,7 +966,7 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs A) {
   if (!PERSIST) {
     const int64_t qi = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (qi >= A.nq) return;
-    run_query<DT, CPL, DELAY, TR>(A, lds, qi, batch_io(A, qi));
+    run_query<DT, CPL, DELAY, TR, NAV>(A, lds, qi, batch_io(A, qi));
     return;
   }
   // Persistent: take queries from the work counter until none is left; every
@@ -843,10 +978,79 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs A) {
     if ((int64_t)t >= A.nq) break;
     const int64_t qi = A.order ? (int64_t)A.order[t] : (int64_t)t;
     if (qi < 0 || qi >= A.nq) continue;  // not a permutation entry: skipped
-    run_query<DT, CPL, DELAY, TR>(A, lds, qi, batch_io(A, qi));
+    run_query<DT, CPL, DELAY, TR, NAV>(A, lds, qi, batch_io(A, qi));
     __builtin_amdgcn_wave_barrier();
   }
 }
+
+template <int DT, int CPL, int DELAY, int TR, int NAV>
+static hipError_t launch_t(const SearchArgs &a, int waves_per_block, bool persistent,
+                           hipStream_t st) {
+  const size_t lds = (size_t)a.lds_per_wave * waves_per_block;
+  const int threads = 64 * waves_per_block;
+  if (!persistent) {
+    const int64_t blocks = (a.nq + waves_per_block - 1) / waves_per_block;
+    hipLaunchKernelGGL((search_kernel<DT, CPL, DELAY, TR, false, NAV>), dim3((unsigned)blocks),
+                       dim3(threads), lds, st, a);
+    return hipGetLastError();
+  }
+  int per_cu = 0, dev = 0, cus = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, (const void *)search_kernel<DT, CPL, DELAY, TR, true, NAV>, threads, lds);
+  if (e != hipSuccess) return e;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return e;
+  int64_t blocks = (int64_t)(per_cu > 0 ? per_cu : 1) * cus;
+  const int64_t need = (a.nq + waves_per_block - 1) / waves_per_block;
+  if (blocks > need) blocks = need;
+  hipLaunchKernelGGL((search_kernel<DT, CPL, DELAY, TR, true, NAV>), dim3((unsigned)blocks),
+                     dim3(threads), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int DT, int CPL, int TR, int NAV>
+static hipError_t launch_d(const SearchArgs &a, int wpb, bool pers, hipStream_t st) {
+  if (a.delay < 0 || a.beam < 1 || (a.delay + 1) * a.beam > kMaxPipe) return hipErrorInvalidValue;
+  if (a.beam == 1 && a.delay == 0) return launch_t<DT, CPL, SCHED_STRICT, TR, NAV>(a, wpb, pers, st);
+  if (a.beam == 1 && a.delay == 1) return launch_t<DT, CPL, SCHED_RELAXED, TR, NAV>(a, wpb, pers, st);
+  return launch_t<DT, CPL, SCHED_GENERIC, TR, NAV>(a, wpb, pers, st);
+}
+
+template <int DT, int CPL, int NAV>
+static hipError_t launch_tr(const SearchArgs &a, int tr, int wpb, bool pers, hipStream_t st) {
+  return tr == TR_DIRECT ? launch_d<DT, CPL, TR_DIRECT, NAV>(a, wpb, pers, st)
+                         : launch_d<DT, CPL, TR_AGENT, NAV>(a, wpb, pers, st);
+}
+
+template <int DT, int NAV>
+static hipError_t launch_c(const SearchArgs &a, int cpl, int tr, int wpb, bool pers,
+                           hipStream_t st) {
+  switch (cpl) {
+    case 1: return launch_tr<DT, 1, NAV>(a, tr, wpb, pers, st);
+    case 2: return launch_tr<DT, 2, NAV>(a, tr, wpb, pers, st);
+    case 3: return launch_tr<DT, 3, NAV>(a, tr, wpb, pers, st);
+    case 4: return launch_tr<DT, 4, NAV>(a, tr, wpb, pers, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int NAV>
+static hipError_t launch_nav(const SearchArgs &a, int dtype, int transport, int waves_per_block,
+                             bool persistent, hipStream_t st) {
+  const int cpl = a.nav_stride / 128;
+  switch (dtype) {
+    case DT_U8: return launch_c<DT_U8, NAV>(a, cpl, transport, waves_per_block, persistent, st);
+    case DT_I8: return launch_c<DT_I8, NAV>(a, cpl, transport, waves_per_block, persistent, st);
+    case DT_F32: return launch_c<DT_F32, NAV>(a, cpl, transport, waves_per_block, persistent, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// The launchers below and the lockstep and server kernels are compiled once;
+// a translation unit that instantiates only the batch kernels for another
+// navigation mode includes this file with FA_SEARCH_TEMPLATES_ONLY defined.
+#ifndef FA_SEARCH_TEMPLATES_ONLY
 
 __global__ void reset_work(uint32_t *work) { *work = 0u; }
 
@@ -1083,58 +1287,6 @@ __global__ void __launch_bounds__(256) server_kernel(ServerArgs S) {
   }
 }
 
-template <int DT, int CPL, int DELAY, int TR>
-static hipError_t launch_t(const SearchArgs &a, int waves_per_block, bool persistent,
-                           hipStream_t st) {
-  const size_t lds = (size_t)a.lds_per_wave * waves_per_block;
-  const int threads = 64 * waves_per_block;
-  if (!persistent) {
-    const int64_t blocks = (a.nq + waves_per_block - 1) / waves_per_block;
-    hipLaunchKernelGGL((search_kernel<DT, CPL, DELAY, TR, false>), dim3((unsigned)blocks),
-                       dim3(threads), lds, st, a);
-    return hipGetLastError();
-  }
-  int per_cu = 0, dev = 0, cus = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per_cu, (const void *)search_kernel<DT, CPL, DELAY, TR, true>, threads, lds);
-  if (e != hipSuccess) return e;
-  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
-    return e;
-  int64_t blocks = (int64_t)(per_cu > 0 ? per_cu : 1) * cus;
-  const int64_t need = (a.nq + waves_per_block - 1) / waves_per_block;
-  if (blocks > need) blocks = need;
-  hipLaunchKernelGGL((search_kernel<DT, CPL, DELAY, TR, true>), dim3((unsigned)blocks),
-                     dim3(threads), lds, st, a);
-  return hipGetLastError();
-}
-
-template <int DT, int CPL, int TR>
-static hipError_t launch_d(const SearchArgs &a, int wpb, bool pers, hipStream_t st) {
-  if (a.delay < 0 || a.beam < 1 || (a.delay + 1) * a.beam > kMaxPipe) return hipErrorInvalidValue;
-  if (a.beam == 1 && a.delay == 0) return launch_t<DT, CPL, SCHED_STRICT, TR>(a, wpb, pers, st);
-  if (a.beam == 1 && a.delay == 1) return launch_t<DT, CPL, SCHED_RELAXED, TR>(a, wpb, pers, st);
-  return launch_t<DT, CPL, SCHED_GENERIC, TR>(a, wpb, pers, st);
-}
-
-template <int DT, int CPL>
-static hipError_t launch_tr(const SearchArgs &a, int tr, int wpb, bool pers, hipStream_t st) {
-  return tr == TR_DIRECT ? launch_d<DT, CPL, TR_DIRECT>(a, wpb, pers, st)
-                         : launch_d<DT, CPL, TR_AGENT>(a, wpb, pers, st);
-}
-
-template <int DT>
-static hipError_t launch_c(const SearchArgs &a, int cpl, int tr, int wpb, bool pers,
-                           hipStream_t st) {
-  switch (cpl) {
-    case 1: return launch_tr<DT, 1>(a, tr, wpb, pers, st);
-    case 2: return launch_tr<DT, 2>(a, tr, wpb, pers, st);
-    case 3: return launch_tr<DT, 3>(a, tr, wpb, pers, st);
-    case 4: return launch_tr<DT, 4>(a, tr, wpb, pers, st);
-    default: return hipErrorInvalidValue;
-  }
-}
-
 template <int DT, int CPL, int TR>
 static hipError_t launch_lockstep_t(const SearchArgs &a, uint32_t *ctl, int wpb, hipStream_t st) {
   const size_t lds = (size_t)a.lds_per_wave * wpb;
@@ -1191,19 +1343,14 @@ hipError_t launch_lockstep(const SearchArgs &a, uint32_t *ctl, int dtype, int tr
   }
 }
 
-uint32_t search_lds_bytes(int Lcap, int nav_stride, int hash_bits) {
-  return lds_layout(Lcap, nav_stride, hash_bits).bytes;
+uint32_t search_lds_bytes(int Lcap, int nav_stride, int hash_bits, int kcap, int pq_m) {
+  return lds_layout(Lcap, nav_stride, hash_bits, kcap, pq_m).bytes;
 }
 
 hipError_t launch_search(const SearchArgs &a, int dtype, int transport, int waves_per_block,
                          bool persistent, hipStream_t st) {
-  const int cpl = a.nav_stride / 128;
-  switch (dtype) {
-    case DT_U8: return launch_c<DT_U8>(a, cpl, transport, waves_per_block, persistent, st);
-    case DT_I8: return launch_c<DT_I8>(a, cpl, transport, waves_per_block, persistent, st);
-    case DT_F32: return launch_c<DT_F32>(a, cpl, transport, waves_per_block, persistent, st);
-    default: return hipErrorInvalidValue;
-  }
+  if (a.pq_m > 0) return launch_search_pq(a, dtype, transport, waves_per_block, persistent, st);
+  return launch_nav<NAV_FULL>(a, dtype, transport, waves_per_block, persistent, st);
 }
 
 template <int DT, int CPL, int DELAY, int TR>
@@ -1267,5 +1414,7 @@ hipError_t launch_reset(uint32_t *work, hipStream_t st) {
   hipLaunchKernelGGL(reset_work, dim3(1), dim3(1), 0, st, work);
   return hipGetLastError();
 }
+
+#endif  // FA_SEARCH_TEMPLATES_ONLY
 
 }  // namespace fa

@@ -20,13 +20,16 @@ TIER_HBM, TIER_HOST, TIER_FILE = 0, 1, 2
 
 TRANSPORT_AUTO, TRANSPORT_DIRECT, TRANSPORT_AGENT = 0, 1, 2
 SYNC_QUERY, SYNC_KERNEL = 0, 1
+NAV_FULL, NAV_PQ = 0, 1
+PQ_DROP_NAV = 1
 
 EXPORTED = ["ann_index_create", "ann_index_info_get", "ann_search", "ann_index_free",
             "ann_last_error", "ann_device_clock_khz", "ann_save_index", "ann_build_index",
             "ann_load_records", "ann_agent_configure", "ann_agent_stats", "ann_search_graph",
             "ann_graph_launch", "ann_graph_free", "ann_server_open", "ann_server_submit",
             "ann_server_poll", "ann_server_stats_get", "ann_server_close", "ann_clock_us",
-            "ann_server_submit_batch", "ann_server_poll_into"]
+            "ann_server_submit_batch", "ann_server_poll_into", "ann_index_set_pq",
+            "ann_index_pq_codes"]
 
 
 class AnnError(RuntimeError):
@@ -43,7 +46,8 @@ class SearchOptions(ctypes.Structure):
                 ("d_phases", ctypes.c_void_p), ("transport", ctypes.c_int32),
                 ("spin_limit", ctypes.c_uint32), ("d_L", ctypes.c_void_p),
                 ("d_k", ctypes.c_void_p), ("d_order", ctypes.c_void_p),
-                ("persistent", ctypes.c_int32), ("sync_grain", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("sync_grain", ctypes.c_int32),
+                ("navigation", ctypes.c_int32)]
 
 
 class IndexInfo(ctypes.Structure):
@@ -51,7 +55,8 @@ class IndexInfo(ctypes.Structure):
                 ("R", ctypes.c_int32), ("entry", ctypes.c_int32), ("slot_bytes", ctypes.c_int32),
                 ("tier", ctypes.c_int32), ("nav_stride", ctypes.c_int32),
                 ("rec_bytes", ctypes.c_int32), ("hbm_bytes", ctypes.c_int64),
-                ("direct_io", ctypes.c_int32)]
+                ("direct_io", ctypes.c_int32), ("pq_m", ctypes.c_int32),
+                ("nav_full", ctypes.c_int32)]
 
 
 class ServerOptions(ctypes.Structure):
@@ -108,6 +113,10 @@ def load_library(path: str = LIB_PATH):
     lib.ann_agent_configure.restype = ctypes.c_int
     lib.ann_agent_stats.argtypes = [vp, u64p, u64p, u64p]
     lib.ann_agent_stats.restype = ctypes.c_int
+    lib.ann_index_set_pq.argtypes = [vp, vp, i32, i32]
+    lib.ann_index_set_pq.restype = ctypes.c_int
+    lib.ann_index_pq_codes.argtypes = [vp, vp]
+    lib.ann_index_pq_codes.restype = ctypes.c_int
     lib.ann_search_graph.argtypes = [vp, vp, i64, i32, i32, i32, ctypes.POINTER(SearchOptions),
                                      vp, vp, vp, vp, ctypes.POINTER(vp)]
     lib.ann_search_graph.restype = ctypes.c_int
@@ -228,6 +237,22 @@ class Index:
             raise RuntimeError("index is closed")
         return self._h
 
+    def set_pq(self, codebooks: np.ndarray, drop_nav: bool = False) -> None:
+        """ann_index_set_pq: encode the base with `codebooks` ([M, 256, d/M]
+        float32) into PQ codes in HBM, for searches with navigation=NAV_PQ."""
+        cb = np.ascontiguousarray(codebooks, dtype=np.float32)
+        if cb.ndim != 3 or cb.shape[1] != 256 or cb.shape[0] * cb.shape[2] != self.d:
+            raise ValueError("codebooks must be [M, 256, d / M] float32")
+        _check(load_library().ann_index_set_pq(self.handle, cb.ctypes.data, cb.shape[0],
+                                               PQ_DROP_NAV if drop_nav else 0))
+
+    def pq_codes(self) -> np.ndarray:
+        """ann_index_pq_codes: the PQ codes, [n, M] uint8 on the host."""
+        info = self.info()
+        out = np.empty((info["n"], info["pq_m"]), dtype=np.uint8)
+        _check(load_library().ann_index_pq_codes(self.handle, out.ctypes.data))
+        return out
+
     def info(self) -> dict:
         out = IndexInfo()
         _check(load_library().ann_index_info_get(self.handle, ctypes.byref(out)))
@@ -253,7 +278,7 @@ def _ptr(t):
 
 def _prepare(index, queries, k, L, R, delay, beam_width, hash_bits, waves_per_block, stats,
              trace, times, phases, transport, spin_limit, L_per_query, k_per_query, order,
-             persistent, out, sync_grain=0):
+             persistent, out, sync_grain=0, navigation=NAV_FULL):
     import torch
 
     if queries.dim() != 2 or queries.shape[1] != index.d:
@@ -278,7 +303,7 @@ def _prepare(index, queries, k, L, R, delay, beam_width, hash_bits, waves_per_bl
     opts = SearchOptions(delay, beam_width, hash_bits, waves_per_block, _ptr(stats), _ptr(trace),
                          trace.shape[1] if trace is not None else 0, _ptr(times), _ptr(phases),
                          transport, spin_limit, _ptr(L_per_query), _ptr(k_per_query), _ptr(order),
-                         1 if persistent else 0, int(sync_grain))
+                         1 if persistent else 0, int(sync_grain), int(navigation))
     return nq, ids, dists, steps, opts
 
 
@@ -286,7 +311,8 @@ def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
            beam_width: int = 1, hash_bits: int = 0, waves_per_block: int = 0, stats=None,
            trace=None, times=None, phases=None, transport: int = TRANSPORT_AUTO,
            spin_limit: int = 0, L_per_query=None, k_per_query=None, order=None,
-           persistent: bool = False, stream=None, out=None, sync_grain: int = SYNC_QUERY):
+           persistent: bool = False, stream=None, out=None, sync_grain: int = SYNC_QUERY,
+           navigation: int = NAV_FULL):
     """ann_search on torch CUDA tensors.
 
     queries: [nq, d] device tensor of the index dtype (uint8/int8/float32).
@@ -299,6 +325,8 @@ def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
     (uneven batches; L and k are then the batch maxima).
     sync_grain: SYNC_QUERY (default) or SYNC_KERNEL (lockstep rounds with
     grid-wide barriers; strict schedule only).
+    navigation: NAV_FULL, or NAV_PQ (PQ codes from Index.set_pq order the
+    list; results re-ranked by exact distance from the records).
     Returns (ids int32 [nq,k], dists [nq,k] int32-viewed uint32 or float32,
     steps int32-viewed uint32 [nq]), all on the device.
     """
@@ -307,7 +335,7 @@ def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
     nq, ids, dists, steps, opts = _prepare(index, queries, k, L, R, delay, beam_width, hash_bits,
                                            waves_per_block, stats, trace, times, phases,
                                            transport, spin_limit, L_per_query, k_per_query,
-                                           order, persistent, out, sync_grain)
+                                           order, persistent, out, sync_grain, navigation)
     st = stream if stream is not None else torch.cuda.current_stream(queries.device)
     _check(load_library().ann_search(index.handle, queries.data_ptr(), nq, k, L, R,
                                      ctypes.byref(opts), ids.data_ptr(), dists.data_ptr(),
@@ -325,11 +353,12 @@ class SearchGraph:
 
     def __init__(self, index: Index, queries, k: int, L: int, stream, R: int = 0,
                  delay: int = 1, hash_bits: int = 0, waves_per_block: int = 0,
-                 L_per_query=None, k_per_query=None, order=None, out=None, beam_width: int = 1):
+                 L_per_query=None, k_per_query=None, order=None, out=None, beam_width: int = 1,
+                 navigation: int = NAV_FULL):
         nq, ids, dists, steps, opts = _prepare(index, queries, k, L, R, delay, beam_width, hash_bits,
                                                waves_per_block, None, None, None, None,
                                                TRANSPORT_DIRECT, 0, L_per_query, k_per_query,
-                                               order, True, out)
+                                               order, True, out, 0, navigation)
         self._keep = (index, queries, ids, dists, steps, L_per_query, k_per_query, order)
         self.ids, self.dists, self.steps = ids, dists, steps
         self.stream = stream
