@@ -225,6 +225,109 @@ def serving_file(fa, ix, queries, kth, L_op, m=2000):
     return out
 
 
+def pq_leg(fa, torch, dev, base, adj, entry, cfg, ix, qd, kth, L_full, stream, subspaces):
+    """Compressed navigation (paper section 2.2): PQ codes in HBM order the
+    candidate list, expanded nodes are re-ranked exactly from their records.
+    Per number of subspaces M: codebook training and GPU encoding time, the
+    recall sweep (up to the first L with recall@10 >= 0.95), and at that L
+    the throughput (records in host DRAM and in HBM, relaxed and strict) and
+    the HBM bytes of navigation per launch against those of the
+    full-precision copy.  L_full None: the full-precision operating L is
+    swept here too."""
+    import numpy as np
+
+    import synth
+
+    nq, k = qd.shape[0], cfg.k
+    info = ix.info()
+    full_sweep = None
+    if L_full is None:
+        full_sweep = []
+        for L in L_SWEEP:
+            ids_, d_, s_ = fa.search(ix, qd, k=k, L=L, delay=1, stream=stream)
+            torch.cuda.synchronize()
+            rec = recall_at(d_.cpu().numpy().view(np.uint32), kth)
+            full_sweep.append({"L": L, "recall@10": round(rec, 4)})
+            if rec >= 0.95:
+                L_full = L
+                break
+        L_full = L_full or L_SWEEP[-1]
+    out = (torch.empty((nq, k), dtype=torch.int32, device=dev),
+           torch.empty((nq, k), dtype=torch.int32, device=dev),
+           torch.empty((nq,), dtype=torch.int32, device=dev))
+
+    def timed(index, L, delay, reps=5, **kw):
+        fa.search(index, qd, k=k, L=L, delay=delay, out=out, stream=stream, **kw)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        for _ in range(reps):
+            fa.search(index, qd, k=k, L=L, delay=delay, out=out, stream=stream, **kw)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps
+
+    def stats_at(index, L, delay, **kw):
+        st = torch.zeros(3, dtype=torch.int64, device=dev)
+        fa.search(index, qd, k=k, L=L, delay=delay, out=out, stream=stream, stats=st, **kw)
+        torch.cuda.synchronize()
+        return st.cpu().numpy()
+
+    res = {"workload": cfg.name, "full_navigation": {
+        "L": L_full, "nav_hbm_bytes": info["n"] * info["nav_stride"],
+        "relaxed_qps": round(nq / (timed(ix, L_full, 1) / 1e3), 1)}}
+    if full_sweep is not None:
+        res["full_navigation"]["sweep"] = full_sweep
+    s_full = stats_at(ix, L_full, 1)
+    res["full_navigation"]["nav_bytes_per_launch"] = int(s_full[1]) * info["nav_stride"]
+    hix = fa.Index(base, adj, entry, cfg.slot, fa.TIER_HBM)
+    try:
+        res["full_navigation"]["records_in_hbm_qps"] = round(nq / (timed(hix, L_full, 1) / 1e3), 1)
+        for M in subspaces:
+            t = time.time()
+            cb = synth.train_codebooks(base, M, iters=8, sample=20000, seed=50 + M)
+            t_train = time.time() - t
+            t = time.time()
+            ix.set_pq(cb)
+            t_enc = time.time() - t
+            hix.set_pq(cb)
+            nav = {"navigation": fa.NAV_PQ}
+            sweep, L_op = [], None
+            for L in L_SWEEP + (384, 512):
+                fa.search(ix, qd, k=k, L=L, delay=1, out=out, stream=stream, **nav)
+                torch.cuda.synchronize()
+                rec = recall_at(out[1].cpu().numpy().view(np.uint32), kth)
+                sweep.append({"L": L, "recall@10": round(rec, 4),
+                              "mean_steps": round(float(out[2].cpu().numpy().mean()), 2)})
+                if rec >= 0.95:
+                    L_op = L
+                    break
+            reached = L_op is not None
+            if L_op is None:  # timed at the largest L of the regular sweep
+                L_op = L_SWEEP[-1]
+            s = stats_at(ix, L_op, 1, **nav)
+            ms_r = timed(ix, L_op, 1, **nav)
+            ms_s = timed(ix, L_op, 0, **nav)
+            ms_h = timed(hix, L_op, 1, **nav)
+            res["M%d" % M] = {
+                "train_s": round(t_train, 1), "encode_s": round(t_enc, 2),
+                "code_hbm_bytes": info["n"] * 32, "code_bytes_per_node": M,
+                "L": L_op, "recall_target_reached": reached, "sweep": sweep,
+                "relaxed_qps": round(nq / (ms_r / 1e3), 1),
+                "strict_qps": round(nq / (ms_s / 1e3), 1),
+                "records_in_hbm_qps": round(nq / (ms_h / 1e3), 1),
+                "expansions": int(s[0]), "codes_scored": int(s[1]),
+                "nav_bytes_per_launch": int(s[1]) * M,
+                "nav_bytes_loaded_per_launch": int(s[1]) * 32,
+                "host_link_bytes_per_launch": int(s[0]) * info["rec_bytes"],
+                # records in HBM: algorithmic bytes (codes + records) per second
+                "records_in_hbm_GBps": round((int(s[1]) * M + int(s[0]) * info["rec_bytes"]) /
+                                             (ms_h / 1e3) / 1e9, 1)}
+            log("PQ M=%d: %s" % (M, {kk: v for kk, v in res["M%d" % M].items() if kk != "sweep"}))
+    finally:
+        hix.close()
+    return res
+
+
 def batched_file_leg(fa, torch, dev, n, nq_total):
     """Batched form at scale: n int8 vectors of d = 100 (4,096-component
     mixture), degree-48 graph, 512 B records in a file read with O_DIRECT by
@@ -338,6 +441,8 @@ def main():
                     help="skip the agent-transport and file-tier measurements")
     ap.add_argument("--file-queries", type=int, default=1000,
                     help="queries of the file-tier measurement (records read with O_DIRECT)")
+    ap.add_argument("--no-pq", action="store_true",
+                    help="skip the compressed (PQ) navigation leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device-to-device copy (scale reference "
                          "for memory counters)")
@@ -595,6 +700,23 @@ def main():
                                   "hbm_frac": round(byt / (ms_h / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
             log("records in HBM: %s" % hbm_tier)
 
+    # ---- compressed navigation: PQ codes in HBM, exact re-rank from records,
+    # on this workload (isotropic clusters: the hard case for PQ) and on one of
+    # intrinsic dimension 16 (the structure of real descriptors)
+    pq = None
+    if not args.no_pq and tier == fa.TIER_HOST:
+        pq = {"isotropic": pq_leg(fa, torch, dev, base, adj, entry, cfg, ix, qd, kth, op[1],
+                                  stream, (16, 32))}
+        lcfg = synth.WORKLOADS["1m-u8-128-latent16"]
+        lbase, lq = synth.make_dataset(lcfg, n=n, nq=nq)
+        ladj, lentry = synth.build_graph(lbase, lcfg.R, 3000 + lcfg.seed_offset, threads=threads)
+        lkth = ground_truth(lbase, lq, k, torch, dev)
+        log("latent-16 workload ready")
+        with fa.Index(lbase, ladj, lentry, lcfg.slot, tier) as lix:
+            pq["latent16"] = pq_leg(fa, torch, dev, lbase, ladj, lentry, lcfg, lix,
+                                    torch.from_numpy(lq).to(dev), lkth, None, stream, (16, 32))
+        del lbase, ladj
+
     # ---- the paper's query-grained I/O stack on the same workload: agent
     # transport from pinned DRAM (all queries) and from a file (O_DIRECT)
     transports = None
@@ -730,6 +852,7 @@ def main():
         "batched": batched,
         "batched_file": batched_file,
         "records_in_hbm": hbm_tier,
+        "pq_navigation": pq,
         "transports": transports,
         "serving": serving,
         "cpu_baseline": cpu,

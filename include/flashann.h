@@ -100,7 +100,8 @@ typedef struct {
   int32_t beam_width;      /* W, nodes selected per iteration (default 1);
                               (delay + 1) * W <= 8 nodes may be in flight */
   int32_t hash_bits;       /* log2 of the per-query visited-hash slots (0 = default 10) */
-  int32_t waves_per_block; /* queries per workgroup, 1..4 (0 = default 4) */
+  int32_t waves_per_block; /* queries per workgroup, 1..4 (0 = 4, or 2 or 1 when
+                              the LDS of a workgroup cannot hold 4 queries) */
   unsigned long long *d_stats; /* optional device counters, 3 x u64, accumulated:
                                   [0] expansions [1] neighbour distances computed
                                   [2] records whose own vector disagreed with the

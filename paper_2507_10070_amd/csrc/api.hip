@@ -605,7 +605,8 @@ int prepare_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, 
   o.beam_width = 1;
   if (opts) o = *opts;
   if (o.hash_bits == 0) o.hash_bits = 10;
-  if (o.waves_per_block == 0) o.waves_per_block = 4;
+  const bool auto_wpb = o.waves_per_block == 0;
+  if (auto_wpb) o.waves_per_block = 4;
   if (o.delay < 0) return fail(ANN_EINVAL, "delay=%d must be >= 0", o.delay);
   if (o.beam_width < 1) return fail(ANN_EINVAL, "beam_width=%d must be >= 1", o.beam_width);
   if ((int64_t)(o.delay + 1) * o.beam_width > fa::kMaxPipe)
@@ -691,6 +692,11 @@ int prepare_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, 
   }
   a.lds_per_wave = fa::search_lds_bytes(a.Lcap, a.nav_stride, a.hash_bits,
                                         a.pq_m ? a.k : 0, a.pq_m);
+  // the default queries per workgroup shrinks to what the LDS holds
+  while (auto_wpb && o.waves_per_block > 1 &&
+         (int64_t)a.lds_per_wave * o.waves_per_block > 160 * 1024)
+    o.waves_per_block /= 2;
+  *o_out = o;
   if ((int64_t)a.lds_per_wave * o.waves_per_block > 160 * 1024)
     return fail(ANN_EINVAL, "LDS need %u B per query x %d exceeds 160 KiB", a.lds_per_wave,
                 o.waves_per_block);
