@@ -308,10 +308,18 @@ def pq_leg(fa, torch, dev, base, adj, entry, cfg, ix, qd, kth, L_full, stream, s
             ms_r = timed(ix, L_op, 1, **nav)
             ms_s = timed(ix, L_op, 0, **nav)
             ms_h = timed(hix, L_op, 1, **nav)
+            # the two ways of forming PQ distances (same results)
+            by_scoring = {}
+            for name, sc in (("table", fa.PQ_TABLE), ("cache", fa.PQ_CACHE)):
+                by_scoring[name] = {
+                    "relaxed_qps": round(nq / (timed(ix, L_op, 1, pq_scoring=sc, **nav) / 1e3), 1),
+                    "records_in_hbm_qps": round(
+                        nq / (timed(hix, L_op, 1, pq_scoring=sc, **nav) / 1e3), 1)}
             res["M%d" % M] = {
                 "train_s": round(t_train, 1), "encode_s": round(t_enc, 2),
                 "code_hbm_bytes": info["n"] * 32, "code_bytes_per_node": M,
                 "L": L_op, "recall_target_reached": reached, "sweep": sweep,
+                "by_scoring": by_scoring,
                 "relaxed_qps": round(nq / (ms_r / 1e3), 1),
                 "strict_qps": round(nq / (ms_s / 1e3), 1),
                 "records_in_hbm_qps": round(nq / (ms_h / 1e3), 1),

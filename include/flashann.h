@@ -70,6 +70,15 @@ typedef enum {
                        re-ranked exactly from their records (ann_index_set_pq) */
 } ann_navigation;
 
+/* How PQ distances are formed (ann_search_opts.pq_scoring); both give the
+ * same fp32 values. */
+typedef enum {
+  ANN_PQ_AUTO = 0,  /* ANN_PQ_TABLE when the table is at most 8 KiB, else ANN_PQ_CACHE */
+  ANN_PQ_TABLE = 1, /* per-query table of m x 256 floats in LDS, one read per code byte */
+  ANN_PQ_CACHE = 2  /* centroids read from the codebook (cache-resident) per code byte;
+                       LDS holds only the query, so more queries fit per CU */
+} ann_pq_scoring;
+
 /* ann_index_set_pq flags */
 #define ANN_PQ_DROP_NAV 1 /* release the full-precision navigation copy */
 
@@ -155,6 +164,7 @@ typedef struct {
                               the first k expanded nodes by exact distance.
                               Needs ann_index_set_pq; sync_grain 0 only;
                               d_stats[2] stays 0. */
+  int32_t pq_scoring;      /* ann_pq_scoring (0 = auto); results do not depend on it */
 } ann_search_opts;
 
 /*

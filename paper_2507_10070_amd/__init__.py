@@ -9,4 +9,5 @@ from .flashann import (ANN_ERRORS, AnnError, Index, SearchGraph, SearchOptions, 
                        Server, clock_us, load_library, search,
                        build_index, save_index, device_clock_khz, DTYPE_CODES, TIER_HBM,
                        TIER_HOST, TIER_FILE, TRANSPORT_AUTO, TRANSPORT_DIRECT, TRANSPORT_AGENT,
-                       SYNC_QUERY, SYNC_KERNEL, NAV_FULL, NAV_PQ, PQ_DROP_NAV)
+                       SYNC_QUERY, SYNC_KERNEL, NAV_FULL, NAV_PQ, PQ_DROP_NAV, PQ_AUTO, PQ_TABLE,
+                       PQ_CACHE)

@@ -639,6 +639,8 @@ int prepare_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, 
     return fail(ANN_EINVAL, "PQ navigation needs codes (ann_index_set_pq)");
   if (o.navigation == ANN_NAV_FULL && !ix->nav)
     return fail(ANN_EINVAL, "the full-precision navigation copy was released; use ANN_NAV_PQ");
+  if (o.pq_scoring < 0 || o.pq_scoring > ANN_PQ_CACHE)
+    return fail(ANN_EINVAL, "pq_scoring=%d", o.pq_scoring);
   if (o.navigation == ANN_NAV_PQ && o.sync_grain)
     return fail(ANN_ENOTSUP, "kernel-grained search scores with the full-precision copy only");
   if (nq > 0x7FFFFFFFll) return fail(ANN_EINVAL, "nq=%lld too large", (long long)nq);
@@ -689,9 +691,13 @@ int prepare_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, 
     a.pq_cb = ix->pq_cb;
     a.pq_m = ix->pq_m;
     a.pq_dsub = ix->d / ix->pq_m;
+    // default: the codebook from the cache unless the table is small
+    a.pq_direct = o.pq_scoring == ANN_PQ_CACHE ||
+                  (o.pq_scoring == 0 && ix->pq_m * fa::kPqKsub * 4 > 8192);
+    a.pq_floats = a.pq_direct ? (int32_t)round_up(ix->d, 4) : ix->pq_m * fa::kPqKsub;
   }
   a.lds_per_wave = fa::search_lds_bytes(a.Lcap, a.nav_stride, a.hash_bits,
-                                        a.pq_m ? a.k : 0, a.pq_m);
+                                        a.pq_m ? a.k : 0, a.pq_floats);
   // the default queries per workgroup shrinks to what the LDS holds
   while (auto_wpb && o.waves_per_block > 1 &&
          (int64_t)a.lds_per_wave * o.waves_per_block > 160 * 1024)

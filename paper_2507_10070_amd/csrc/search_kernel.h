@@ -66,16 +66,19 @@ struct SearchArgs {
   const int32_t *order;    // optional processing order (persistent launches)
   uint32_t *work;          // persistent launches: device work counter, zero at launch
   int32_t delay, beam;     // SCHED_GENERIC: staleness and beam width, (delay+1)*beam <= kMaxPipe
-  // NAV_PQ (pq_m > 0): codes n x kPqStride (HBM), codebooks pq_m x 256 x pq_dsub f32
+  // NAV_PQ (pq_m > 0): codes n x kPqStride (HBM), codebooks pq_m x 256 x pq_dsub f32.
+  // pq_direct: centroids read from the cache per code instead of a per-query
+  // LDS table (same arithmetic); pq_floats: LDS floats of either
   const uint8_t *pq_codes;
   const float *pq_cb;
-  int32_t pq_m, pq_dsub;
+  int32_t pq_m, pq_dsub, pq_direct, pq_floats;
   uint32_t lds_per_wave;
 };
 
-// Per-wave LDS bytes; kcap (result capacity, the batch k) and pq_m only for
-// compressed navigation.
-uint32_t search_lds_bytes(int Lcap, int nav_stride, int hash_bits, int kcap = 0, int pq_m = 0);
+// Per-wave LDS bytes; kcap (result capacity, the batch k) and pq_floats
+// (SearchArgs::pq_floats) only for compressed navigation.
+uint32_t search_lds_bytes(int Lcap, int nav_stride, int hash_bits, int kcap = 0,
+                          int pq_floats = 0);
 // Continuous-batching server: a persistent kernel whose waves take queries
 // from a ring in device memory as the host publishes them.
 //   ring entry (entry_bytes): u32 seq+1, u32 result slot, u32 k | L << 16,

@@ -198,11 +198,12 @@ struct WaveLds {
   uint32_t *hash;
   uint64_t *fifo;
   uint64_t *res;   // NAV_PQ: exact (distance << 32 | id) keys, sorted, up to k
-  float *tab;      // NAV_PQ: distance table, pq_m x 256
+  float *tab;      // NAV_PQ: distance table, pq_m x 256 -- or, when centroids
+                   // are read from the cache instead, the query as d floats
 };
 
 __host__ __device__ inline LdsLayout lds_layout(int Lcap, int nav_stride, int hash_bits,
-                                                int kcap, int pq_m) {
+                                                int kcap, int pq_floats) {
   LdsLayout o;
   uint32_t off = 0;
   o.cand = off; off += 8u * (uint32_t)Lcap;
@@ -214,7 +215,8 @@ __host__ __device__ inline LdsLayout lds_layout(int Lcap, int nav_stride, int ha
   o.hash = off; off += 4u << hash_bits;
   o.fifo = off; off += 8u * (uint32_t)kMaxPipe;
   o.res = off; off += 8u * (uint32_t)kcap;
-  o.tab = off; off += 4u * (uint32_t)kPqKsub * (uint32_t)pq_m;
+  off = (off + 15u) & ~15u;  // 16 B reads of the query floats
+  o.tab = off; off += 4u * (uint32_t)pq_floats;
   o.bytes = (off + 15u) & ~15u;
   return o;
 }
@@ -284,13 +286,14 @@ struct Searcher {
   bool failed;    // TR_AGENT: a record read failed or timed out
   unsigned long long t_fetch, t_comp;  // summed phase ticks (strict, optional)
 
-  __device__ Searcher(const SearchArgs &args, uint8_t *base, int64_t query, const QueryIO &qio)
+  __device__ __forceinline__ Searcher(const SearchArgs &args, uint8_t *base, int64_t query,
+                                      const QueryIO &qio)
       : A(args), io(qio), qi(query) {
     lane = lane_id();
     sub = lane & 7;
     grp = lane >> 3;
     const LdsLayout lay = lds_layout(A.Lcap, A.nav_stride, A.hash_bits,
-                                     NAV == NAV_PQ ? A.k : 0, NAV == NAV_PQ ? A.pq_m : 0);
+                                     NAV == NAV_PQ ? A.k : 0, NAV == NAV_PQ ? A.pq_floats : 0);
     S.cand = (uint64_t *)(base + lay.cand);
     S.nk = (uint64_t *)(base + lay.nk);
     S.stage = (uint4 *)(base + lay.stage);
@@ -322,7 +325,11 @@ struct Searcher {
     }
     qq = group8_sum(a);
     nres = 0;
-    if (NAV == NAV_PQ) {
+    if (NAV == NAV_PQ && A.pq_direct) {
+      // centroids read from the cache per scored code: the query as floats
+      for (int i = lane; i < A.pq_m * A.pq_dsub; i += 64) S.tab[i] = query_elem<DT>(S.qbuf, i);
+      __builtin_amdgcn_wave_barrier();
+    } else if (NAV == NAV_PQ) {
       // distance table: entry m*256 + c is the squared distance of query
       // subspace m to centroid c (fmaf over its dimensions in order)
       const int ds = A.pq_dsub;
@@ -366,11 +373,117 @@ struct Searcher {
     return D::finish(qq, group8_sum(a));
   }
 
-  // PQ distance of a code row held in two 16 B registers: the table entries
-  // of its pq_m bytes summed in subspace order.
+  // Squared distance of query subspace m (floats in S.tab) to centroid c,
+  // read from the codebook: fmaf over the subspace's dimensions in order --
+  // the same value as table entry m*256 + c.
+  __device__ __forceinline__ float pq_sub_direct(int m, uint32_t c) const {
+    const int ds = A.pq_dsub;
+    const float *q = S.tab + m * ds;
+    const float *cc = A.pq_cb + ((int64_t)m * kPqKsub + c) * ds;
+    float acc = 0.0f;
+    for (int j = 0; j < ds; j++) {
+      const float t = q[j] - cc[j];
+      acc = fmaf(t, t, acc);
+    }
+    return acc;
+  }
+
+  // PQ distance of a code row held in two 16 B registers: the sub-distances
+  // of its pq_m bytes (table entries, or computed from the codebook) summed
+  // in subspace order.
+  // Code word I (bytes 4I..4I+3) of a code row held in two registers.
+  template <int I>
+  __device__ __forceinline__ static uint32_t code_word(const uint4 c0, const uint4 c1) {
+    if constexpr (I == 0) return c0.x;
+    else if constexpr (I == 1) return c0.y;
+    else if constexpr (I == 2) return c0.z;
+    else if constexpr (I == 3) return c0.w;
+    else if constexpr (I == 4) return c1.x;
+    else if constexpr (I == 5) return c1.y;
+    else if constexpr (I == 6) return c1.z;
+    else return c1.w;
+  }
+
+  // Subspaces [GI*G, GI*G + G) of pq_sum with centroids from the codebook,
+  // d/M = DS in {4, 8}, G = 32 / DS: the group's centroid loads (8 x 16 B
+  // per lane) are issued before its arithmetic; then s += each sub-distance
+  // in subspace order.  Every index is a compile-time constant.
+  template <int DS, int GI>
+  __device__ __forceinline__ float pq_group(const uint4 c0, const uint4 c1, float s) const {
+    constexpr int G = 32 / DS;
+    float4 v[G][DS / 4];
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int m = GI * G + u;
+      const int mm = m < A.pq_m ? m : A.pq_m - 1;  // past pq_m: a valid row, unused
+      uint32_t w;
+      if ((u >> 2) == 0) w = code_word<(GI * G) / 4>(c0, c1);
+      else w = code_word<(GI * G) / 4 + ((G - 1) >> 2)>(c0, c1);
+      const uint32_t c = (w >> (8 * (m & 3))) & 0xFFu;
+      const float4 *cc = (const float4 *)(A.pq_cb + ((int64_t)mm * kPqKsub + c) * DS);
+#pragma unroll
+      for (int h = 0; h < DS / 4; h++) v[u][h] = cc[h];
+    }
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      if (GI * G + u < A.pq_m) {
+        const float4 *q = (const float4 *)(S.tab + (GI * G + u) * DS);
+        float acc = 0.0f, t;
+#pragma unroll
+        for (int h = 0; h < DS / 4; h++) {
+          const float4 qq = q[h];
+          t = qq.x - v[u][h].x; acc = fmaf(t, t, acc);
+          t = qq.y - v[u][h].y; acc = fmaf(t, t, acc);
+          t = qq.z - v[u][h].z; acc = fmaf(t, t, acc);
+          t = qq.w - v[u][h].w; acc = fmaf(t, t, acc);
+        }
+        s += acc;
+      }
+    }
+    return s;
+  }
+
+  // Groups GI, GI+1, ... of pq_sum_direct while they hold subspaces
+  // (at most kPqMaxM / G groups).
+  template <int DS, int GI>
+  __device__ __forceinline__ float pq_groups_from(const uint4 c0, const uint4 c1, float s) const {
+    constexpr int G = 32 / DS;
+    if constexpr (GI * G < kPqMaxM) {
+      if (GI * G < A.pq_m) {
+        s = pq_group<DS, GI>(c0, c1, s);
+        s = pq_groups_from<DS, GI + 1>(c0, c1, s);
+      }
+    }
+    return s;
+  }
+
+  template <int DS>
+  __device__ __forceinline__ float pq_sum_direct(const uint4 c0, const uint4 c1) const {
+    return pq_groups_from<DS, 0>(c0, c1, 0.0f);
+  }
+
   __device__ __forceinline__ float pq_sum(const uint4 c0, const uint4 c1) const {
-    const uint32_t w[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
     float s = 0.0f;
+    if (A.pq_direct && A.pq_dsub == 4) return pq_sum_direct<4>(c0, c1);
+    if (A.pq_direct && A.pq_dsub == 8) return pq_sum_direct<8>(c0, c1);
+    if (A.pq_direct) {
+      // other d/M: not unrolled; the word of subspace m is picked by selects
+      // on the wave-uniform m (an indexed register array would live in scratch)
+      for (int m = 0; m < A.pq_m; m++) {
+        const int i = m >> 2;
+        uint32_t w = c0.x;
+        w = i == 1 ? c0.y : w;
+        w = i == 2 ? c0.z : w;
+        w = i == 3 ? c0.w : w;
+        w = i == 4 ? c1.x : w;
+        w = i == 5 ? c1.y : w;
+        w = i == 6 ? c1.z : w;
+        w = i == 7 ? c1.w : w;
+        s += pq_sub_direct(m, (w >> (8 * (m & 3))) & 0xFFu);
+      }
+      return s;
+    }
+    const uint32_t w[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
 #pragma unroll
     for (int m = 0; m < kPqMaxM; m++) {
       if (m < A.pq_m) s += S.tab[m * kPqKsub + ((w[m >> 2] >> (8 * (m & 3))) & 0xFFu)];
@@ -383,7 +496,7 @@ struct Searcher {
     return pq_sum(p[0], p[1]);
   }
 
-  __device__ void init_entry() {
+  __device__ __forceinline__ void init_entry() {
     const uint32_t e = (uint32_t)A.entry;
     uint32_t dist;
     if (NAV == NAV_PQ) dist = __float_as_uint(pq_dist(e));
@@ -399,7 +512,7 @@ struct Searcher {
   // First unexpanded candidate: marks it and returns its key (kNoKey if none).
   // A correct search expands each node at most once; the cap at n expansions
   // guarantees termination regardless.
-  __device__ uint64_t select() {
+  __device__ __forceinline__ uint64_t select() {
     if ((int64_t)steps >= A.n || failed) return kNoKey;
     for (int base = 0; base < nc; base += 64) {
       const int i = base + lane;
@@ -801,7 +914,7 @@ struct Searcher {
     }
   }
 
-  __device__ void finish_query() {
+  __device__ __forceinline__ void finish_query() {
     const uint64_t *out = NAV == NAV_PQ ? S.res : S.cand;
     const int nout = NAV == NAV_PQ ? nres : nc;
     for (int j = lane; j < io.width; j += 64) {
@@ -1343,8 +1456,8 @@ hipError_t launch_lockstep(const SearchArgs &a, uint32_t *ctl, int dtype, int tr
   }
 }
 
-uint32_t search_lds_bytes(int Lcap, int nav_stride, int hash_bits, int kcap, int pq_m) {
-  return lds_layout(Lcap, nav_stride, hash_bits, kcap, pq_m).bytes;
+uint32_t search_lds_bytes(int Lcap, int nav_stride, int hash_bits, int kcap, int pq_floats) {
+  return lds_layout(Lcap, nav_stride, hash_bits, kcap, pq_floats).bytes;
 }
 
 hipError_t launch_search(const SearchArgs &a, int dtype, int transport, int waves_per_block,

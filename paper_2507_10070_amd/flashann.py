@@ -21,6 +21,7 @@ TIER_HBM, TIER_HOST, TIER_FILE = 0, 1, 2
 TRANSPORT_AUTO, TRANSPORT_DIRECT, TRANSPORT_AGENT = 0, 1, 2
 SYNC_QUERY, SYNC_KERNEL = 0, 1
 NAV_FULL, NAV_PQ = 0, 1
+PQ_AUTO, PQ_TABLE, PQ_CACHE = 0, 1, 2
 PQ_DROP_NAV = 1
 
 EXPORTED = ["ann_index_create", "ann_index_info_get", "ann_search", "ann_index_free",
@@ -47,7 +48,7 @@ class SearchOptions(ctypes.Structure):
                 ("spin_limit", ctypes.c_uint32), ("d_L", ctypes.c_void_p),
                 ("d_k", ctypes.c_void_p), ("d_order", ctypes.c_void_p),
                 ("persistent", ctypes.c_int32), ("sync_grain", ctypes.c_int32),
-                ("navigation", ctypes.c_int32)]
+                ("navigation", ctypes.c_int32), ("pq_scoring", ctypes.c_int32)]
 
 
 class IndexInfo(ctypes.Structure):
@@ -278,7 +279,7 @@ def _ptr(t):
 
 def _prepare(index, queries, k, L, R, delay, beam_width, hash_bits, waves_per_block, stats,
              trace, times, phases, transport, spin_limit, L_per_query, k_per_query, order,
-             persistent, out, sync_grain=0, navigation=NAV_FULL):
+             persistent, out, sync_grain=0, navigation=NAV_FULL, pq_scoring=PQ_AUTO):
     import torch
 
     if queries.dim() != 2 or queries.shape[1] != index.d:
@@ -303,7 +304,8 @@ def _prepare(index, queries, k, L, R, delay, beam_width, hash_bits, waves_per_bl
     opts = SearchOptions(delay, beam_width, hash_bits, waves_per_block, _ptr(stats), _ptr(trace),
                          trace.shape[1] if trace is not None else 0, _ptr(times), _ptr(phases),
                          transport, spin_limit, _ptr(L_per_query), _ptr(k_per_query), _ptr(order),
-                         1 if persistent else 0, int(sync_grain), int(navigation))
+                         1 if persistent else 0, int(sync_grain), int(navigation),
+                         int(pq_scoring))
     return nq, ids, dists, steps, opts
 
 
@@ -312,7 +314,7 @@ def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
            trace=None, times=None, phases=None, transport: int = TRANSPORT_AUTO,
            spin_limit: int = 0, L_per_query=None, k_per_query=None, order=None,
            persistent: bool = False, stream=None, out=None, sync_grain: int = SYNC_QUERY,
-           navigation: int = NAV_FULL):
+           navigation: int = NAV_FULL, pq_scoring: int = PQ_AUTO):
     """ann_search on torch CUDA tensors.
 
     queries: [nq, d] device tensor of the index dtype (uint8/int8/float32).
@@ -327,6 +329,8 @@ def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
     grid-wide barriers; strict schedule only).
     navigation: NAV_FULL, or NAV_PQ (PQ codes from Index.set_pq order the
     list; results re-ranked by exact distance from the records).
+    pq_scoring: PQ_AUTO, PQ_TABLE (per-query LDS table) or PQ_CACHE
+    (centroids from the cache); the results are the same.
     Returns (ids int32 [nq,k], dists [nq,k] int32-viewed uint32 or float32,
     steps int32-viewed uint32 [nq]), all on the device.
     """
@@ -335,7 +339,8 @@ def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
     nq, ids, dists, steps, opts = _prepare(index, queries, k, L, R, delay, beam_width, hash_bits,
                                            waves_per_block, stats, trace, times, phases,
                                            transport, spin_limit, L_per_query, k_per_query,
-                                           order, persistent, out, sync_grain, navigation)
+                                           order, persistent, out, sync_grain, navigation,
+                                           pq_scoring)
     st = stream if stream is not None else torch.cuda.current_stream(queries.device)
     _check(load_library().ann_search(index.handle, queries.data_ptr(), nq, k, L, R,
                                      ctypes.byref(opts), ids.data_ptr(), dists.data_ptr(),

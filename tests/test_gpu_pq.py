@@ -72,27 +72,38 @@ def test_codes_bit_exact(u8w, M):
     np.testing.assert_array_equal(got, oracle.pq_encode(base, cbs[M]))
 
 
+SCORINGS = ["table", "cache"]
+
+
+def scoring(name):
+    return {"table": fa.PQ_TABLE, "cache": fa.PQ_CACHE}[name]
+
+
+@pytest.mark.parametrize("sc", SCORINGS)
 @pytest.mark.parametrize("tier", ["hbm", "host"])
 @pytest.mark.parametrize("delay,beam", [(0, 1), (1, 1), (2, 2), (1, 4)])
 @pytest.mark.parametrize("L", [16, 64, 200])
-def test_u8_parity(u8w, tier, delay, beam, L):
+def test_u8_parity(u8w, sc, tier, delay, beam, L):
     base, q, adj, entry, cbs = u8w
     t = fa.TIER_HBM if tier == "hbm" else fa.TIER_HOST
     with fa.Index(base, adj, entry, 512, t) as ix:
         ix.set_pq(cbs[16])
-        g = run(ix, q, 10, L, delay=delay, beam_width=beam, trace_cap=800)
+        g = run(ix, q, 10, L, delay=delay, beam_width=beam, trace_cap=800,
+                pq_scoring=scoring(sc))
     ref = oracle.search(base, adj, entry, q, 10, L, delay=delay, beam=beam, trace_cap=800,
                         codebooks=cbs[16])
     assert_int_parity(g, ref)
 
 
+@pytest.mark.parametrize("sc", SCORINGS)
 @pytest.mark.parametrize("M", [8, 32])
 @pytest.mark.parametrize("persistent", [False, True])
-def test_u8_subspaces_and_persistent(u8w, M, persistent):
+def test_u8_subspaces_and_persistent(u8w, sc, M, persistent):
     base, q, adj, entry, cbs = u8w
     with fa.Index(base, adj, entry, 512) as ix:
         ix.set_pq(cbs[M])
-        g = run(ix, q, 10, 48, delay=1, persistent=persistent, trace_cap=500)
+        g = run(ix, q, 10, 48, delay=1, persistent=persistent, trace_cap=500,
+                pq_scoring=scoring(sc))
     ref = oracle.search(base, adj, entry, q, 10, 48, delay=1, trace_cap=500, codebooks=cbs[M])
     assert_int_parity(g, ref)
 
@@ -102,8 +113,8 @@ def test_k_and_L_edges(u8w, k, L):
     base, q, adj, entry, cbs = u8w
     with fa.Index(base, adj, entry, 512) as ix:
         ix.set_pq(cbs[16])
-        for delay in (0, 1):
-            g = run(ix, q[:37], k, L, delay=delay)
+        for delay, sc in ((0, "table"), (1, "table"), (1, "cache")):
+            g = run(ix, q[:37], k, L, delay=delay, pq_scoring=scoring(sc))
             ref = oracle.search(base, adj, entry, q[:37], k, L, delay=delay, codebooks=cbs[16])
             assert_int_parity(g, ref)
 
@@ -134,8 +145,9 @@ def test_agent_transport_file_tier(u8w, tmp_path):
     with fa.Index.load(d, fa.TIER_FILE) as ix:
         ix.configure_agent(threads=8)
         ix.set_pq(cbs[16])
-        for delay, beam in ((0, 1), (1, 1), (1, 2)):
-            g = run(ix, q[:120], 10, 64, delay=delay, beam_width=beam, trace_cap=500)
+        for delay, beam, sc in ((0, 1, "table"), (1, 1, "cache"), (1, 2, "table")):
+            g = run(ix, q[:120], 10, 64, delay=delay, beam_width=beam, trace_cap=500,
+                    pq_scoring=scoring(sc))
             ref = oracle.search(base, adj, entry, q[:120], 10, 64, delay=delay, beam=beam,
                                 trace_cap=500, codebooks=cbs[16])
             assert_int_parity(g, ref)
@@ -167,8 +179,8 @@ def test_i8_parity(dt, d, M, R):
     with fa.Index(base, adj, entry, slot_for(d, 1, R)) as ix:
         ix.set_pq(cb)
         np.testing.assert_array_equal(ix.pq_codes(), oracle.pq_encode(base, cb))
-        for delay in (0, 1):
-            g = run(ix, q, 10, 80, delay=delay, trace_cap=600)
+        for delay, sc in ((0, "table"), (1, "table"), (1, "cache")):
+            g = run(ix, q, 10, 80, delay=delay, trace_cap=600, pq_scoring=scoring(sc))
             ref = oracle.search(base, adj, entry, q, 10, 80, delay=delay, trace_cap=600,
                                 codebooks=cb)
             assert_int_parity(g, ref)
@@ -183,8 +195,8 @@ def test_f32_parity(d, M):
     with fa.Index(base, adj, entry, slot_for(d, 4, 32)) as ix:
         ix.set_pq(cb)
         np.testing.assert_array_equal(ix.pq_codes(), oracle.pq_encode(base, cb))
-        for delay in (0, 1):
-            g = run(ix, q, 10, 96, delay=delay, trace_cap=600)
+        for delay, sc in ((0, "table"), (1, "table"), (1, "cache")):
+            g = run(ix, q, 10, 96, delay=delay, trace_cap=600, pq_scoring=scoring(sc))
             ref = oracle.search(base, adj, entry, q, 10, 96, delay=delay, trace_cap=600,
                                 codebooks=cb)
             np.testing.assert_array_equal(g["trace"], ref["trace"])
@@ -233,3 +245,21 @@ def test_drop_nav_and_errors(u8w):
         with pytest.raises(fa.AnnError) as e:
             fa.Server(ix, hbm_budget_bytes=64 << 20)
         assert e.value.code == -22
+        with pytest.raises(fa.AnnError) as e:
+            fa.search(ix, qd, k=10, L=32, navigation=fa.NAV_PQ, pq_scoring=3)
+        assert e.value.code == -22
+
+
+@pytest.mark.parametrize("M", [12, 6, 3])  # d/M = 4, 8 (partial last groups) and 16
+def test_partial_subspace_groups(M):
+    d = 48
+    base = synth.make_base(4000, d, "u8", 16, 801)
+    q = synth.make_queries(80, d, "u8", 16, 801, 802)
+    adj, entry = synth.build_graph(base, 24, 803, threads=8)
+    cb = synth.train_codebooks(base, M, iters=4, sample=3000, seed=804)
+    with fa.Index(base, adj, entry, slot_for(d, 1, 24)) as ix:
+        ix.set_pq(cb)
+        ref = oracle.search(base, adj, entry, q, 10, 48, delay=1, trace_cap=400, codebooks=cb)
+        for sc in SCORINGS:
+            g = run(ix, q, 10, 48, delay=1, trace_cap=400, pq_scoring=scoring(sc))
+            assert_int_parity(g, ref)
