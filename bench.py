@@ -336,6 +336,54 @@ def pq_leg(fa, torch, dev, base, adj, entry, cfg, ix, qd, kth, L_full, stream, s
     return res
 
 
+def pq_kernel_run(fa, torch, dev, steps):
+    """One compressed-navigation configuration alone, for profiling its kernel:
+    the 1M u8/128 workload of intrinsic dimension 16 with records in HBM, PQ
+    codes with M = 32 scored from the cache, relaxed schedule, L = 64 (its
+    recall@10 >= 0.95 point); `steps` timed launches of 10k queries.  Prints
+    one JSON line with the kernel's algorithmic bytes and rate."""
+    import numpy as np
+
+    import synth
+
+    cfg = synth.WORKLOADS["1m-u8-128-latent16"]
+    base, q = synth.make_dataset(cfg)
+    adj, entry = synth.build_graph(base, cfg.R, 3000 + cfg.seed_offset,
+                                   threads=min(16, os.cpu_count() or 1))
+    kth = ground_truth(base, q, cfg.k, torch, dev)
+    cb = synth.train_codebooks(base, 32, iters=8, sample=20000, seed=50 + 32)
+    stream = torch.cuda.current_stream(dev)
+    qd = torch.from_numpy(q).to(dev)
+    L, M = 64, 32
+    with fa.Index(base, adj, entry, cfg.slot, fa.TIER_HBM) as ix:
+        ix.set_pq(cb)
+        info = ix.info()
+        kw = dict(k=cfg.k, L=L, delay=1, navigation=fa.NAV_PQ, pq_scoring=fa.PQ_CACHE,
+                  stream=stream)
+        st = torch.zeros(3, dtype=torch.int64, device=dev)
+        ids, dists, steps_ = fa.search(ix, qd, stats=st, **kw)
+        torch.cuda.synchronize()
+        rec = recall_at(dists.cpu().numpy().view(np.uint32), kth)
+        s = st.cpu().numpy()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        for _ in range(steps):
+            fa.search(ix, qd, **kw)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / steps
+    byt = int(s[1]) * M + int(s[0]) * info["rec_bytes"] + len(q) * (cfg.d + 8 * cfg.k + 4)
+    print(json.dumps({"pq_kernel": {"workload": "1M u8/128 of intrinsic dimension 16, records in HBM",
+                                    "M": M, "L": L, "scoring": "cache",
+                                    "recall@10": round(rec, 4), "ms_per_launch": round(ms, 4),
+                                    "qps": round(len(q) / (ms / 1e3), 1),
+                                    "expansions": int(s[0]), "codes_scored": int(s[1]),
+                                    "algorithmic_bytes_per_launch": byt,
+                                    "algorithmic_GBps": round(byt / (ms / 1e3) / 1e9, 1),
+                                    "hbm_frac": round(byt / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}}),
+          flush=True)
+
+
 def batched_file_leg(fa, torch, dev, n, nq_total):
     """Batched form at scale: n int8 vectors of d = 100 (4,096-component
     mixture), degree-48 graph, 512 B records in a file read with O_DIRECT by
@@ -451,6 +499,8 @@ def main():
                     help="queries of the file-tier measurement (records read with O_DIRECT)")
     ap.add_argument("--no-pq", action="store_true",
                     help="skip the compressed (PQ) navigation leg")
+    ap.add_argument("--pq-kernel-only", action="store_true",
+                    help="run only one compressed-navigation configuration (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device-to-device copy (scale reference "
                          "for memory counters)")
@@ -470,6 +520,9 @@ def main():
 
     fa.load_library()
     dev = torch.device("cuda:0")
+    if args.pq_kernel_only:
+        pq_kernel_run(fa, torch, dev, args.steps)
+        return
     cfg = synth.WORKLOADS["1m-u8-128"]
     n = args.n or cfg.n
     nq = args.nq or cfg.nq
