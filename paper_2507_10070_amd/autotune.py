@@ -3,8 +3,10 @@
 Two kinds of parameters are tuned on a representative batch:
 
 * tiles that do not change results -- queries per workgroup, visited-hash
-  size, persistent or one-shot grid, and for uneven batches (per-query L) the
-  processing order: as given, or longest list first (`longest_first`);
+  size, persistent or one-shot grid, with compressed navigation the way PQ
+  distances are formed (`pq_scoring`: LDS table or centroids from the cache),
+  and for uneven batches (per-query L) the processing order: as given, or
+  longest list first (`longest_first`);
 * schedule parameters that change the search path but keep it valid -- the
   staleness delay (prefetch depth, paper section 4.1.2) and the beam width W.
   These can move recall a little either way, so a setting is admissible only
@@ -46,10 +48,11 @@ def _bucket(x: int) -> int:
     return b
 
 
-def cache_key(index, L: int, nq: int, uneven: bool = False) -> str:
+def cache_key(index, L: int, nq: int, uneven: bool = False, pq: bool = False) -> str:
     info = index.info()
-    return "dt%d-d%d-R%d-tier%d-L%d-nq%d%s" % (info["dtype"], info["d"], info["R"], info["tier"],
-                                              _bucket(L), _bucket(nq), "-uneven" if uneven else "")
+    return "dt%d-d%d-R%d-tier%d-L%d-nq%d%s%s" % (
+        info["dtype"], info["d"], info["R"], info["tier"], _bucket(L), _bucket(nq),
+        "-uneven" if uneven else "", "-pq%d" % info["pq_m"] if pq else "")
 
 
 def valid(params) -> bool:
@@ -99,7 +102,7 @@ def tune(index, queries, k, L, space=None, reps=3, cache_path=DEFAULT_CACHE, use
     e.g. a tile whose LDS need exceeds the CU).  `progress`, if given, is
     called with each new table row."""
     uneven = extra.get("L_per_query") is not None or extra.get("k_per_query") is not None
-    key = cache_key(index, L, queries.shape[0], uneven)
+    key = cache_key(index, L, queries.shape[0], uneven, extra.get("navigation", 0) == 1)
     cache = {}
     if cache_path and os.path.exists(cache_path):
         try:
@@ -112,6 +115,8 @@ def tune(index, queries, k, L, space=None, reps=3, cache_path=DEFAULT_CACHE, use
     space = dict(space or SPACE)
     if uneven and extra.get("order") is None:
         space.setdefault("longest_first", (False, True))
+    if extra.get("navigation", 0) == 1 and extra.get("pq_scoring") is None:
+        space.setdefault("pq_scoring", (2, 1))  # cache, table
     cur = dict(start or DEFAULT)
     cur = {n: cur.get(n, DEFAULT.get(n, space[n][0])) for n in space}
     if score is None:  # no quality measure: results-neutral parameters only

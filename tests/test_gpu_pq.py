@@ -263,3 +263,20 @@ def test_partial_subspace_groups(M):
         for sc in SCORINGS:
             g = run(ix, q, 10, 48, delay=1, trace_cap=400, pq_scoring=scoring(sc))
             assert_int_parity(g, ref)
+
+
+def test_autotune_picks_a_scoring(u8w):
+    from paper_2507_10070_amd import autotune
+
+    base, q, adj, entry, cbs = u8w
+    qd = torch.from_numpy(np.ascontiguousarray(q)).to("cuda:0")
+    with fa.Index(base, adj, entry, 512) as ix:
+        ix.set_pq(cbs[32])
+        best = autotune.tune(ix, qd, 10, 64, cache_path=None, reps=1, passes=1,
+                             navigation=fa.NAV_PQ)
+        assert best["params"]["pq_scoring"] in (fa.PQ_TABLE, fa.PQ_CACHE)
+        kw = autotune.search_kwargs(best["params"], {"navigation": fa.NAV_PQ})
+        ids, dists, steps = fa.search(ix, qd, k=10, L=64, **kw)
+        torch.cuda.synchronize()
+    ref = oracle.search(base, adj, entry, q, 10, 64, delay=1, codebooks=cbs[32])
+    np.testing.assert_array_equal(ids.cpu().numpy(), ref["ids"])
