@@ -563,6 +563,41 @@ int oracle_search(const void *base, int64_t n, int32_t d, int32_t dtype,
  * dists are the first k of the expanded nodes by exact distance (float64,
  * exact for u8/i8), padded with -1 / +inf.  Other arguments as oracle_search.
  */
+/* Rows [i0, i1) of the base encoded by one thread (oracle_pq_encode on a slice). */
+typedef struct {
+  const void *base;
+  int64_t i0, i1;
+  int32_t d, dtype, M;
+  const float *cb;
+  uint8_t *codes;
+  int err;
+} orc_enc_job;
+
+static void *orc_enc_worker(void *arg) {
+  orc_enc_job *J = (orc_enc_job *)arg;
+  const size_t row = (size_t)J->d * orc_elem_bytes(J->dtype);
+  if (J->i1 > J->i0)
+    J->err = oracle_pq_encode((const char *)J->base + (size_t)J->i0 * row, J->i1 - J->i0, J->d,
+                              J->dtype, J->cb, J->M, J->codes + J->i0 * J->M);
+  return NULL;
+}
+
+static int orc_pq_encode_threads(const void *base, int64_t n, int32_t d, int32_t dtype,
+                                 const float *cb, int32_t M, uint8_t *codes, int32_t threads) {
+  if (threads < 1) threads = 1;
+  orc_enc_job *jobs = (orc_enc_job *)calloc((size_t)threads, sizeof(orc_enc_job));
+  if (!jobs) return ORC_ENOMEM;
+  for (int32_t t = 0; t < threads; t++) {
+    orc_enc_job j = {base, n * t / threads, n * (t + 1) / threads, d, dtype, M, cb, codes, 0};
+    jobs[t] = j;
+  }
+  int rc = orc_run_threads(orc_enc_worker, jobs, sizeof(orc_enc_job), threads);
+  for (int32_t t = 0; t < threads && rc == 0; t++)
+    if (jobs[t].err) rc = jobs[t].err;
+  free(jobs);
+  return rc;
+}
+
 int oracle_search_pq(const void *base, int64_t n, int32_t d, int32_t dtype,
                      const int32_t *adj, int32_t adj_stride, int32_t entry,
                      const void *queries, int64_t nq, int32_t k, int32_t L, int32_t R,
@@ -572,7 +607,7 @@ int oracle_search_pq(const void *base, int64_t n, int32_t d, int32_t dtype,
   if (!base || !codebooks || n < 1 || !orc_pq_check(d, M)) return ORC_EINVAL;
   uint8_t *codes = (uint8_t *)malloc((size_t)n * (size_t)M);
   if (!codes) return ORC_ENOMEM;
-  int rc = oracle_pq_encode(base, n, d, dtype, codebooks, M, codes);
+  int rc = orc_pq_encode_threads(base, n, d, dtype, codebooks, M, codes, threads);
   if (rc == 0)
     rc = orc_search_all(base, n, d, dtype, adj, adj_stride, entry, queries, nq, k, L, R, delay,
                         beam, threads, ids, dists, steps, trace, theta, trace_cap, codes,

@@ -1,9 +1,11 @@
 """Parity at full size: 1M u8/128 vectors, degree-64 graph, 512 B records in
-pinned host DRAM, 10,000 queries, k = 10, L = 192 -- the workload and launch
-configuration the benchmark times.  The GPU runs every query; the oracle
-recomputes a seeded sample of them one by one; sampled rows must match
-bit-exactly (ids, distances, steps), for both schedules and both record
-transports."""
+pinned host DRAM, 10,000 queries, k = 10, at the benchmark's operating L (44)
+and at L = 192 -- the workload and launch configuration the benchmark times.
+The GPU runs every query; the oracle recomputes a seeded sample of them one by
+one; sampled rows must match bit-exactly (ids, distances, steps), for both
+schedules and both record transports.  Compressed navigation likewise on the
+1M workload of intrinsic dimension 16 at its timed configuration (PQ M = 32,
+L = 64, relaxed)."""
 import numpy as np
 import pytest
 
@@ -15,7 +17,6 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 fa = pytest.importorskip("paper_2507_10070_amd")
 
-L_BENCH = 192
 SAMPLE = 256
 
 
@@ -28,20 +29,51 @@ def w1m():
     return cfg, base, q, adj, entry, sample
 
 
+@pytest.mark.parametrize("L", [44, 192])
 @pytest.mark.parametrize("transport", ["direct", "agent"])
-def test_1m_sampled_parity(w1m, transport):
+def test_1m_sampled_parity(w1m, transport, L):
     cfg, base, q, adj, entry, sample = w1m
     tr = fa.TRANSPORT_DIRECT if transport == "direct" else fa.TRANSPORT_AGENT
     qd = torch.from_numpy(q).to("cuda:0")
     with fa.Index(base, adj, entry, cfg.slot, fa.TIER_HOST) as ix:
         for delay in (0, 1):
-            ids, dists, steps = fa.search(ix, qd, k=cfg.k, L=L_BENCH, delay=delay, transport=tr)
+            ids, dists, steps = fa.search(ix, qd, k=cfg.k, L=L, delay=delay, transport=tr)
             torch.cuda.synchronize()
             ids = ids.cpu().numpy()[sample]
             dists = dists.cpu().numpy().view(np.uint32)[sample].astype(np.float64)
             steps = steps.cpu().numpy().view(np.uint32)[sample]
-            ref = oracle.search(base, adj, entry, q[sample], cfg.k, L_BENCH, delay=delay,
+            ref = oracle.search(base, adj, entry, q[sample], cfg.k, L, delay=delay,
                                 threads=16)
             np.testing.assert_array_equal(ids, ref["ids"])
             np.testing.assert_array_equal(dists, ref["dists"])
             np.testing.assert_array_equal(steps, ref["steps"])
+
+
+@pytest.fixture(scope="module")
+def w1m_latent():
+    cfg = synth.WORKLOADS["1m-u8-128-latent16"]
+    base, q = synth.make_dataset(cfg)
+    adj, entry = synth.build_graph(base, cfg.R, 3000 + cfg.seed_offset, threads=16)
+    cb = synth.train_codebooks(base, 32, iters=8, sample=20000, seed=50 + 32)
+    sample = np.sort(np.random.default_rng(54321).choice(cfg.nq, SAMPLE, replace=False))
+    return cfg, base, q, adj, entry, cb, sample
+
+
+@pytest.mark.parametrize("tier,scoring", [("hbm", "cache"), ("host", "table")])
+def test_1m_pq_sampled_parity(w1m_latent, tier, scoring):
+    cfg, base, q, adj, entry, cb, sample = w1m_latent
+    t = fa.TIER_HBM if tier == "hbm" else fa.TIER_HOST
+    sc = fa.PQ_CACHE if scoring == "cache" else fa.PQ_TABLE
+    qd = torch.from_numpy(q).to("cuda:0")
+    with fa.Index(base, adj, entry, cfg.slot, t) as ix:
+        ix.set_pq(cb)
+        ids, dists, steps = fa.search(ix, qd, k=cfg.k, L=64, delay=1, navigation=fa.NAV_PQ,
+                                      pq_scoring=sc)
+        torch.cuda.synchronize()
+        codes = ix.pq_codes()[sample]
+    np.testing.assert_array_equal(codes, oracle.pq_encode(base[sample], cb))
+    ref = oracle.search(base, adj, entry, q[sample], cfg.k, 64, delay=1, threads=16, codebooks=cb)
+    np.testing.assert_array_equal(ids.cpu().numpy()[sample], ref["ids"])
+    np.testing.assert_array_equal(dists.cpu().numpy().view(np.uint32)[sample].astype(np.float64),
+                                  ref["dists"])
+    np.testing.assert_array_equal(steps.cpu().numpy().view(np.uint32)[sample], ref["steps"])
