@@ -80,19 +80,32 @@ def host_cpu():
     return {"model": model, "smt": smt, "online": os.cpu_count()}
 
 
+def _code_only(src: bytes) -> bytes:
+    """C++ source without // comments and blank lines (the code it compiles)."""
+    out = []
+    for line in src.split(b"\n"):
+        i = line.find(b"//")
+        if i >= 0:
+            line = line[:i]
+        line = line.rstrip()
+        if line:
+            out.append(line)
+    return b"\n".join(out)
+
+
 def kernel_source_hash():
-    """Hash of the source the search kernel is compiled from: the kernel
-    header and search_kernel.hip up to the end of the search kernel itself
-    (the lockstep and server kernels and the host launchers follow it and do
-    not change the profiled code)."""
+    """Hash of the code the search kernel is compiled from: the kernel header
+    and search_kernel.hip up to the end of the search kernel itself (the
+    lockstep and server kernels and the host launchers follow it and do not
+    change the profiled code), comments and blank lines left out."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2507_10070_amd", "csrc")
     with open(os.path.join(csrc, "search_kernel.h"), "rb") as fh:
-        h.update(fh.read())
+        h.update(_code_only(fh.read()))
     with open(os.path.join(csrc, "search_kernel.hip"), "rb") as fh:
         src = fh.read()
     end = src.find(b"__global__ void reset_work(")
-    h.update(src if end < 0 else src[:end])
+    h.update(_code_only(src if end < 0 else src[:end]))
     return h.hexdigest()[:16]
 
 

@@ -28,8 +28,9 @@
 //
 // Compressed navigation (NAV_PQ; the in-memory quantised vectors of graph
 // indexes, paper section 2.2): neighbours are scored by product-quantisation
-// codes (one 32 B row per node in HBM) against a per-query distance table in
-// LDS, so the candidate list is ordered by PQ distance; each expanded node's
+// codes (one 32 B row per node in HBM), with sub-distances taken from a
+// per-query table in LDS or computed from centroids read through the cache,
+// so the candidate list is ordered by PQ distance; each expanded node's
 // exact distance, from the full-precision vector in its record, goes to a
 // sorted result list res[k] in LDS, which is the answer.  The PQ arithmetic
 // is fp32 in one fixed order (table entry: fmaf over the subspace's
@@ -679,7 +680,7 @@ struct Searcher {
   }
 
   // NAV_PQ scoring of S.ids[0..m) (m <= 64): one neighbour per lane, its
-  // 32 B code row in two loads, then pq_m table reads.  Lanes past m re-read
+  // 32 B code row in two loads, then pq_m sub-distances (pq_sum).  Lanes past m re-read
   // row 0 so that no load sits under a branch; WITH_FETCH issues the record
   // fetch after the code loads, as gather_block does.
   template <bool WITH_FETCH>
