@@ -316,8 +316,9 @@ int ann_device_clock_khz(int32_t *khz);
  *   waves_per_block (4), hash_bits (10), queue_cap (2^20 waiting arrivals),
  *   idle_polls (50000: empty polls before the kernel leaves; it is started
  *   again when work arrives), beam_width (1); the schedule is that of
- *   ann_search with the same delay and beam width.  The server scores with
- *   the full-precision navigation copy (not after ANN_PQ_DROP_NAV).
+ *   ann_search with the same delay and beam width, and so is the
+ *   navigation (full precision, or PQ codes with exact re-rank).
+ *   waves_per_block 0 = 4, or fewer when the LDS cannot hold 4 queries.
  * Errors: ANN_EINVAL, ANN_ENOMEM (budget too small or allocation), ANN_EIO.
  */
 typedef struct ann_server ann_server;
@@ -330,6 +331,9 @@ typedef struct {
                          line for all the queries it serves (section 4.2) */
   uint32_t spin_limit; /* AGENT: polls of a completion word before a query
                           gives up with ANN_ETIMEDOUT (0 = 2^24) */
+  int32_t navigation;  /* ann_navigation (0 = full precision); ANN_NAV_PQ as
+                          in ann_search_opts (needs ann_index_set_pq) */
+  int32_t pq_scoring;  /* ann_pq_scoring (0 = auto) */
 } ann_server_opts;
 typedef struct {
   uint64_t tag;          /* the caller's tag */

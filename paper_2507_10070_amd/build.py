@@ -10,7 +10,9 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libflashann.so")
-SOURCES = ["search_kernel.hip", "search_pq.hip", "api.hip", "agent.cpp", "server.cpp",
+SOURCES = ["search_kernel.hip", "search_full_u8.hip", "search_full_i8.hip", "search_full_f32.hip",
+           "search_pq_u8.hip", "search_pq_i8.hip", "search_pq_f32.hip", "search_pq.hip",
+           "api.hip", "agent.cpp", "server.cpp",
            # the graph builder of the input generators, for ann_build_index
            os.path.join("..", "..", "synth", "csrc", "graph_build.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

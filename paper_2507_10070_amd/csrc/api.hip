@@ -587,6 +587,18 @@ int check_lockstep(ann_index *ix, hipStream_t st) {
   return ANN_OK;
 }
 
+// Compressed-navigation kernel arguments (codes and codebooks of the index).
+void set_pq_args(const ann_index *ix, int32_t pq_scoring, fa::SearchArgs *a) {
+  a->pq_codes = ix->pq_codes;
+  a->pq_cb = ix->pq_cb;
+  a->pq_m = ix->pq_m;
+  a->pq_dsub = ix->d / ix->pq_m;
+  // default: centroids from the cache unless the table is small
+  a->pq_direct = pq_scoring == ANN_PQ_CACHE ||
+                 (pq_scoring == ANN_PQ_AUTO && ix->pq_m * fa::kPqKsub * 4 > 8192);
+  a->pq_floats = a->pq_direct ? (int32_t)round_up(ix->d, 4) : ix->pq_m * fa::kPqKsub;
+}
+
 // Validates a search and fills the kernel arguments.  Returns ANN_OK with
 // *empty set when there is nothing to launch (nq == 0).
 int prepare_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int32_t L,
@@ -686,16 +698,7 @@ int prepare_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, 
   a.delay = o.delay;
   a.beam = o.beam_width;
   a.pslots = std::max(2, (o.delay + 1) * o.beam_width);
-  if (o.navigation == ANN_NAV_PQ) {
-    a.pq_codes = ix->pq_codes;
-    a.pq_cb = ix->pq_cb;
-    a.pq_m = ix->pq_m;
-    a.pq_dsub = ix->d / ix->pq_m;
-    // default: the codebook from the cache unless the table is small
-    a.pq_direct = o.pq_scoring == ANN_PQ_CACHE ||
-                  (o.pq_scoring == 0 && ix->pq_m * fa::kPqKsub * 4 > 8192);
-    a.pq_floats = a.pq_direct ? (int32_t)round_up(ix->d, 4) : ix->pq_m * fa::kPqKsub;
-  }
+  if (o.navigation == ANN_NAV_PQ) set_pq_args(ix, o.pq_scoring, &a);
   a.lds_per_wave = fa::search_lds_bytes(a.Lcap, a.nav_stride, a.hash_bits,
                                         a.pq_m ? a.k : 0, a.pq_floats);
   // the default queries per workgroup shrinks to what the LDS holds
@@ -887,11 +890,16 @@ int ann_internal_server_transport(ann_index *ix, int32_t requested, int32_t *tr,
 }
 
 int ann_internal_server_args(ann_index *ix, int32_t k_max, int32_t L_max, int32_t hash_bits,
-                             fa::SearchArgs *base, int32_t *dtype) {
+                             int32_t navigation, int32_t pq_scoring, fa::SearchArgs *base,
+                             int32_t *dtype) {
   if (hash_bits < 6 || hash_bits > 14) return fail(ANN_EINVAL, "hash_bits=%d", hash_bits);
-  if (!ix->nav)
-    return fail(ANN_EINVAL, "the server scores with the full-precision navigation copy, "
-                            "which was released");
+  if (navigation != ANN_NAV_FULL && navigation != ANN_NAV_PQ)
+    return fail(ANN_EINVAL, "navigation=%d", navigation);
+  if (pq_scoring < 0 || pq_scoring > ANN_PQ_CACHE) return fail(ANN_EINVAL, "pq_scoring=%d", pq_scoring);
+  if (navigation == ANN_NAV_FULL && !ix->nav)
+    return fail(ANN_EINVAL, "the full-precision navigation copy was released; use ANN_NAV_PQ");
+  if (navigation == ANN_NAV_PQ && !ix->pq_codes)
+    return fail(ANN_EINVAL, "PQ navigation needs codes (ann_index_set_pq)");
   fa::SearchArgs &a = *base;
   a = fa::SearchArgs{};
   a.nav = ix->nav;
@@ -910,7 +918,9 @@ int ann_internal_server_args(ann_index *ix, int32_t k_max, int32_t L_max, int32_
   a.k_stride = k_max;
   a.entry = ix->entry;
   a.hash_bits = hash_bits;
-  a.lds_per_wave = fa::search_lds_bytes(a.Lcap, a.nav_stride, a.hash_bits);
+  if (navigation == ANN_NAV_PQ) set_pq_args(ix, pq_scoring, &a);
+  a.lds_per_wave = fa::search_lds_bytes(a.Lcap, a.nav_stride, a.hash_bits, a.pq_m ? a.k : 0,
+                                        a.pq_floats);
   *dtype = ix->dtype;
   return ANN_OK;
 }

@@ -100,9 +100,12 @@ struct ServerArgs {
   int32_t transport;        // TR_DIRECT, or TR_AGENT: transport line = resident wave index
   uint32_t idle_limit;      // empty polls before a wave leaves
 };
-// The schedule follows a.base.delay and a.base.beam, as in launch_search.
+// The schedule follows a.base.delay and a.base.beam, as in launch_search;
+// a.base.pq_m > 0 selects compressed navigation (launch_server_pq).
 hipError_t launch_server(const ServerArgs &a, int dtype, int waves_per_block,
                          int64_t *resident_waves, hipStream_t st);
+hipError_t launch_server_pq(const ServerArgs &a, int dtype, int waves_per_block,
+                            int64_t *resident_waves, hipStream_t st);
 
 // persistent: grid sized to the resident capacity of the GPU; waves take
 // queries from a->work (which must be zero at launch) until all are done.

@@ -1149,21 +1149,10 @@ static hipError_t launch_c(const SearchArgs &a, int cpl, int tr, int wpb, bool p
   }
 }
 
-template <int NAV>
-static hipError_t launch_nav(const SearchArgs &a, int dtype, int transport, int waves_per_block,
-                             bool persistent, hipStream_t st) {
-  const int cpl = a.nav_stride / 128;
-  switch (dtype) {
-    case DT_U8: return launch_c<DT_U8, NAV>(a, cpl, transport, waves_per_block, persistent, st);
-    case DT_I8: return launch_c<DT_I8, NAV>(a, cpl, transport, waves_per_block, persistent, st);
-    case DT_F32: return launch_c<DT_F32, NAV>(a, cpl, transport, waves_per_block, persistent, st);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-// The launchers below and the lockstep and server kernels are compiled once;
-// a translation unit that instantiates only the batch kernels for another
-// navigation mode includes this file with FA_SEARCH_TEMPLATES_ONLY defined.
+// The launchers below and the lockstep kernel are compiled in this unit
+// only; the units that instantiate the batch and server kernels of one
+// element type and navigation mode include this file with
+// FA_SEARCH_TEMPLATES_ONLY defined.
 #ifndef FA_SEARCH_TEMPLATES_ONLY
 
 __global__ void reset_work(uint32_t *work) { *work = 0u; }
@@ -1313,12 +1302,106 @@ __global__ void reset_ctl(uint32_t *ctl, uint32_t words) {
   for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) ctl[i] = 0u;
 }
 
+template <int DT, int CPL, int TR>
+static hipError_t launch_lockstep_t(const SearchArgs &a, uint32_t *ctl, int wpb, hipStream_t st) {
+  const size_t lds = (size_t)a.lds_per_wave * wpb;
+  const int threads = 64 * wpb;
+  const void *fn = (const void *)lockstep_kernel<DT, CPL, TR>;
+  int per_cu = 0, dev = 0, cus = 0, coop = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
+  if (e != hipSuccess) return e;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return e;
+  if ((e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev)) != hipSuccess)
+    return e;
+  if (!coop || per_cu < 1) return hipErrorNotSupported;
+  int64_t blocks = (int64_t)per_cu * cus;
+  const int64_t need = (a.nq + wpb - 1) / wpb;
+  if (blocks > need) blocks = need;
+  if (blocks > (int64_t)kLockstepGroups * kBarrierGroup) blocks = (int64_t)kLockstepGroups * kBarrierGroup;
+  hipLaunchKernelGGL(reset_ctl, dim3(1), dim3(256), 0, st, ctl, (uint32_t)kLockstepCtlWords);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  SearchArgs args = a;
+  uint32_t *c = ctl;
+  void *params[] = {(void *)&args, (void *)&c};
+  // a cooperative launch fails instead of starting a grid whose waves could
+  // not all be resident at once, so the barriers cannot wait for an absent wave
+  return hipLaunchCooperativeKernel(fn, dim3((unsigned)blocks), dim3(threads), params,
+                                    (unsigned)lds, st);
+}
+
+template <int DT>
+static hipError_t launch_lockstep_c(const SearchArgs &a, uint32_t *ctl, int tr, int wpb,
+                                    hipStream_t st) {
+  const int cpl = a.nav_stride / 128;
+#define FA_LS(C)                                                               \
+  return tr == TR_DIRECT ? launch_lockstep_t<DT, C, TR_DIRECT>(a, ctl, wpb, st) \
+                         : launch_lockstep_t<DT, C, TR_AGENT>(a, ctl, wpb, st)
+  switch (cpl) {
+    case 1: FA_LS(1);
+    case 2: FA_LS(2);
+    case 3: FA_LS(3);
+    case 4: FA_LS(4);
+    default: return hipErrorInvalidValue;
+  }
+#undef FA_LS
+}
+
+hipError_t launch_lockstep(const SearchArgs &a, uint32_t *ctl, int dtype, int transport,
+                           int waves_per_block, hipStream_t st) {
+  switch (dtype) {
+    case DT_U8: return launch_lockstep_c<DT_U8>(a, ctl, transport, waves_per_block, st);
+    case DT_I8: return launch_lockstep_c<DT_I8>(a, ctl, transport, waves_per_block, st);
+    case DT_F32: return launch_lockstep_c<DT_F32>(a, ctl, transport, waves_per_block, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+uint32_t search_lds_bytes(int Lcap, int nav_stride, int hash_bits, int kcap, int pq_floats) {
+  return lds_layout(Lcap, nav_stride, hash_bits, kcap, pq_floats).bytes;
+}
+
+// The batch and server kernels of each element type and navigation mode are
+// instantiated in units of their own (search_full_*.hip, search_pq_*.hip),
+// so that they compile in parallel.
+#define FA_NAV_LAUNCHERS(N, T)                                                                 \
+  hipError_t launch_search_##N##_##T(const SearchArgs &a, int transport, int wpb, bool pers,   \
+                                     hipStream_t st);                                          \
+  hipError_t launch_server_##N##_##T(const ServerArgs &a, int wpb, int64_t *res, hipStream_t st);
+FA_NAV_LAUNCHERS(full, u8)
+FA_NAV_LAUNCHERS(full, i8)
+FA_NAV_LAUNCHERS(full, f32)
+#undef FA_NAV_LAUNCHERS
+
+hipError_t launch_search(const SearchArgs &a, int dtype, int transport, int waves_per_block,
+                         bool persistent, hipStream_t st) {
+  if (a.pq_m > 0) return launch_search_pq(a, dtype, transport, waves_per_block, persistent, st);
+  switch (dtype) {
+    case DT_U8: return launch_search_full_u8(a, transport, waves_per_block, persistent, st);
+    case DT_I8: return launch_search_full_i8(a, transport, waves_per_block, persistent, st);
+    case DT_F32: return launch_search_full_f32(a, transport, waves_per_block, persistent, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_reset(uint32_t *work, hipStream_t st) {
+  hipLaunchKernelGGL(reset_work, dim3(1), dim3(1), 0, st, work);
+  return hipGetLastError();
+}
+
+#endif  // FA_SEARCH_TEMPLATES_ONLY
+
+// ------------------------------------------------------------------ server
+// Compiled in both units like the batch kernels: full-precision navigation
+// here, compressed navigation in the PQ unit.
+
 // Continuous-batching server.  Waves take ring indices as tickets from one
 // counter and serve each once the host has published it; a wave that leaves
 // while idle holds no ticket (see the claim loop).  The entry is read with
 // system-scope loads because ring memory is rewritten by host copies; results
 // go to host-mapped rows, then the slot's done word tells the host.
-template <int DT, int CPL, int DELAY, int TR>
+template <int DT, int CPL, int DELAY, int TR, int NAV>
 __global__ void __launch_bounds__(256) server_kernel(ServerArgs S) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int wave = threadIdx.x >> 6;
@@ -1388,7 +1471,7 @@ __global__ void __launch_bounds__(256) server_kernel(ServerArgs S) {
     // queries it serves (its request numbers continue in line_seq)
     io.line = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     io.status = S.res_status ? S.res_status + slot : nullptr;
-    run_query<DT, CPL, DELAY, TR>(S.base, lds, (int64_t)slot, io);
+    run_query<DT, CPL, DELAY, TR, NAV>(S.base, lds, (int64_t)slot, io);
     // The result rows were written with system-scope (write-through) stores:
     // once they have completed, the done word may follow.  This avoids a
     // release fence, which would write back the whole L2 for every query.
@@ -1401,80 +1484,14 @@ __global__ void __launch_bounds__(256) server_kernel(ServerArgs S) {
   }
 }
 
-template <int DT, int CPL, int TR>
-static hipError_t launch_lockstep_t(const SearchArgs &a, uint32_t *ctl, int wpb, hipStream_t st) {
-  const size_t lds = (size_t)a.lds_per_wave * wpb;
-  const int threads = 64 * wpb;
-  const void *fn = (const void *)lockstep_kernel<DT, CPL, TR>;
-  int per_cu = 0, dev = 0, cus = 0, coop = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
-  if (e != hipSuccess) return e;
-  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
-    return e;
-  if ((e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev)) != hipSuccess)
-    return e;
-  if (!coop || per_cu < 1) return hipErrorNotSupported;
-  int64_t blocks = (int64_t)per_cu * cus;
-  const int64_t need = (a.nq + wpb - 1) / wpb;
-  if (blocks > need) blocks = need;
-  if (blocks > (int64_t)kLockstepGroups * kBarrierGroup) blocks = (int64_t)kLockstepGroups * kBarrierGroup;
-  hipLaunchKernelGGL(reset_ctl, dim3(1), dim3(256), 0, st, ctl, (uint32_t)kLockstepCtlWords);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  SearchArgs args = a;
-  uint32_t *c = ctl;
-  void *params[] = {(void *)&args, (void *)&c};
-  // a cooperative launch fails instead of starting a grid whose waves could
-  // not all be resident at once, so the barriers cannot wait for an absent wave
-  return hipLaunchCooperativeKernel(fn, dim3((unsigned)blocks), dim3(threads), params,
-                                    (unsigned)lds, st);
-}
-
-template <int DT>
-static hipError_t launch_lockstep_c(const SearchArgs &a, uint32_t *ctl, int tr, int wpb,
-                                    hipStream_t st) {
-  const int cpl = a.nav_stride / 128;
-#define FA_LS(C)                                                               \
-  return tr == TR_DIRECT ? launch_lockstep_t<DT, C, TR_DIRECT>(a, ctl, wpb, st) \
-                         : launch_lockstep_t<DT, C, TR_AGENT>(a, ctl, wpb, st)
-  switch (cpl) {
-    case 1: FA_LS(1);
-    case 2: FA_LS(2);
-    case 3: FA_LS(3);
-    case 4: FA_LS(4);
-    default: return hipErrorInvalidValue;
-  }
-#undef FA_LS
-}
-
-hipError_t launch_lockstep(const SearchArgs &a, uint32_t *ctl, int dtype, int transport,
-                           int waves_per_block, hipStream_t st) {
-  switch (dtype) {
-    case DT_U8: return launch_lockstep_c<DT_U8>(a, ctl, transport, waves_per_block, st);
-    case DT_I8: return launch_lockstep_c<DT_I8>(a, ctl, transport, waves_per_block, st);
-    case DT_F32: return launch_lockstep_c<DT_F32>(a, ctl, transport, waves_per_block, st);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-uint32_t search_lds_bytes(int Lcap, int nav_stride, int hash_bits, int kcap, int pq_floats) {
-  return lds_layout(Lcap, nav_stride, hash_bits, kcap, pq_floats).bytes;
-}
-
-hipError_t launch_search(const SearchArgs &a, int dtype, int transport, int waves_per_block,
-                         bool persistent, hipStream_t st) {
-  if (a.pq_m > 0) return launch_search_pq(a, dtype, transport, waves_per_block, persistent, st);
-  return launch_nav<NAV_FULL>(a, dtype, transport, waves_per_block, persistent, st);
-}
-
-template <int DT, int CPL, int DELAY, int TR>
+template <int DT, int CPL, int DELAY, int TR, int NAV>
 static hipError_t launch_server_t(const ServerArgs &a, int wpb, int64_t *resident,
                                   hipStream_t st) {
   const size_t lds = (size_t)a.base.lds_per_wave * wpb;
   const int threads = 64 * wpb;
   int per_cu = 0, dev = 0, cus = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per_cu, (const void *)server_kernel<DT, CPL, DELAY, TR>, threads, lds);
+      &per_cu, (const void *)server_kernel<DT, CPL, DELAY, TR, NAV>, threads, lds);
   if (e != hipSuccess) return e;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
   if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
@@ -1482,51 +1499,49 @@ static hipError_t launch_server_t(const ServerArgs &a, int wpb, int64_t *residen
   const int64_t blocks = (int64_t)(per_cu > 0 ? per_cu : 1) * cus;
   if (resident) *resident = blocks * wpb;
   if (!st) return hipSuccess;  // size query only
-  hipLaunchKernelGGL((server_kernel<DT, CPL, DELAY, TR>), dim3((unsigned)blocks), dim3(threads),
+  hipLaunchKernelGGL((server_kernel<DT, CPL, DELAY, TR, NAV>), dim3((unsigned)blocks), dim3(threads),
                      lds, st, a);
   return hipGetLastError();
 }
 
-template <int DT, int CPL, int TR>
+template <int DT, int CPL, int TR, int NAV>
 static hipError_t launch_server_s(const ServerArgs &a, int wpb, int64_t *res, hipStream_t st) {
   const int delay = a.base.delay, beam = a.base.beam;
   if (delay < 0 || beam < 1 || (delay + 1) * beam > kMaxPipe) return hipErrorInvalidValue;
-  if (beam == 1 && delay == 0) return launch_server_t<DT, CPL, SCHED_STRICT, TR>(a, wpb, res, st);
+  if (beam == 1 && delay == 0) return launch_server_t<DT, CPL, SCHED_STRICT, TR, NAV>(a, wpb, res, st);
   if (beam == 1 && delay == 1)
-    return launch_server_t<DT, CPL, SCHED_RELAXED, TR>(a, wpb, res, st);
-  return launch_server_t<DT, CPL, SCHED_GENERIC, TR>(a, wpb, res, st);
+    return launch_server_t<DT, CPL, SCHED_RELAXED, TR, NAV>(a, wpb, res, st);
+  return launch_server_t<DT, CPL, SCHED_GENERIC, TR, NAV>(a, wpb, res, st);
 }
 
-template <int DT, int CPL>
+template <int DT, int CPL, int NAV>
 static hipError_t launch_server_d(const ServerArgs &a, int wpb, int64_t *res, hipStream_t st) {
-  return a.transport == TR_AGENT ? launch_server_s<DT, CPL, TR_AGENT>(a, wpb, res, st)
-                                 : launch_server_s<DT, CPL, TR_DIRECT>(a, wpb, res, st);
+  return a.transport == TR_AGENT ? launch_server_s<DT, CPL, TR_AGENT, NAV>(a, wpb, res, st)
+                                 : launch_server_s<DT, CPL, TR_DIRECT, NAV>(a, wpb, res, st);
 }
 
-template <int DT>
+template <int DT, int NAV>
 static hipError_t launch_server_c(const ServerArgs &a, int wpb, int64_t *res, hipStream_t st) {
   switch (a.base.nav_stride / 128) {
-    case 1: return launch_server_d<DT, 1>(a, wpb, res, st);
-    case 2: return launch_server_d<DT, 2>(a, wpb, res, st);
-    case 3: return launch_server_d<DT, 3>(a, wpb, res, st);
-    case 4: return launch_server_d<DT, 4>(a, wpb, res, st);
+    case 1: return launch_server_d<DT, 1, NAV>(a, wpb, res, st);
+    case 2: return launch_server_d<DT, 2, NAV>(a, wpb, res, st);
+    case 3: return launch_server_d<DT, 3, NAV>(a, wpb, res, st);
+    case 4: return launch_server_d<DT, 4, NAV>(a, wpb, res, st);
     default: return hipErrorInvalidValue;
   }
 }
+
+#ifndef FA_SEARCH_TEMPLATES_ONLY
 
 hipError_t launch_server(const ServerArgs &a, int dtype, int waves_per_block,
                          int64_t *resident_waves, hipStream_t st) {
+  if (a.base.pq_m > 0) return launch_server_pq(a, dtype, waves_per_block, resident_waves, st);
   switch (dtype) {
-    case DT_U8: return launch_server_c<DT_U8>(a, waves_per_block, resident_waves, st);
-    case DT_I8: return launch_server_c<DT_I8>(a, waves_per_block, resident_waves, st);
-    case DT_F32: return launch_server_c<DT_F32>(a, waves_per_block, resident_waves, st);
+    case DT_U8: return launch_server_full_u8(a, waves_per_block, resident_waves, st);
+    case DT_I8: return launch_server_full_i8(a, waves_per_block, resident_waves, st);
+    case DT_F32: return launch_server_full_f32(a, waves_per_block, resident_waves, st);
     default: return hipErrorInvalidValue;
   }
-}
-
-hipError_t launch_reset(uint32_t *work, hipStream_t st) {
-  hipLaunchKernelGGL(reset_work, dim3(1), dim3(1), 0, st, work);
-  return hipGetLastError();
 }
 
 #endif  // FA_SEARCH_TEMPLATES_ONLY

@@ -1,18 +1,48 @@
-// search_pq.hip -- batch search kernels with compressed (PQ) navigation, and
-// the PQ encoder that fills the code rows they read.
+// search_pq.hip -- batch search and server kernels with compressed (PQ)
+// navigation, and the PQ encoder that fills the code rows they read.
 //
 // The search templates are shared with the full-precision kernels (the
-// navigation mode is a template argument of the same kernel); this unit
-// instantiates them for NAV_PQ only, so the two sets compile in parallel.
+// navigation mode is a template argument of the same kernel); the NAV_PQ
+// instances live in one unit per element type (below), so that all of them
+// compile in parallel with the full-precision set.
 #define FA_SEARCH_TEMPLATES_ONLY
 #include "search_kernel.hip"
 
 namespace fa {
 
+// The PQ kernels of each element type are instantiated in a unit of their
+// own (search_pq_u8.hip, search_pq_i8.hip, search_pq_f32.hip), so that they
+// compile in parallel.
+#define FA_PQ_LAUNCHERS(T)                                                                     \
+  hipError_t launch_search_pq_##T(const SearchArgs &a, int transport, int wpb, bool pers,      \
+                                  hipStream_t st);                                             \
+  hipError_t launch_server_pq_##T(const ServerArgs &a, int wpb, int64_t *res, hipStream_t st);
+FA_PQ_LAUNCHERS(u8)
+FA_PQ_LAUNCHERS(i8)
+FA_PQ_LAUNCHERS(f32)
+#undef FA_PQ_LAUNCHERS
+
 hipError_t launch_search_pq(const SearchArgs &a, int dtype, int transport, int waves_per_block,
                             bool persistent, hipStream_t st) {
   if (a.pq_m < 1 || a.pq_m > kPqMaxM || !a.pq_codes || !a.pq_cb) return hipErrorInvalidValue;
-  return launch_nav<NAV_PQ>(a, dtype, transport, waves_per_block, persistent, st);
+  switch (dtype) {
+    case DT_U8: return launch_search_pq_u8(a, transport, waves_per_block, persistent, st);
+    case DT_I8: return launch_search_pq_i8(a, transport, waves_per_block, persistent, st);
+    case DT_F32: return launch_search_pq_f32(a, transport, waves_per_block, persistent, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_server_pq(const ServerArgs &a, int dtype, int waves_per_block,
+                            int64_t *resident_waves, hipStream_t st) {
+  const SearchArgs &b = a.base;
+  if (b.pq_m < 1 || b.pq_m > kPqMaxM || !b.pq_codes || !b.pq_cb) return hipErrorInvalidValue;
+  switch (dtype) {
+    case DT_U8: return launch_server_pq_u8(a, waves_per_block, resident_waves, st);
+    case DT_I8: return launch_server_pq_i8(a, waves_per_block, resident_waves, st);
+    case DT_F32: return launch_server_pq_f32(a, waves_per_block, resident_waves, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // One block per (128 rows, subspace m): the subspace's 256 centroids and the

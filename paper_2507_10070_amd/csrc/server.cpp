@@ -31,7 +31,8 @@
 
 // Defined in api.hip.
 int ann_internal_server_args(ann_index *ix, int32_t k_max, int32_t L_max, int32_t hash_bits,
-                             fa::SearchArgs *base, int32_t *dtype);
+                             int32_t navigation, int32_t pq_scoring, fa::SearchArgs *base,
+                             int32_t *dtype);
 int ann_internal_fail(int code, const char *msg);
 int ann_internal_server_transport(ann_index *ix, int32_t requested, int32_t *tr,
                                   fa::Agent **agent, int64_t *stage_stride);
@@ -331,7 +332,8 @@ int ann_server_open(ann_index *ix, size_t hbm_budget_bytes, const ann_server_opt
   if (opts) o = *opts;
   if (o.k_max == 0) o.k_max = 100;
   if (o.L_max == 0) o.L_max = 256;
-  if (o.waves_per_block == 0) o.waves_per_block = 4;
+  const bool auto_wpb = o.waves_per_block == 0;
+  if (auto_wpb) o.waves_per_block = 4;
   if (o.hash_bits == 0) o.hash_bits = 10;
   if (o.queue_cap == 0) o.queue_cap = 1 << 20;
   if (o.idle_polls == 0) o.idle_polls = 50000;
@@ -349,13 +351,22 @@ int ann_server_open(ann_index *ix, size_t hbm_budget_bytes, const ann_server_opt
   s->k_max = o.k_max;
   s->L_max = o.L_max;
   s->delay = o.delay;
-  s->wpb = o.waves_per_block;
   s->queue_cap = o.queue_cap;
-  int rc = ann_internal_server_args(ix, o.k_max, o.L_max, o.hash_bits, &s->args.base, &s->dtype);
+  int rc = ann_internal_server_args(ix, o.k_max, o.L_max, o.hash_bits, o.navigation,
+                                    o.pq_scoring, &s->args.base, &s->dtype);
   if (rc) {
     server_free(s);
     return rc;
   }
+  // the default queries per workgroup shrinks to what the LDS holds
+  while (auto_wpb && o.waves_per_block > 1 &&
+         (int64_t)s->args.base.lds_per_wave * o.waves_per_block > 160 * 1024)
+    o.waves_per_block /= 2;
+  if ((int64_t)s->args.base.lds_per_wave * o.waves_per_block > 160 * 1024) {
+    server_free(s);
+    return ann_internal_fail(ANN_EINVAL, "LDS need per query x waves_per_block exceeds 160 KiB");
+  }
+  s->wpb = o.waves_per_block;
   s->args.base.delay = o.delay;
   s->args.base.beam = o.beam_width;
   s->args.base.pslots = std::max(2, (o.delay + 1) * o.beam_width);

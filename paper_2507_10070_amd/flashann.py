@@ -65,7 +65,8 @@ class ServerOptions(ctypes.Structure):
                 ("waves_per_block", ctypes.c_int32), ("hash_bits", ctypes.c_int32),
                 ("queue_cap", ctypes.c_int32), ("idle_polls", ctypes.c_int32),
                 ("beam_width", ctypes.c_int32), ("transport", ctypes.c_int32),
-                ("spin_limit", ctypes.c_uint32)]
+                ("spin_limit", ctypes.c_uint32),
+                ("navigation", ctypes.c_int32), ("pq_scoring", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -398,13 +399,15 @@ class Server:
     def __init__(self, index: Index, hbm_budget_bytes: int, k_max: int = 100, L_max: int = 256,
                  delay: int = 1, waves_per_block: int = 0, hash_bits: int = 0,
                  queue_cap: int = 0, idle_polls: int = 0, beam_width: int = 1,
-                 transport: int = TRANSPORT_AUTO, spin_limit: int = 0):
+                 transport: int = TRANSPORT_AUTO, spin_limit: int = 0,
+                 navigation: int = NAV_FULL, pq_scoring: int = PQ_AUTO):
         self.index = index
         self.dtype = index.dtype
         self.d = index.d
         self.k_max = k_max
         opts = ServerOptions(k_max, L_max, delay, waves_per_block, hash_bits, queue_cap,
-                             idle_polls, beam_width, transport, spin_limit)
+                             idle_polls, beam_width, transport, spin_limit, navigation,
+                             pq_scoring)
         h = ctypes.c_void_p()
         _check(load_library().ann_server_open(index.handle, int(hbm_budget_bytes),
                                               ctypes.byref(opts), ctypes.byref(h)))

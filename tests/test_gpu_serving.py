@@ -212,3 +212,47 @@ def test_server_agent_read_failure_is_per_query(cfg1, tmp_path):
         else:
             assert got[i]["status"] == 0
             np.testing.assert_array_equal(got[i]["ids"], ref["ids"][i])
+
+
+@pytest.mark.parametrize("tier,scoring,delay,beam", [("host", fa.PQ_CACHE, 1, 1),
+                                                     ("host", fa.PQ_TABLE, 0, 1),
+                                                     ("file", fa.PQ_AUTO, 2, 2)])
+def test_server_pq_navigation_matches_oracle(cfg1, tmp_path, tier, scoring, delay, beam):
+    """Compressed navigation in the server: every result equals the oracle's
+    PQ search with re-rank, across the k / L mix, for both scorings and the
+    file tier (served through the server's own agents)."""
+    base, q, adj, entry = cfg1
+    cb = synth.train_codebooks(base, 16, iters=4, sample=5000, seed=61)
+    ks, Ls = plan(len(q), 21)
+    ix = (fa.Index(base, adj, entry, 256, fa.TIER_HOST) if tier == "host"
+          else _file_index(tmp_path, base, adj, entry))
+    with ix:
+        ix.set_pq(cb)
+        with fa.Server(ix, hbm_budget_bytes=64 << 20, delay=delay, beam_width=beam,
+                       navigation=fa.NAV_PQ, pq_scoring=scoring) as srv:
+            for i in range(len(q)):
+                srv.submit(q[i], int(ks[i]), int(Ls[i]), i)
+            got = collect(srv, len(q))
+    for i in range(len(q)):
+        assert got[i]["status"] == 0
+        ref = oracle.search(base, adj, entry, q[i:i + 1], int(ks[i]), int(Ls[i]), delay=delay,
+                            beam=beam, codebooks=cb)
+        np.testing.assert_array_equal(got[i]["ids"], ref["ids"][0])
+        np.testing.assert_array_equal(got[i]["dists"].astype(np.float64), ref["dists"][0])
+        assert got[i]["steps"] == ref["steps"][0]
+
+
+def test_server_navigation_needs_its_data(cfg1):
+    base, q, adj, entry = cfg1
+    with fa.Index(base, adj, entry, 256, fa.TIER_HOST) as ix:
+        with pytest.raises(fa.AnnError) as e:  # no codes yet
+            fa.Server(ix, hbm_budget_bytes=64 << 20, navigation=fa.NAV_PQ)
+        assert e.value.code == -22
+        ix.set_pq(synth.train_codebooks(base, 8, iters=2, sample=2000, seed=62), drop_nav=True)
+        with pytest.raises(fa.AnnError) as e:  # the full-precision copy is gone
+            fa.Server(ix, hbm_budget_bytes=64 << 20)
+        assert e.value.code == -22
+        with fa.Server(ix, hbm_budget_bytes=64 << 20, navigation=fa.NAV_PQ) as srv:
+            srv.submit(q[0], 10, 64, 0)
+            r = collect(srv, 1)[0]
+        assert r["status"] == 0 and (r["ids"] >= 0).all()
