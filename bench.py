@@ -196,11 +196,12 @@ def serving_leg(fa, ix, queries, kth, budget, L_op):
     return out
 
 
-def serving_file(fa, ix, queries, kth, L_op, m=2000):
-    """Continuous batching with the records in a file: the server's own host
-    agents read them (O_DIRECT), one request line per resident wave.  The
-    operating mix of the serving leg; saturation from an m-query burst, then
-    Poisson arrivals at half of it."""
+def serving_burst(fa, ix, queries, kth, L_op, m=2000, where="records in a file", **server_kw):
+    """Continuous batching measured briefly: the operating mix of the serving
+    leg (L >= L_op), saturation from an m-query burst, then Poisson arrivals
+    at half of it.  With records in a file the server's own host agents read
+    them (O_DIRECT), one request line per resident wave; `server_kw` passes
+    server options (e.g. compressed navigation)."""
     import numpy as np
 
     rng = np.random.default_rng(23)
@@ -214,8 +215,8 @@ def serving_file(fa, ix, queries, kth, L_op, m=2000):
         d10 = res["dists"][:, :10].astype(np.float64)
         return float((np.minimum((d10 <= kth[qi][:, None]).sum(1), 10) / 10.0).mean())
 
-    out = {"workload": "records in a file, k in {10, 100}, L in %s with L >= k" % Lset}
-    with fa.Server(ix, hbm_budget_bytes=256 << 20) as srv:
+    out = {"workload": "%s, k in {10, 100}, L in %s with L >= k" % (where, Lset)}
+    with fa.Server(ix, hbm_budget_bytes=256 << 20, **server_kw) as srv:
         idx = np.arange(m) % nq
         t0 = fa.clock_us()
         srv.submit_batch(queries[idx], ks[:m], Ls[:m], idx.astype(np.uint64))
@@ -234,11 +235,12 @@ def serving_file(fa, ix, queries, kth, L_op, m=2000):
                             "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
                             "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
                             "recall@10": round(recall(res), 4)}
-    log("file-tier serving: %s" % out)
+    log("serving (%s): %s" % (where, out))
     return out
 
 
-def pq_leg(fa, torch, dev, base, adj, entry, cfg, ix, qd, kth, L_full, stream, subspaces):
+def pq_leg(fa, torch, dev, base, adj, entry, cfg, ix, qd, kth, L_full, stream, subspaces,
+           queries_host=None):
     """Compressed navigation (paper section 2.2): PQ codes in HBM order the
     candidate list, expanded nodes are re-ranked exactly from their records.
     Per number of subspaces M: codebook training and GPU encoding time, the
@@ -344,6 +346,11 @@ def pq_leg(fa, torch, dev, base, adj, entry, cfg, ix, qd, kth, L_full, stream, s
                 "records_in_hbm_GBps": round((int(s[1]) * M + int(s[0]) * info["rec_bytes"]) /
                                              (ms_h / 1e3) / 1e9, 1)}
             log("PQ M=%d: %s" % (M, {kk: v for kk, v in res["M%d" % M].items() if kk != "sweep"}))
+            if reached and queries_host is not None:
+                res["M%d" % M]["serving"] = serving_burst(
+                    fa, ix, queries_host, kth, L_op, m=50000,
+                    where="PQ navigation (M = %d), records in host DRAM" % M,
+                    navigation=fa.NAV_PQ)
     finally:
         hix.close()
     return res
@@ -788,7 +795,8 @@ def main():
         log("latent-16 workload ready")
         with fa.Index(lbase, ladj, lentry, lcfg.slot, tier) as lix:
             pq["latent16"] = pq_leg(fa, torch, dev, lbase, ladj, lentry, lcfg, lix,
-                                    torch.from_numpy(lq).to(dev), lkth, None, stream, (16, 32))
+                                    torch.from_numpy(lq).to(dev), lkth, None, stream, (16, 32),
+                                    queries_host=lq)
         del lbase, ladj
 
     # ---- the paper's query-grained I/O stack on the same workload: agent
@@ -857,7 +865,7 @@ def main():
             transports["file"] = {"queries": mq, "L": op[1], "direct_io": fix.info()["direct_io"],
                                   "write_s": round(t_save, 1), **compare(fix, qsub, 1, 2)}
             if not args.no_serving:
-                transports["file"]["serving"] = serving_file(fa, fix, queries, kth, op[1])
+                transports["file"]["serving"] = serving_burst(fa, fix, queries, kth, op[1])
             fix.close()
             log("file tier: %s" % transports["file"])
         finally:
