@@ -64,3 +64,13 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_kernel_hash_ignores_comments_only():
+    """The stored memory-counter figures stay valid across comment edits of the
+    kernel source, and not across code edits."""
+    import bench
+
+    src = b"int a; // one\n\n// two\nint b;  \n"
+    assert bench._code_only(src) == bench._code_only(b"int a;\nint b; // three\n")
+    assert bench._code_only(src) != bench._code_only(b"int a;\nint c;\n")
