@@ -245,8 +245,10 @@ int ann_agent_stats(const ann_index *ix, uint64_t *requests, uint64_t *bytes, ui
  *              a later ann_index_set_pq need the copy)
  * Code of a vector, per subspace: the centroid of smallest fp32 squared
  * distance, accumulated with fused multiply-adds over the subspace's
- * dimensions in order; the lowest index among equals.  Synchronous.
- * Errors: ANN_EINVAL (sizes, or no navigation copy to encode), ANN_ENOMEM.
+ * dimensions in order; the lowest index among equals.  Synchronous: waits for
+ * all device work (searches still reading the old codes) before replacing.
+ * Errors: ANN_EINVAL (sizes, or no navigation copy to encode), ANN_EBUSY (a
+ * server is open on the index), ANN_ENOMEM.
  */
 int ann_index_set_pq(ann_index *ix, const float *codebooks, int32_t m, int32_t flags);
 /* ann_index_pq_codes -- copy the PQ codes to `host_codes` (caller-owned,

@@ -8,6 +8,7 @@
 #include <unistd.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cerrno>
 #include <cstdarg>
 #include <cstdio>
@@ -59,6 +60,7 @@ struct ann_index {
   uint8_t *pq_codes = nullptr;      // device, n x kPqStride
   float *pq_cb = nullptr;           // device, pq_m x 256 x (d / pq_m)
   int32_t pq_m = 0;
+  std::atomic<int> servers{0};      // servers open on this index
 };
 
 struct ann_graph {
@@ -507,6 +509,8 @@ int ann_index_set_pq(ann_index *ix, const float *codebooks, int32_t m, int32_t f
                 fa::kPqMaxM, ix->d);
   if (flags & ~ANN_PQ_DROP_NAV) return fail(ANN_EINVAL, "flags=%d", flags);
   if (!ix->nav) return fail(ANN_EINVAL, "the navigation copy was released; nothing to encode");
+  if (ix->servers.load() > 0)
+    return fail(ANN_EBUSY, "a server is open on this index; close it first");
   const size_t cb_bytes = sizeof(float) * (size_t)m * fa::kPqKsub * (size_t)(ix->d / m);
   const size_t code_bytes = (size_t)ix->n * fa::kPqStride;
   uint8_t *codes = nullptr;
@@ -517,6 +521,7 @@ int ann_index_set_pq(ann_index *ix, const float *codebooks, int32_t m, int32_t f
   if (e == hipSuccess)
     e = fa::launch_pq_encode(ix->nav, ix->n, ix->nav_stride, ix->dtype, ix->d, cb, m, codes,
                              nullptr);
+  // also waits for searches still reading the codes or the copy replaced below
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     if (codes) (void)hipFree(codes);
@@ -943,3 +948,7 @@ int ann_index_free(ann_index *ix) {
 }
 
 }  // extern "C"
+
+void ann_internal_server_hold(ann_index *ix, int delta) {
+  if (ix) ix->servers.fetch_add(delta);
+}

@@ -34,6 +34,9 @@ int ann_internal_server_args(ann_index *ix, int32_t k_max, int32_t L_max, int32_
                              int32_t navigation, int32_t pq_scoring, fa::SearchArgs *base,
                              int32_t *dtype);
 int ann_internal_fail(int code, const char *msg);
+// Counts servers open on an index (the index refuses to replace or release
+// what a running server kernel reads).
+void ann_internal_server_hold(ann_index *ix, int delta);
 int ann_internal_server_transport(ann_index *ix, int32_t requested, int32_t *tr,
                                   fa::Agent **agent, int64_t *stage_stride);
 
@@ -74,6 +77,7 @@ struct Done {
 
 struct ann_server {
   ann_index *ix = nullptr;
+  bool held = false;  // counted in the index's open servers
   fa::ServerArgs args{};
   int32_t dtype = 0, delay = 1, wpb = 4, k_max = 100, L_max = 256;
   int32_t qbytes = 0, nav_stride = 0;
@@ -290,6 +294,8 @@ namespace {
 void server_free(ann_server *s) {
   if (!s) return;
   s->agent.reset();  // joins the agents before their arrays go
+  if (s->held) ann_internal_server_hold(s->ix, -1);
+  s->held = false;
   if (s->h_req) (void)hipHostFree(s->h_req);
   if (s->h_cpl) (void)hipHostFree(s->h_cpl);
   if (s->h_tstage) (void)hipHostFree(s->h_tstage);
@@ -477,6 +483,8 @@ int ann_server_open(ann_index *ix, size_t hbm_budget_bytes, const ann_server_opt
   }
   s->admit_thr = std::thread([s] { s->admit_loop(); });
   s->reap_thr = std::thread([s] { s->reap_loop(); });
+  ann_internal_server_hold(ix, +1);
+  s->held = true;
   *out = s;
   return ANN_OK;
 }

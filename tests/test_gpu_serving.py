@@ -248,7 +248,14 @@ def test_server_navigation_needs_its_data(cfg1):
         with pytest.raises(fa.AnnError) as e:  # no codes yet
             fa.Server(ix, hbm_budget_bytes=64 << 20, navigation=fa.NAV_PQ)
         assert e.value.code == -22
-        ix.set_pq(synth.train_codebooks(base, 8, iters=2, sample=2000, seed=62), drop_nav=True)
+        cb8 = synth.train_codebooks(base, 8, iters=2, sample=2000, seed=62)
+        with fa.Server(ix, hbm_budget_bytes=64 << 20) as srv:
+            with pytest.raises(fa.AnnError) as e:  # a running server reads the index
+                ix.set_pq(cb8)
+            assert e.value.code == -16
+            srv.submit(q[0], 10, 64, 0)
+            assert (collect(srv, 1)[0]["ids"] >= 0).all()
+        ix.set_pq(cb8, drop_nav=True)  # allowed again once the server closed
         with pytest.raises(fa.AnnError) as e:  # the full-precision copy is gone
             fa.Server(ix, hbm_budget_bytes=64 << 20)
         assert e.value.code == -22
