@@ -405,14 +405,12 @@ struct Searcher {
     else return c1.w;
   }
 
-  // Subspaces [GI*G, GI*G + G) of pq_sum with centroids from the codebook,
-  // d/M = DS in {4, 8}, G = 32 / DS: the group's centroid loads (8 x 16 B
-  // per lane) are issued before its arithmetic; then s += each sub-distance
-  // in subspace order.  Every index is a compile-time constant.
+  // Centroid loads of subspaces [GI*G, GI*G + G), d/M = DS in {4, 8},
+  // G = 32 / DS (8 x 16 B per lane); every index a compile-time constant.
   template <int DS, int GI>
-  __device__ __forceinline__ float pq_group(const uint4 c0, const uint4 c1, float s) const {
+  __device__ __forceinline__ void pq_load(const uint4 c0, const uint4 c1,
+                                          float4 (&v)[32 / DS][DS / 4]) const {
     constexpr int G = 32 / DS;
-    float4 v[G][DS / 4];
 #pragma unroll
     for (int u = 0; u < G; u++) {
       const int m = GI * G + u;
@@ -425,6 +423,12 @@ struct Searcher {
 #pragma unroll
       for (int h = 0; h < DS / 4; h++) v[u][h] = cc[h];
     }
+  }
+
+  // s += the sub-distances of subspaces [GI*G, GI*G + G) in subspace order.
+  template <int DS, int GI>
+  __device__ __forceinline__ float pq_add(const float4 (&v)[32 / DS][DS / 4], float s) const {
+    constexpr int G = 32 / DS;
 #pragma unroll
     for (int u = 0; u < G; u++) {
       if (GI * G + u < A.pq_m) {
@@ -444,23 +448,28 @@ struct Searcher {
     return s;
   }
 
-  // Groups GI, GI+1, ... of pq_sum_direct while they hold subspaces
-  // (at most kPqMaxM / G groups).
+  // Group GI is loaded (cur): issue the loads of group GI+1, then add group
+  // GI, so that one group's loads are in flight during the other's FMAs.
   template <int DS, int GI>
-  __device__ __forceinline__ float pq_groups_from(const uint4 c0, const uint4 c1, float s) const {
+  __device__ __forceinline__ float pq_pipe(const uint4 c0, const uint4 c1, float s,
+                                           const float4 (&cur)[32 / DS][DS / 4]) const {
     constexpr int G = 32 / DS;
-    if constexpr (GI * G < kPqMaxM) {
-      if (GI * G < A.pq_m) {
-        s = pq_group<DS, GI>(c0, c1, s);
-        s = pq_groups_from<DS, GI + 1>(c0, c1, s);
+    if constexpr ((GI + 1) * G < kPqMaxM) {
+      if ((GI + 1) * G < A.pq_m) {
+        float4 nxt[G][DS / 4];
+        pq_load<DS, GI + 1>(c0, c1, nxt);
+        s = pq_add<DS, GI>(cur, s);
+        return pq_pipe<DS, GI + 1>(c0, c1, s, nxt);
       }
     }
-    return s;
+    return pq_add<DS, GI>(cur, s);
   }
 
   template <int DS>
   __device__ __forceinline__ float pq_sum_direct(const uint4 c0, const uint4 c1) const {
-    return pq_groups_from<DS, 0>(c0, c1, 0.0f);
+    float4 v[32 / DS][DS / 4];
+    pq_load<DS, 0>(c0, c1, v);
+    return pq_pipe<DS, 0>(c0, c1, 0.0f, v);
   }
 
   __device__ __forceinline__ float pq_sum(const uint4 c0, const uint4 c1) const {
