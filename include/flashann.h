@@ -247,6 +247,8 @@ int ann_agent_stats(const ann_index *ix, uint64_t *requests, uint64_t *bytes, ui
  * distance, accumulated with fused multiply-adds over the subspace's
  * dimensions in order; the lowest index among equals.  Synchronous: waits for
  * all device work (searches still reading the old codes) before replacing.
+ * Graphs captured by ann_search_graph before this call hold the old codes
+ * (or the released copy) and must not be replayed after it.
  * Errors: ANN_EINVAL (sizes, or no navigation copy to encode), ANN_EBUSY (a
  * server is open on the index), ANN_ENOMEM.
  */
