@@ -41,6 +41,8 @@ MUTANTS = {
     "pq_entry_keyed_exactly": ("cand[0].dist = orc_nav_dist(J, w, q, J->entry);",
                                "cand[0].dist = orc_dist(J->base, J->entry, J->d, J->dtype, q);"),
     "pq_answer_not_reranked": ("out = res;\n    nout = nres;", "out = cand;\n    nout = nc;"),
+    "pq_encode_slices_leave_a_gap": ("orc_enc_job j = {base, n * t / threads, n * (t + 1) / threads,",
+                                     "orc_enc_job j = {base, n * t / threads + (t > 0), n * (t + 1) / threads,"),
     "selects_second_unexpanded": ("if (cand[i].expanded) continue;",
                                   "if (cand[i].expanded || (nsel == 0 && i == 0 && nc > 1 && !cand[1].expanded)) continue;"),
 }
