@@ -404,6 +404,31 @@ def pq_kernel_run(fa, torch, dev, steps):
           flush=True)
 
 
+def pq_scale_run(fa, torch, dev, n):
+    """Compressed against full-precision navigation at a larger size: the
+    workload of intrinsic dimension 16 with n vectors, records in pinned host
+    DRAM, PQ M = 32 (the pq_navigation leg on that index).  Prints one JSON
+    line."""
+    import synth
+
+    cfg = synth.WORKLOADS["1m-u8-128-latent16"]
+    log("generating %d x %d u8 vectors of intrinsic dimension %d" % (n, cfg.d, cfg.latent))
+    base, q = synth.make_dataset(cfg, n=n)
+    os.environ["FLASHANN_BUILD_PROGRESS"] = "1"
+    t = time.time()
+    adj, entry = synth.build_graph(base, cfg.R, 3000 + cfg.seed_offset,
+                                   threads=min(16, os.cpu_count() or 1))
+    log("graph R=%d built in %.1fs" % (cfg.R, time.time() - t))
+    kth = ground_truth(base, q, cfg.k, torch, dev)
+    log("ground truth done")
+    stream = torch.cuda.current_stream(dev)
+    with fa.Index(base, adj, entry, cfg.slot, fa.TIER_HOST) as ix:
+        res = pq_leg(fa, torch, dev, base, adj, entry, cfg, ix, torch.from_numpy(q).to(dev), kth,
+                     None, stream, (32,), queries_host=q)
+    res["n"] = n
+    print(json.dumps({"pq_scale": res}, default=float), flush=True)
+
+
 def batched_file_leg(fa, torch, dev, n, nq_total):
     """Batched form at scale: n int8 vectors of d = 100 (4,096-component
     mixture), degree-48 graph, 512 B records in a file read with O_DIRECT by
@@ -521,6 +546,9 @@ def main():
                     help="skip the compressed (PQ) navigation leg")
     ap.add_argument("--pq-kernel-only", action="store_true",
                     help="run only one compressed-navigation configuration (for profiling)")
+    ap.add_argument("--pq-n", type=int, default=0,
+                    help="run only the compressed-navigation leg on an n-vector index of "
+                         "intrinsic dimension 16 (e.g. 10000000)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device-to-device copy (scale reference "
                          "for memory counters)")
@@ -542,6 +570,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.pq_kernel_only:
         pq_kernel_run(fa, torch, dev, args.steps)
+        return
+    if args.pq_n:
+        pq_scale_run(fa, torch, dev, args.pq_n)
         return
     cfg = synth.WORKLOADS["1m-u8-128"]
     n = args.n or cfg.n
