@@ -425,6 +425,7 @@ def pq_scale_run(fa, torch, dev, n):
     with fa.Index(base, adj, entry, cfg.slot, fa.TIER_HOST) as ix:
         res = pq_leg(fa, torch, dev, base, adj, entry, cfg, ix, torch.from_numpy(q).to(dev), kth,
                      None, stream, (32,), queries_host=q)
+    res["workload"] = "%d x u8/128 of intrinsic dimension 16, records in pinned host DRAM" % n
     res["n"] = n
     print(json.dumps({"pq_scale": res}, default=float), flush=True)
 
