@@ -94,10 +94,14 @@ def _code_only(src: bytes) -> bytes:
 
 
 def kernel_source_hash():
-    """Hash of the code the search kernel is compiled from: the kernel header
-    and search_kernel.hip up to the end of the search kernel itself (the
-    lockstep and server kernels and the host launchers follow it and do not
-    change the profiled code), comments and blank lines left out."""
+    """Hash of everything the profiled search kernel is compiled from: the
+    kernel header, search_kernel.hip up to the end of the search kernel
+    itself (the lockstep and server kernels and the host launchers follow it
+    and do not change the profiled code), the units that instantiate it for
+    each element type, and the compiler flags; comments and blank lines are
+    left out of the sources."""
+    from paper_2507_10070_amd import build as hip_build
+
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2507_10070_amd", "csrc")
     with open(os.path.join(csrc, "search_kernel.h"), "rb") as fh:
@@ -106,6 +110,11 @@ def kernel_source_hash():
         src = fh.read()
     end = src.find(b"__global__ void reset_work(")
     h.update(_code_only(src if end < 0 else src[:end]))
+    for unit in sorted(u for u in hip_build.SOURCES if os.path.basename(u).startswith("search_")
+                       and u != "search_kernel.hip"):
+        with open(os.path.join(csrc, unit), "rb") as fh:
+            h.update(_code_only(fh.read()))
+    h.update(" ".join(hip_build.FLAGS).encode())
     return h.hexdigest()[:16]
 
 

@@ -338,6 +338,9 @@ typedef struct {
   int32_t navigation;  /* ann_navigation (0 = full precision); ANN_NAV_PQ as
                           in ann_search_opts (needs ann_index_set_pq) */
   int32_t pq_scoring;  /* ann_pq_scoring (0 = auto) */
+  uint64_t first_ticket; /* first admission ticket (0 by default).  Tickets
+                            are 64-bit on the host and the device; a start
+                            near 2^32 checks that none is cut to 32 bits */
 } ann_server_opts;
 typedef struct {
   uint64_t tag;          /* the caller's tag */
@@ -381,7 +384,10 @@ int ann_server_close(ann_server *s);
 /* Monotonic host clock (microseconds) of ann_result's time stamps. */
 double ann_clock_us(void);
 
-/* ann_index_free -- release everything the index holds (NULL is a no-op). */
+/* ann_index_free -- release everything the index holds (NULL is a no-op).
+ * ANN_EBUSY, with nothing released, while a server opened on the index is
+ * still open: close every server first (its kernel and agents read the
+ * index's memory). */
 int ann_index_free(ann_index *ix);
 
 /* Thread-local message describing the last failure of this thread. */

@@ -943,6 +943,9 @@ int ann_device_clock_khz(int32_t *khz) {
 }
 
 int ann_index_free(ann_index *ix) {
+  // an open server's kernel and agents read the index's memory
+  if (ix && ix->servers.load() > 0)
+    return fail(ANN_EBUSY, "a server is open on this index: close it first");
   release(ix);
   return ANN_OK;
 }

@@ -88,8 +88,8 @@ struct ServerArgs {
   const uint8_t *ring;      // device, ring_cap entries
   int64_t entry_bytes;
   uint32_t ring_cap, nslots;
-  uint32_t *next;           // device: next ring index to claim
-  const uint32_t *published;  // device: entries published (written by the host's stream)
+  uint64_t *next;           // device: next ticket to claim (entry = ticket % ring_cap)
+  const uint64_t *published;  // device: tickets published (written by the host's stream)
   const uint32_t *stop;     // device: non-zero = leave once idle
   int32_t *res_ids;         // host-mapped, nslots x k_max
   uint32_t *res_dists;      // host-mapped, nslots x k_max

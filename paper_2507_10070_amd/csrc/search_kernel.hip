@@ -1417,7 +1417,11 @@ __global__ void __launch_bounds__(256) server_kernel(ServerArgs S) {
   const int lane = lane_id();
   uint8_t *lds = smem + (size_t)wave * S.base.lds_per_wave;
   for (;;) {
-    uint32_t got = 0xFFFFFFFFu;
+    // Tickets are 64-bit on the device as on the host, so they never wrap in
+    // practice and the ring entry is the ticket modulo the ring capacity on
+    // both sides.
+    uint64_t got = 0;
+    int have = 0;
     if (lane == 0) {
       // Tickets come from one fetch-add on `next` (one L2 atomic per claim,
       // however many waves look for work at once).  A wave whose ticket is
@@ -1431,22 +1435,23 @@ __global__ void __launch_bounds__(256) server_kernel(ServerArgs S) {
         // relaxed system-scope polls bypass the caches without the L2
         // invalidation an acquire would cost every idle wave on every poll;
         // the entry itself is read with system-scope loads below
-        uint32_t pub = __hip_atomic_load(S.published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        const uint32_t c = __hip_atomic_load(S.next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t pub = __hip_atomic_load(S.published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        const uint64_t c = __hip_atomic_load(S.next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (c < pub) {
-          const uint32_t t = atomicAdd(S.next, 1u);
+          const uint64_t t = atomicAdd((unsigned long long *)S.next, 1ull);
           uint32_t hold_nap = 1;
           for (;;) {
             if (t < pub) {
               got = t;
+              have = 1;
               break;
             }
-            if (atomicCAS(S.next, t + 1u, t) == t + 1u) break;  // handed back
+            if (atomicCAS((unsigned long long *)S.next, t + 1ull, t) == t + 1ull) break;  // handed back
             for (uint32_t i = 0; i < hold_nap; i++) __builtin_amdgcn_s_sleep(2);
             hold_nap = hold_nap < 8 ? hold_nap * 2 : 8;
             pub = __hip_atomic_load(S.published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
           }
-          if (got != 0xFFFFFFFFu) break;
+          if (have) break;
           continue;
         }
         if (__hip_atomic_load(S.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
@@ -1455,8 +1460,10 @@ __global__ void __launch_bounds__(256) server_kernel(ServerArgs S) {
         nap = nap < 8 ? nap * 2 : 8;
       }
     }
-    got = (uint32_t)__builtin_amdgcn_readfirstlane((int)got);
-    if (got == 0xFFFFFFFFu) return;
+    have = __builtin_amdgcn_readfirstlane(have);
+    if (!have) return;
+    got = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(got >> 32)) << 32) |
+          (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)got);
     const uint8_t *e = S.ring + (int64_t)(got % S.ring_cap) * S.entry_bytes;
     const uint32_t *ctrl = (const uint32_t *)e;
     const uint32_t slot =
@@ -1488,7 +1495,7 @@ __global__ void __launch_bounds__(256) server_kernel(ServerArgs S) {
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_sched_barrier(0);
     if (lane == 0)
-      __hip_atomic_store(S.done + 16 * (int64_t)slot, got + 1u, __ATOMIC_RELAXED,
+      __hip_atomic_store(S.done + 16 * (int64_t)slot, (uint32_t)(got + 1u), __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }

@@ -84,7 +84,7 @@ struct ann_server {
   int64_t queue_cap = 0, resident = 0;
   // device
   uint8_t *d_ring = nullptr;
-  uint32_t *d_ctl = nullptr;  // [0] next, [16] published, [32] stop (separate lines)
+  uint32_t *d_ctl = nullptr;  // 64 B lines: [0] next (u64), [16] published (u64), [32] stop
   // host (pinned, mapped)
   uint8_t *h_stage = nullptr;
   int32_t *h_ids = nullptr;
@@ -171,6 +171,9 @@ struct ann_server {
           const uint32_t slot = batch[i].first;
           Inflight &f = inflight[slot];
           f.seq = published + i;
+          // the slot's 32-bit done word must not already hold this query's
+          // mark, seq + 1 modulo 2^32, from an earlier use or its zero start
+          __atomic_store_n(&h_done[16 * (int64_t)slot], (uint32_t)f.seq, __ATOMIC_RELAXED);
           f.tag = batch[i].second.tag;
           f.k = batch[i].second.k;
           f.submit_us = batch[i].second.submit_us;
@@ -204,7 +207,7 @@ struct ann_server {
                              st_copy);
           s += run;
         }
-        if (e == hipSuccess) e = hipStreamWriteValue32(st_copy, d_ctl + 16, (uint32_t)last, 0);
+        if (e == hipSuccess) e = hipStreamWriteValue64(st_copy, d_ctl + 16, last, 0);
         if (e == hipSuccess) e = hipStreamSynchronize(st_copy);
         if (e != hipSuccess) {
           error_msg = std::string("admission copy: ") + hipGetErrorString(e);
@@ -215,7 +218,7 @@ struct ann_server {
         admitted.fetch_add(batch.size());
       }
       // the kernel leaves after a long idle spell; start it again when work waits
-      if (published > completed.load() + 0 && (!kernel_live || hipEventQuery(ev_kernel) == hipSuccess)) {
+      if (admitted.load() > completed.load() && (!kernel_live || hipEventQuery(ev_kernel) == hipSuccess)) {
         if (kernel_live) relaunches.fetch_add(1);
         if (launch_kernel() != ANN_OK) return;
       }
@@ -358,6 +361,7 @@ int ann_server_open(ann_index *ix, size_t hbm_budget_bytes, const ann_server_opt
   s->L_max = o.L_max;
   s->delay = o.delay;
   s->queue_cap = o.queue_cap;
+  s->published = o.first_ticket;  // tickets, next and published start here
   int rc = ann_internal_server_args(ix, o.k_max, o.L_max, o.hash_bits, o.navigation,
                                     o.pq_scoring, &s->args.base, &s->dtype);
   if (rc) {
@@ -423,6 +427,10 @@ int ann_server_open(ann_index *ix, size_t hbm_budget_bytes, const ann_server_opt
       (e = hipHostMalloc((void **)&s->h_done, slots * 64, fl)) != hipSuccess ||
       (e = hipHostMalloc((void **)&s->h_status, slots * 4, fl)) != hipSuccess ||
       (e = hipMemset(s->d_ctl, 0, 64 * sizeof(uint32_t))) != hipSuccess ||
+      (e = hipMemcpy(s->d_ctl, &o.first_ticket, sizeof(uint64_t), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(s->d_ctl + 16, &o.first_ticket, sizeof(uint64_t), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
       (e = hipStreamCreateWithFlags(&s->st_kernel, hipStreamNonBlocking)) != hipSuccess ||
       (e = hipStreamCreateWithFlags(&s->st_copy, hipStreamNonBlocking)) != hipSuccess ||
       (e = hipEventCreateWithFlags(&s->ev_kernel, hipEventDisableTiming)) != hipSuccess) {
@@ -459,8 +467,8 @@ int ann_server_open(ann_index *ix, size_t hbm_budget_bytes, const ann_server_opt
     s->agent->arm(s->h_req, s->h_cpl, s->h_tstage, G, ss, (int)P);
   }
   s->args.ring = s->d_ring;
-  s->args.next = s->d_ctl;
-  s->args.published = s->d_ctl + 16;
+  s->args.next = (uint64_t *)s->d_ctl;
+  s->args.published = (const uint64_t *)(s->d_ctl + 16);
   s->args.stop = s->d_ctl + 32;
   s->args.res_ids = mapped(s->h_ids);
   s->args.res_dists = mapped(s->h_dists);

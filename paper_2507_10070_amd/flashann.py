@@ -66,7 +66,8 @@ class ServerOptions(ctypes.Structure):
                 ("queue_cap", ctypes.c_int32), ("idle_polls", ctypes.c_int32),
                 ("beam_width", ctypes.c_int32), ("transport", ctypes.c_int32),
                 ("spin_limit", ctypes.c_uint32),
-                ("navigation", ctypes.c_int32), ("pq_scoring", ctypes.c_int32)]
+                ("navigation", ctypes.c_int32), ("pq_scoring", ctypes.c_int32),
+                ("first_ticket", ctypes.c_uint64)]
 
 
 class Result(ctypes.Structure):
@@ -261,11 +262,16 @@ class Index:
         return {f: getattr(out, f) for f, _ in IndexInfo._fields_}
 
     def close(self):
+        """Release the index; AnnError (ANN_EBUSY) while a server on it is open."""
         if getattr(self, "_h", None) is not None:
-            load_library().ann_index_free(self._h)
+            _check(load_library().ann_index_free(self._h))
             self._h = None
 
-    __del__ = close
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass  # still in use by an open server: the server keeps a reference
 
     def __enter__(self):
         return self
@@ -276,6 +282,14 @@ class Index:
 
 def _ptr(t):
     return t.data_ptr() if t is not None else None
+
+
+def _check_buffer(name, t, dtypes, numel, dev):
+    if t.dtype not in dtypes or not t.is_cuda or t.device != dev or not t.is_contiguous() \
+            or t.numel() != numel:
+        raise ValueError("%s must be a contiguous %s tensor of %d elements on %s (got %s %s on %s)"
+                         % (name, "/".join(str(d) for d in dtypes), numel, dev, t.dtype,
+                            tuple(t.shape), t.device))
 
 
 def _prepare(index, queries, k, L, R, delay, beam_width, hash_bits, waves_per_block, stats,
@@ -295,13 +309,29 @@ def _prepare(index, queries, k, L, R, delay, beam_width, hash_bits, waves_per_bl
             raise ValueError("%s must be a CUDA int32 tensor of nq entries" % name)
     nq = queries.shape[0]
     dev = queries.device
+    dist_dtype = torch.float32 if index.dtype == np.float32 else torch.int32
     if out is None:
         ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
-        dists = torch.empty((nq, k), dtype=torch.float32 if index.dtype == np.float32
-                            else torch.int32, device=dev)
+        dists = torch.empty((nq, k), dtype=dist_dtype, device=dev)
         steps = torch.empty((nq,), dtype=torch.int32, device=dev)
     else:
         ids, dists, steps = out
+    # every caller-supplied device buffer is written by the kernel: its
+    # dtype, device, contiguity and size must match what the launch assumes
+    _check_buffer("ids", ids, (torch.int32,), nq * k, dev)
+    _check_buffer("dists", dists, (dist_dtype,), nq * k, dev)
+    if steps is not None:
+        _check_buffer("steps", steps, (torch.int32,), nq, dev)
+    if stats is not None:
+        _check_buffer("stats", stats, (torch.int64,), 3, dev)
+    if trace is not None:
+        if trace.dim() != 2 or trace.shape[0] != nq or trace.shape[1] < 1:
+            raise ValueError("trace must be [nq, cap >= 1]")
+        _check_buffer("trace", trace, (torch.int32,), trace.numel(), dev)
+    if times is not None:
+        _check_buffer("times", times, (torch.int64,), 2 * nq, dev)
+    if phases is not None:
+        _check_buffer("phases", phases, (torch.int64,), 2 * nq, dev)
     opts = SearchOptions(delay, beam_width, hash_bits, waves_per_block, _ptr(stats), _ptr(trace),
                          trace.shape[1] if trace is not None else 0, _ptr(times), _ptr(phases),
                          transport, spin_limit, _ptr(L_per_query), _ptr(k_per_query), _ptr(order),
@@ -400,14 +430,15 @@ class Server:
                  delay: int = 1, waves_per_block: int = 0, hash_bits: int = 0,
                  queue_cap: int = 0, idle_polls: int = 0, beam_width: int = 1,
                  transport: int = TRANSPORT_AUTO, spin_limit: int = 0,
-                 navigation: int = NAV_FULL, pq_scoring: int = PQ_AUTO):
+                 navigation: int = NAV_FULL, pq_scoring: int = PQ_AUTO,
+                 first_ticket: int = 0):
         self.index = index
         self.dtype = index.dtype
         self.d = index.d
         self.k_max = k_max
         opts = ServerOptions(k_max, L_max, delay, waves_per_block, hash_bits, queue_cap,
                              idle_polls, beam_width, transport, spin_limit, navigation,
-                             pq_scoring)
+                             pq_scoring, first_ticket)
         h = ctypes.c_void_p()
         _check(load_library().ann_server_open(index.handle, int(hbm_budget_bytes),
                                               ctypes.byref(opts), ctypes.byref(h)))

@@ -1,6 +1,8 @@
 // graph_build.cpp -- deterministic proximity-graph construction for the
 // synthetic workloads (index building; the paper does not describe it and
-// inherits DiskANN-style graphs).  Input generation only: no search here.
+// inherits DiskANN-style graphs).  Input generation only: the greedy searches
+// of the refinement step (7) build the graph and share no code with the
+// search under test or with the oracle.
 //
 // Steps (all deterministic for a given seed, independent of thread count):
 //   1. kNN pool of size K per point: exact for n <= exact_limit, otherwise
@@ -25,9 +27,9 @@
 //      distances inside a component are nearly equal, so a rule with
 //      alpha = 1.2 keeps almost every candidate, the lists degenerate into
 //      kNN lists, and search recall fell to about 0.3 (measured); alpha = 1
-//      keeps them diverse.  Then steps 5 and 6 again.  Searches of a batch read a frozen graph and updates are
-//      applied in batch order, so the result does not depend on the number
-//      of threads.
+//      keeps them diverse.  Then steps 5 and 6 again.  Searches of a batch
+//      read a frozen graph and updates are applied in batch order, so the
+//      result does not depend on the number of threads.
 // Distances are squared L2 accumulated in int32 (u8/i8) or float (f32) and
 // compared as float with ties broken by id.
 #include <algorithm>

@@ -21,6 +21,8 @@ def main(path):
 
     for case in range(3):
         P.test_worked_example(case)
+    for case in range(5):
+        P.test_beam_schedule_example(case)
     for dt in (np.uint8, np.int8, np.float32):
         P.test_distances_match_scipy(dt)
         P.test_bruteforce_matches_lexsort(dt)

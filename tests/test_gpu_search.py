@@ -1,24 +1,23 @@
 """GPU parity: the HIP search (through the C ABI) against the CPU oracle.
 
 Integer vectors: ids, distances, step counts and expansion traces bit-exact.
-fp32 vectors: every returned distance within 1e-5 relative of its fp64 value;
-ids and traces equal unless the traces diverge, and every divergence must be
-explained by a near-tie (two candidates within 1e-5 relative) at the first
-divergent selection.
+fp32 vectors: the positional rule of tests/parity.py for every query (each
+distance within 1e-5 relative of the oracle's at the same position; a
+different id only at a tie inside the tolerance), with trace divergences
+explained by a near-tie at the first divergent selection and bounded in
+number.
 """
 import numpy as np
 import pytest
 
 import oracle
 import synth
+from parity import assert_f32_parity, assert_int_parity
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 fa = pytest.importorskip("paper_2507_10070_amd")
-
-TOL = 1e-5
-
 
 def dev():
     return torch.device("cuda:0")
@@ -45,18 +44,6 @@ def gpu_search(ix, q, k, L, trace_cap=0, **kw):
     if trace is not None:
         out["trace"] = trace.cpu().numpy()
     return out
-
-
-def assert_int_parity(g, ref, check_trace=False):
-    np.testing.assert_array_equal(g["ids"], ref["ids"])
-    rd = ref["dists"]
-    gd = g["dists"].astype(np.float64)
-    gd[g["dists"] == 0xFFFFFFFF] = np.inf
-    np.testing.assert_array_equal(gd, rd)
-    np.testing.assert_array_equal(g["steps"], ref["steps"])
-    if check_trace:
-        cap = g["trace"].shape[1]
-        np.testing.assert_array_equal(g["trace"], ref["trace"][:, :cap])
 
 
 @pytest.mark.parametrize("tier", ["hbm", "host"])
@@ -175,29 +162,6 @@ def test_padding_and_unreachable():
             assert g["ids"][0].tolist() == [0, 1, -1, -1]
 
 
-def assert_f32_parity(base, q, g, ref):
-    explained = unexplained = 0
-    for i in range(len(q)):
-        full = oracle.distances(base, q[i])
-        ids = g["ids"][i]
-        ok = ids >= 0
-        np.testing.assert_allclose(g["dists"][i][ok], full[ids[ok]], rtol=TOL, atol=0)
-        gt, rt = g["trace"][i], ref["trace"][i][: g["trace"].shape[1]]
-        if np.array_equal(gt, rt):
-            np.testing.assert_array_equal(ids, ref["ids"][i])
-            np.testing.assert_allclose(g["dists"][i][ok], ref["dists"][i][ok], rtol=TOL)
-            assert g["steps"][i] == ref["steps"][i]
-            continue
-        t = int(np.argmax(gt != rt))
-        a, b = int(gt[t]), int(rt[t])
-        if a >= 0 and b >= 0 and abs(full[a] - full[b]) <= TOL * max(full[a], full[b]):
-            explained += 1
-        else:
-            unexplained += 1
-    assert unexplained == 0, "%d divergent queries without a near-tie" % unexplained
-    return explained
-
-
 @pytest.mark.parametrize("d,R", [(96, 32), (128, 24), (33, 10)])
 def test_f32_parity(d, R):
     base = synth.make_base(5000, d, "f32", 64, 601)
@@ -255,6 +219,31 @@ def test_degree_selector_small():
     for r in rows:
         assert r["T_f_us"] > 0 and r["T_c_us"] > 0 and r["expansions"] > 0
     assert degree_selector.select(rows) in (8, 24)
+
+
+def test_beam_schedule_example_hand_derived():
+    """The hand-derived example of tests/golden/beam_schedule_example.json
+    (staleness 0..2, beam width 1..2) run on the GPU: every schedule's trace,
+    step count and answer as derived by hand."""
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "beam_schedule_example.json")
+    with open(path) as f:
+        gold = json.load(f)
+    x = np.array(gold["points_1d_u8"], dtype=np.uint8).reshape(-1, 1)
+    adj = np.array(gold["adjacency"], dtype=np.int32)
+    q = np.array([[gold["query_1d_u8"]]], dtype=np.uint8)
+    with fa.Index(x, adj, gold["entry"], min_slot(1, 1, 2)) as ix:
+        for c in gold["cases"]:
+            for hbits in (0, 6):
+                g = gpu_search(ix, q, gold["k"], gold["L"], delay=c["delay"],
+                               beam_width=c["beam"], hash_bits=hbits, trace_cap=16)
+                assert g["ids"][0].tolist() == c["ids"], c
+                assert g["dists"][0].tolist() == c["dists"], c
+                assert int(g["steps"][0]) == c["steps"], c
+                tr = g["trace"][0]
+                assert tr[tr >= 0].tolist() == c["trace"], c
 
 
 # Any staleness and beam width: the generic FIFO kernel (delta * W nodes may

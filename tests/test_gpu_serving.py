@@ -263,3 +263,46 @@ def test_server_navigation_needs_its_data(cfg1):
             srv.submit(q[0], 10, 64, 0)
             r = collect(srv, 1)[0]
         assert r["status"] == 0 and (r["ids"] >= 0).all()
+
+
+@pytest.mark.parametrize("transport", ["direct", "agent"])
+def test_tickets_past_two_to_the_32(cfg1, transport):
+    """Admission tickets start just below 2^32 and run past it: a ticket cut
+    to 32 bits anywhere would name the wrong ring entry or stop the claims.
+    A small budget keeps the ring short, so its index wraps as well."""
+    base, q, adj, entry = cfg1
+    ref = oracle.search(base, adj, entry, q, 10, 64, delay=1)
+    tr = fa.TRANSPORT_AGENT if transport == "agent" else fa.TRANSPORT_DIRECT
+    with fa.Index(base, adj, entry, 256, fa.TIER_HOST) as ix:
+        probe = fa.Server(ix, hbm_budget_bytes=64 << 20, transport=tr)
+        resident = probe.stats()["resident_waves"]
+        probe.close()
+        with fa.Server(ix, hbm_budget_bytes=(resident + 5) * (16 + 128), transport=tr,
+                       first_ticket=(1 << 32) - 37) as srv:
+            for rep in range(3):
+                for i in range(len(q)):
+                    srv.submit(q[i], 10, 64, 1000 * rep + i)
+                got = collect(srv, len(q))
+                for i in range(len(q)):
+                    r = got[1000 * rep + i]
+                    assert r["status"] == 0
+                    np.testing.assert_array_equal(r["ids"], ref["ids"][i])
+                    np.testing.assert_array_equal(r["dists"].astype(np.float64), ref["dists"][i])
+                    assert r["steps"] == ref["steps"][i]
+            st = srv.stats()
+    assert st["completed"] == 3 * len(q)
+
+
+def test_index_free_refused_while_a_server_is_open(cfg1):
+    base, q, adj, entry = cfg1
+    ix = fa.Index(base, adj, entry, 256, fa.TIER_HBM)
+    srv = fa.Server(ix, hbm_budget_bytes=64 << 20)
+    with pytest.raises(fa.AnnError) as e:
+        ix.close()
+    assert e.value.code == -16
+    srv.submit(q[0], 10, 64, 0)           # the index is intact and still served
+    r = collect(srv, 1)[0]
+    ref = oracle.search(base, adj, entry, q[:1], 10, 64, delay=1)
+    np.testing.assert_array_equal(r["ids"], ref["ids"][0])
+    srv.close()
+    ix.close()                            # allowed once the server closed

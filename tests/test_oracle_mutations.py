@@ -4,7 +4,10 @@ Each mutant is a copy of oracle.c with one plausible mistake -- a reversed
 tie-break, an off-by-one staleness, a dropped visited mark, a dropped
 dimension or neighbour, a short candidate list, a wrong sign, and in the PQ
 navigation a dropped subspace, a reversed code tie-break, a shifted centroid,
-an exact entry key or a missing re-rank -- compiled into a temporary library.  The pin battery (tests/oracle_battery.py) must fail on
+an exact entry key or a missing re-rank, and in the beam-width schedule a
+drain of all or of one in-flight node when nothing was selected and a
+processing threshold of delay instead of delay*W -- compiled into a
+temporary library.  The pin battery (tests/oracle_battery.py) must fail on
 every mutant and pass on the unmodified source.
 """
 import os
@@ -43,6 +46,12 @@ MUTANTS = {
     "pq_answer_not_reranked": ("out = res;\n    nout = nres;", "out = cand;\n    nout = nc;"),
     "pq_encode_slices_leave_a_gap": ("orc_enc_job j = {base, n * t / threads, n * (t + 1) / threads,",
                                      "orc_enc_job j = {base, n * t / threads + (t > 0), n * (t + 1) / threads,"),
+    "drain_all_in_flight_when_idle": ("if (nsel == 0 && to_process == 0) to_process = f_len < W ? f_len : W;",
+                                      "if (nsel == 0 && to_process == 0) to_process = f_len;"),
+    "drain_one_when_idle": ("if (nsel == 0 && to_process == 0) to_process = f_len < W ? f_len : W;",
+                            "if (nsel == 0 && to_process == 0) to_process = 1;"),
+    "threshold_ignores_beam": ("if (f_len > J->delay * W) to_process = f_len - J->delay * W;",
+                               "if (f_len > J->delay) to_process = f_len - J->delay;"),
     "selects_second_unexpanded": ("if (cand[i].expanded) continue;",
                                   "if (cand[i].expanded || (nsel == 0 && i == 0 && nc > 1 && !cand[1].expanded)) continue;"),
 }

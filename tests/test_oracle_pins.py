@@ -1,6 +1,9 @@
 """Pins of the CPU oracle against things other than itself.
 
 * a hand-derived worked example (tests/golden/worked_example.json);
+* a second hand-derived example for beam width W > 1 and staleness 2
+  (tests/golden/beam_schedule_example.json), built so that the drain rule and
+  the delay*W processing threshold change the selection order;
 * exhaustive search: with L >= N on a connected graph every reachable node is
   expanded, so the result must be the exact top-k of a full scan computed
   with numpy's lexsort (paper section 4.1.1 search + the definition of k-NN);
@@ -20,6 +23,7 @@ from scipy.spatial.distance import cdist
 import oracle
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "worked_example.json")
+BEAM_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "beam_schedule_example.json")
 
 
 def _example():
@@ -44,6 +48,30 @@ def test_worked_example(case):
     if c["theta"] is not None:
         th = r["theta"][0]
         assert th[~np.isnan(th)].tolist() == c["theta"]
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_beam_schedule_example(case):
+    """(delay, W) in {(0,1), (1,1), (0,2), (1,2), (2,1)}: traces, step counts,
+    L-th key after each processed node (null = fewer than L candidates) and
+    answers derived by hand from the schedule of paper section 4.1.2 with the
+    beam-width reading R6."""
+    with open(BEAM_GOLDEN) as f:
+        g = json.load(f)
+    x = np.array(g["points_1d_u8"], dtype=np.uint8).reshape(-1, 1)
+    adj = np.array(g["adjacency"], dtype=np.int32)
+    q = np.array([[g["query_1d_u8"]]], dtype=np.uint8)
+    c = g["cases"][case]
+    r = oracle.search(x, adj, g["entry"], q, g["k"], g["L"], delay=c["delay"], beam=c["beam"],
+                      trace_cap=32)
+    assert r["ids"][0].tolist() == c["ids"]
+    assert r["dists"][0].tolist() == c["dists"]
+    assert int(r["steps"][0]) == c["steps"]
+    tr = r["trace"][0]
+    assert tr[tr >= 0].tolist() == c["trace"]
+    th = r["theta"][0]
+    want = [np.inf if t is None else float(t) for t in c["theta"]]
+    assert th[~np.isnan(th)].tolist() == want
 
 
 def _rand(dtype, n, d, rng):
