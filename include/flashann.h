@@ -302,6 +302,30 @@ int ann_search_graph(ann_index *ix, const void *d_queries, int64_t nq, int32_t k
 int ann_graph_launch(ann_graph *g, void *hip_stream);
 int ann_graph_free(ann_graph *g);
 
+/*
+ * ann_search_noalloc -- ann_search for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Arguments, layouts, ownership and results are those of
+ * ann_search; the call itself allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine, no memset node: scratch is cleared by kernels).
+ * Its scratch -- the persistent grid's work counter and the kernel-grained
+ * grid barrier state -- lives in a fixed device array of
+ * ANN_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds until the
+ * process ends.  Every call on a GPU shares that array, so calls that overlap
+ * on one GPU race: order them (e.g. one stream).  The index's device must be
+ * current.
+ * Supported: the DIRECT transport (records in HBM or host DRAM), one-shot or
+ * persistent grids, query- or kernel-grained synchronisation, every schedule
+ * and navigation of ann_search.
+ * Errors: those of ann_search; ANN_EINVAL for the AGENT transport or a FILE
+ * tier (their request lines are host memory the library allocates), for
+ * another device than the index's, or if the scratch need exceeded the array.
+ */
+#define ANN_NOALLOC_SCRATCH_BYTES 32768
+int ann_search_noalloc(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int32_t L,
+                       int32_t R, const ann_search_opts *opts, int32_t *d_ids, void *d_dists,
+                       uint32_t *d_steps, void *hip_stream);
+
 /* ann_device_clock_khz -- frequency of the device wall clock used by
  * ann_search_opts.d_times on the current device (host int, caller-owned). */
 int ann_device_clock_khz(int32_t *khz);

@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -583,10 +584,10 @@ int ann_agent_stats(const ann_index *ix, uint64_t *requests, uint64_t *bytes, ui
 namespace {
 
 // Waits for a kernel-grained search and reports an abandoned barrier wait.
-int check_lockstep(ann_index *ix, hipStream_t st) {
+int check_lockstep(const uint32_t *ctl, hipStream_t st) {
   uint32_t flag = 0;
   hipError_t e = hipStreamSynchronize(st);
-  if (e == hipSuccess) e = hipMemcpy(&flag, ix->d_ctl + 4, sizeof(flag), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(&flag, ctl + 4, sizeof(flag), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "kernel-grained search");
   if (flag) return fail(ANN_ETIMEDOUT, "a grid barrier wait exceeded spin_limit; results invalid");
   return ANN_OK;
@@ -609,7 +610,7 @@ void set_pq_args(const ann_index *ix, int32_t pq_scoring, fa::SearchArgs *a) {
 int prepare_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int32_t L,
                    int32_t R, const ann_search_opts *opts, int32_t *d_ids, void *d_dists,
                    uint32_t *d_steps, ann_search_opts *o_out, int *transport_out,
-                   fa::SearchArgs *args, bool *empty) {
+                   fa::SearchArgs *args, bool *empty, bool may_allocate = true) {
   *empty = false;
   if (!ix) return fail(ANN_EINVAL, "index is NULL");
   if (nq < 0) return fail(ANN_EINVAL, "nq=%lld", (long long)nq);
@@ -668,11 +669,11 @@ int prepare_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, 
     return ANN_OK;
   }
   if (!d_queries || !d_ids || !d_dists) return fail(ANN_EINVAL, "NULL query/output pointer");
-  if (o.persistent && !ix->d_work) {
+  if (o.persistent && !ix->d_work && may_allocate) {
     hipError_t e = hipMalloc(&ix->d_work, sizeof(uint32_t));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(work counter)");
   }
-  if (o.sync_grain && !ix->d_ctl) {
+  if (o.sync_grain && !ix->d_ctl && may_allocate) {
     hipError_t e = hipMalloc(&ix->d_ctl, fa::kLockstepCtlWords * sizeof(uint32_t));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(barrier state)");
   }
@@ -736,7 +737,7 @@ int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int3
   if (transport == ANN_TRANSPORT_DIRECT && o.sync_grain) {
     hipError_t e = fa::launch_lockstep(a, ix->d_ctl, ix->dtype, fa::TR_DIRECT, o.waves_per_block, st);
     if (e != hipSuccess) return hip_fail(e, "kernel-grained search launch");
-    return check_lockstep(ix, st);
+    return check_lockstep(ix->d_ctl, st);
   }
   if (transport == ANN_TRANSPORT_DIRECT) {
     hipError_t e = hipSuccess;
@@ -778,7 +779,7 @@ int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int3
   ix->agent->disarm();
   if (e != hipSuccess) return hip_fail(e, "search launch");
   if (es != hipSuccess) return hip_fail(es, "search");
-  if (o.sync_grain && (rc = check_lockstep(ix, st)) != ANN_OK) return rc;
+  if (o.sync_grain && (rc = check_lockstep(ix->d_ctl, st)) != ANN_OK) return rc;
   std::vector<int32_t> status((size_t)nq);
   if ((e = hipMemcpy(status.data(), ix->d_status, sizeof(int32_t) * nq, hipMemcpyDeviceToHost)) !=
       hipSuccess)
@@ -856,6 +857,92 @@ int ann_graph_free(ann_graph *g) {
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
   delete g;
+  return ANN_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ search without allocation
+// ann_search_noalloc keeps its scratch -- the persistent grid's work counter
+// (byte 0) and the kernel-grained grid barrier state (from byte 256) -- in
+// one fixed device array.  Each GPU the library runs on holds its own copy
+// until the process ends; every call on that GPU shares it, so calls that
+// overlap on one GPU race (the caller orders them, e.g. on one stream).  In
+// host code `scratch` is only a host-side stand-in: its device address on
+// the current GPU comes from hipGetSymbolAddress, once per device.
+namespace {
+
+constexpr size_t kScratchCtlOffset = 256;
+static_assert(kScratchCtlOffset + fa::kLockstepCtlWords * sizeof(uint32_t) <= ANN_NOALLOC_SCRATCH_BYTES,
+              "the barrier state must fit the scratch array");
+static __device__ __align__(256) uint32_t scratch[ANN_NOALLOC_SCRATCH_BYTES / sizeof(uint32_t)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on GPU `dev` (which is current).
+int scratch_on(int dev, uint32_t **out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(ANN_ENODEV, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(ANN_EIO, "scratch array has no device address");
+    g_scratch_dev[dev] = (uint32_t *)p;
+  }
+  *out = g_scratch_dev[dev];
+  return ANN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ann_search_noalloc(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int32_t L,
+                       int32_t R, const ann_search_opts *opts, int32_t *d_ids, void *d_dists,
+                       uint32_t *d_steps, void *hip_stream) {
+  if (!ix) return fail(ANN_EINVAL, "index is NULL");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != ix->device)
+    return fail(ANN_EINVAL, "the index lives on device %d; make it current (device %d is)",
+                ix->device, dev);
+  ann_search_opts o;
+  int transport = 0;
+  fa::SearchArgs a;
+  bool empty = false;
+  int rc = prepare_search(ix, d_queries, nq, k, L, R, opts, d_ids, d_dists, d_steps, &o,
+                          &transport, &a, &empty, /*may_allocate=*/false);
+  if (rc || empty) return rc;
+  if (transport != ANN_TRANSPORT_DIRECT)
+    return fail(ANN_EINVAL, "the allocation-free search reads records directly (HBM or host "
+                            "tier); the agent transport needs host request lines");
+  // the scratch need is fixed: one work counter and one barrier state
+  const size_t need = kScratchCtlOffset + (o.sync_grain ? fa::kLockstepCtlWords * sizeof(uint32_t) : 0);
+  if (need > ANN_NOALLOC_SCRATCH_BYTES)
+    return fail(ANN_EINVAL, "scratch need %zu B exceeds the %d B array", need,
+                ANN_NOALLOC_SCRATCH_BYTES);
+  uint32_t *base = nullptr;
+  if ((rc = scratch_on(dev, &base)) != ANN_OK) return rc;
+  uint32_t *work = base;
+  uint32_t *ctl = base + kScratchCtlOffset / sizeof(uint32_t);
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (o.sync_grain) {
+    a.spin_limit = o.spin_limit ? o.spin_limit : (1u << 24);
+    // the launcher clears the barrier state with a kernel before the search
+    e = fa::launch_lockstep(a, ctl, ix->dtype, fa::TR_DIRECT, o.waves_per_block, st);
+    if (e != hipSuccess) return hip_fail(e, "kernel-grained search launch");
+    return check_lockstep(ctl, st);
+  }
+  a.work = work;
+  e = hipSuccess;
+  if (o.persistent) e = fa::launch_reset(work, st);  // a kernel, not a memset
+  if (e == hipSuccess)
+    e = fa::launch_search(a, ix->dtype, fa::TR_DIRECT, o.waves_per_block, o.persistent != 0, st);
+  if (e != hipSuccess) return hip_fail(e, "search launch");
   return ANN_OK;
 }
 

@@ -30,7 +30,7 @@ EXPORTED = ["ann_index_create", "ann_index_info_get", "ann_search", "ann_index_f
             "ann_graph_launch", "ann_graph_free", "ann_server_open", "ann_server_submit",
             "ann_server_poll", "ann_server_stats_get", "ann_server_close", "ann_clock_us",
             "ann_server_submit_batch", "ann_server_poll_into", "ann_index_set_pq",
-            "ann_index_pq_codes"]
+            "ann_index_pq_codes", "ann_search_noalloc"]
 
 
 class AnnError(RuntimeError):
@@ -103,6 +103,8 @@ def load_library(path: str = LIB_PATH):
     lib.ann_search.argtypes = [vp, vp, i64, i32, i32, i32, ctypes.POINTER(SearchOptions),
                                vp, vp, vp, vp]
     lib.ann_search.restype = ctypes.c_int
+    lib.ann_search_noalloc.argtypes = lib.ann_search.argtypes
+    lib.ann_search_noalloc.restype = ctypes.c_int
     lib.ann_index_free.argtypes = [vp]
     lib.ann_index_free.restype = ctypes.c_int
     cp, u64p = ctypes.c_char_p, ctypes.POINTER(ctypes.c_uint64)
@@ -377,6 +379,32 @@ def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
                                      ctypes.byref(opts), ids.data_ptr(), dists.data_ptr(),
                                      steps.data_ptr() if steps is not None else None,
                                      st.cuda_stream))
+    return ids, dists, steps
+
+
+def search_noalloc(index: Index, queries, k: int, L: int, out, R: int = 0, delay: int = 1,
+                   beam_width: int = 1, hash_bits: int = 0, waves_per_block: int = 0,
+                   stats=None, trace=None, times=None, L_per_query=None, k_per_query=None,
+                   order=None, persistent: bool = False, stream=None,
+                   sync_grain: int = SYNC_QUERY, spin_limit: int = 0, navigation: int = NAV_FULL,
+                   pq_scoring: int = PQ_AUTO):
+    """ann_search_noalloc: the search without any allocation in the call.
+    `out` = (ids, dists, steps) device tensors are required (the binding
+    allocates nothing either); records are read directly (HBM or host tier)."""
+    import torch
+
+    if out is None:
+        raise ValueError("search_noalloc writes into caller-owned out=(ids, dists, steps)")
+    nq, ids, dists, steps, opts = _prepare(index, queries, k, L, R, delay, beam_width, hash_bits,
+                                           waves_per_block, stats, trace, times, None,
+                                           TRANSPORT_DIRECT, spin_limit, L_per_query, k_per_query,
+                                           order, persistent, out, sync_grain, navigation,
+                                           pq_scoring)
+    st = stream if stream is not None else torch.cuda.current_stream(queries.device)
+    _check(load_library().ann_search_noalloc(index.handle, queries.data_ptr(), nq, k, L, R,
+                                             ctypes.byref(opts), ids.data_ptr(), dists.data_ptr(),
+                                             steps.data_ptr() if steps is not None else None,
+                                             st.cuda_stream))
     return ids, dists, steps
 
 
