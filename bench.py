@@ -857,14 +857,34 @@ def main():
                       times=times, **kw)
             tt = times.cpu().numpy()
             lat = (tt[:, 1] - tt[:, 0]) / khz
+            p0 = index.agent_profile()
             t = time.perf_counter()
             for _ in range(reps):
                 fa.search(index, qsub, k=k, L=L, delay=delay, transport=fa.TRANSPORT_AGENT,
                           out=outs, **kw)
             el = (time.perf_counter() - t) / reps
-            return {"qps": round(qsub.shape[0] / el, 1), "ms_per_step": round(el * 1e3, 3),
-                    "query_latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
-                    "query_latency_ms_p99": round(float(np.percentile(lat, 99)), 3)}
+            p1 = index.agent_profile()
+            out = {"qps": round(qsub.shape[0] / el, 1), "ms_per_step": round(el * 1e3, 3),
+                   "query_latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
+                   "query_latency_ms_p99": round(float(np.percentile(lat, 99)), 3)}
+            out.update(agent_split(p0, p1, el * reps))
+            return out
+
+        def agent_split(p0, p1, wall_s):
+            """Where the agent threads' time went over a timed region: requests
+            per second, the fraction of the threads' wall time spent scanning
+            request lines, copying records or doing file I/O, and requests per
+            busy scan (the batch one pass serves)."""
+            d = {key: p1[key] - p0[key] for key in ("requests", "passes", "busy_passes",
+                                                    "scan_ns", "copy_ns", "io_ns")}
+            thr_s = max(1e-9, wall_s * p1["threads"])
+            return {"agent": {"threads": p1["threads"], "async_io": p1["async_io"],
+                              "requests_per_s": round(d["requests"] / wall_s, 1),
+                              "scan_frac": round(d["scan_ns"] / 1e9 / thr_s, 3),
+                              "copy_frac": round(d["copy_ns"] / 1e9 / thr_s, 3),
+                              "io_frac": round(d["io_ns"] / 1e9 / thr_s, 3),
+                              "requests_per_busy_pass": round(d["requests"] / max(1, d["busy_passes"]), 1),
+                              "passes_per_s_per_thread": round(d["passes"] / thr_s, 1)}}
 
         # query-grained (each query waits for its own records; relaxed and
         # strict) against kernel-grained (lockstep rounds, strict)
@@ -876,16 +896,23 @@ def main():
             for _ in range(rounds):  # alternate the modes so drift hits all alike
                 for m, delay, kw in modes:
                     res[m].append(measure(index, qsub, op[1], delay, reps, **kw))
-            out = {}
-            for m, rows in res.items():
-                out[m] = {key: round(float(np.mean([r[key] for r in rows])), 3) for key in rows[0]}
-            return out
+            def mean_rows(rows):
+                return {key: (mean_rows([r[key] for r in rows]) if isinstance(rows[0][key], dict)
+                              else round(float(np.mean([r[key] for r in rows])), 3))
+                        for key in rows[0]}
+
+            return {m: mean_rows(rows) for m, rows in res.items()}
 
         if tier == fa.TIER_HOST:
             reps = max(1, min(args.steps, 3))
             transports["agent_host"] = {"queries": nq, "L": op[1], **compare(ix, qd, reps, 1)}
             st = ix.agent_stats()
             transports["agent_host"]["agent_threads_requests"] = st["requests"]
+            # the GPU's completion polls share the host link with the staged
+            # records: the pause between polls, short (4 units, ~1.7 us) and
+            # the default (32 units, ~14 us)
+            transports["agent_host"]["poll_backoff"] = {
+                str(pb): measure(ix, qd, op[1], 1, reps, poll_backoff=pb)["qps"] for pb in (4, 32, 128)}
             log("agent transport: %s" % transports["agent_host"])
             kg = timed(op[1], 0, 3, 1, sync_grain=fa.SYNC_KERNEL)
             transports["direct_host"] = {

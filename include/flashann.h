@@ -98,6 +98,7 @@ typedef struct {
   int32_t direct_io;  /* ANN_TIER_FILE: 1 if the file is read with O_DIRECT */
   int32_t pq_m;       /* PQ subspaces of the codes in HBM (0 = none) */
   int32_t nav_full;   /* 1 while the full-precision navigation copy is held */
+  int32_t stripes;    /* ANN_TIER_FILE: record files the records are striped over */
 } ann_index_info;
 
 /* Search options; a NULL pointer means {delay = 1, beam_width = 1, defaults}. */
@@ -165,6 +166,10 @@ typedef struct {
                               Needs ann_index_set_pq; sync_grain 0 only;
                               d_stats[2] stays 0. */
   int32_t pq_scoring;      /* ann_pq_scoring (0 = auto); results do not depend on it */
+  int32_t poll_backoff;    /* AGENT: the longest pause between two polls of a
+                              completion word, in units of 1024 GPU cycles
+                              (about 0.43 us); pauses double from one unit up
+                              to it.  0 = 32.  Results do not depend on it. */
 } ann_search_opts;
 
 /*
@@ -216,9 +221,35 @@ int ann_build_index(const void *vectors, int64_t n, int32_t d, int32_t dtype, in
 int ann_load_records(const char *dir, int32_t tier, const char *records_path, ann_index **out);
 
 /*
+ * Records striped over several files, one per storage device (paper section
+ * 5.2 and 5.6: the records of one index spread over 1 to 8 SSDs).  Record v
+ * is slot v / stripes of file v % stripes, so consecutive ids alternate
+ * between devices and every device serves an equal share of random reads.
+ *
+ * ann_save_records_striped -- write the `stripes` record files `paths[s]`
+ * (host pointers; each file holds records s, s + stripes, ... in the layout
+ * of ann_index_create).  Errors: ANN_EINVAL (stripes not in [1, 16], bad
+ * sizes), ANN_EIO.
+ *
+ * ann_load_records_striped -- ann_load_records with the records in the
+ * `stripes` files `paths` (meta.json and vectors.bin from `dir`).  The FILE
+ * tier keeps one descriptor per stripe; the agent reads record v from file
+ * v % stripes, and each agent thread keeps its asynchronous reads in flight
+ * on every device at once.  HBM and HOST tiers read the stripes into memory.
+ * Errors: those of ann_load_records.
+ */
+int ann_save_records_striped(const void *vectors, const int32_t *adjacency, int64_t n, int32_t d,
+                             int32_t dtype, int32_t R, int32_t slot_bytes,
+                             const char *const *paths, int32_t stripes);
+int ann_load_records_striped(const char *dir, int32_t tier, const char *const *paths,
+                             int32_t stripes, ann_index **out);
+
+/*
  * ann_agent_configure -- settings of the host agent used by the AGENT
  * transport: `threads` (0 = default: hardware threads - 2, at most 32, for
- * memory copies; 64 for file reads, which block and set the queue depth).  The other
+ * memory copies; 8 for files read with O_DIRECT, each keeping up to 64
+ * asynchronous reads in flight; 64 for buffered file reads, which block in
+ * pread and set the queue depth by their number).  The other
  * arguments inject faults for tests, -1 = off: requests for `delay_node`
  * complete after `delay_us` microseconds (a straggler), requests for
  * `fail_node` complete with a read error (ANN_EIO for that query), requests
@@ -230,6 +261,23 @@ int ann_agent_configure(ann_index *ix, int32_t threads, int32_t delay_node, int3
 /* ann_agent_stats -- cumulative agent counters: requests served, bytes copied
  * or read, failed reads (host integers, caller-owned). */
 int ann_agent_stats(const ann_index *ix, uint64_t *requests, uint64_t *bytes, uint64_t *errors);
+
+/* ann_agent_profile_get -- where the agent threads' time went (cumulative
+ * over the agent's life; zeros before its first use).  A pass is one scan of
+ * a thread's query range; busy passes found or finished requests.  scan_ns:
+ * reading request lines; copy_ns: copying records from host memory into
+ * staging and publishing completions; io_ns: submitting and reaping file
+ * reads.  max_batch: most requests one scan found.  stripe_requests[s]:
+ * requests served from stripe s. */
+typedef struct {
+  uint64_t requests, bytes, errors, passes, busy_passes, scan_ns, copy_ns, io_ns, max_batch;
+  int32_t threads;   /* agent threads */
+  int32_t async_io;  /* 1 if file reads are asynchronous (O_DIRECT + Linux AIO) */
+  int32_t stripes;   /* record files (1 for host memory) */
+  int32_t reserved;
+  uint64_t stripe_requests[16];
+} ann_agent_profile;
+int ann_agent_profile_get(const ann_index *ix, ann_agent_profile *out);
 
 /*
  * ann_index_set_pq -- compressed navigation (paper section 2.2: the

@@ -41,7 +41,8 @@ struct ann_index {
   uint8_t *rec_dev = nullptr;   // device-visible record base (HBM / HOST tiers)
   uint8_t *rec_hbm = nullptr;   // hipMalloc'd records (tier HBM)
   void *rec_host = nullptr;     // hipHostMalloc'd records (tier HOST)
-  int fd = -1;                  // record file (tier FILE)
+  int fd = -1;                  // record file of stripe 0 (tier FILE)
+  std::vector<int> fds;         // tier FILE: one per stripe (fds[0] == fd)
   bool direct_io = false;
   int device = 0;
   int64_t hbm_bytes = 0;
@@ -118,7 +119,9 @@ void release(ann_index *ix) {
   if (ix->pq_cb) (void)hipFree(ix->pq_cb);
   if (ix->rec_hbm) (void)hipFree(ix->rec_hbm);
   if (ix->rec_host) (void)hipHostFree(ix->rec_host);
-  if (ix->fd >= 0) close(ix->fd);
+  for (const int f : ix->fds)
+    if (f >= 0) close(f);
+  if (ix->fds.empty() && ix->fd >= 0) close(ix->fd);
   delete ix;
 }
 
@@ -190,7 +193,19 @@ struct RecordSource {
   const uint8_t *vecs = nullptr;
   const int32_t *adj = nullptr;
   int fd = -1;
+  const int *stripes = nullptr;  // striped files (record v: file v % S, slot v / S)
+  int nstripes = 0;
   int fill(const ann_index *ix, int64_t i0, int64_t i1, uint8_t *dst) const {
+    if (nstripes > 1) {
+      for (int64_t i = i0; i < i1; i++) {
+        const int64_t off = (i / nstripes) * ix->slot;
+        if (pread(stripes[i % nstripes], dst + (i - i0) * ix->slot, (size_t)ix->slot, (off_t)off) !=
+            (ssize_t)ix->slot)
+          return fail(ANN_EIO, "stripe %lld read failed at %lld", (long long)(i % nstripes),
+                      (long long)off);
+      }
+      return ANN_OK;
+    }
     if (fd < 0) {
       pack_records(i0, i1, ix->vec_bytes, ix->vec_pad, ix->R, ix->slot, vecs, adj, dst);
       return ANN_OK;
@@ -239,12 +254,24 @@ int build_records(ann_index *ix, const RecordSource &src) {
   return ANN_OK;
 }
 
-// Memory copies are CPU-bound: one thread per spare hardware thread.  File
-// reads block in pread, so more threads keep more reads in flight (the queue
-// depth the storage sees).
-int default_agent_threads(bool file) {
+// Memory copies are CPU-bound: one thread per spare hardware thread.  Direct
+// file reads are asynchronous (kAioDepth in flight per thread), so a few
+// threads keep the storage queues full; buffered reads block in pread, so
+// there more threads keep more reads in flight.
+constexpr int kAioDepth = 64;
+int default_agent_threads(bool file, bool direct) {
   const int hw = (int)std::thread::hardware_concurrency();
-  return file ? 64 : std::max(1, std::min(32, hw - 2));
+  if (file) return direct ? 8 : 64;
+  return std::max(1, std::min(32, hw - 2));
+}
+
+fa::Agent *new_agent(ann_index *ix, int threads) {
+  const bool file = ix->tier == ANN_TIER_FILE;
+  const int32_t io = file && ix->direct_io ? (int32_t)round_up(ix->rec_bytes, 512) : ix->rec_bytes;
+  const int t = threads > 0 ? threads : default_agent_threads(file, ix->direct_io);
+  return new (std::nothrow) fa::Agent(file ? nullptr : (const uint8_t *)ix->rec_host,
+                                      ix->fds.data(), (int)ix->fds.size(), ix->direct_io,
+                                      ix->slot, ix->rec_bytes, io, t, kAioDepth);
 }
 
 // Transport buffers for nq queries and the agent itself.
@@ -252,9 +279,8 @@ int ensure_transport(ann_index *ix, int64_t nq, int32_t pslots) {
   const bool file = ix->tier == ANN_TIER_FILE;
   const int32_t io = file && ix->direct_io ? (int32_t)round_up(ix->rec_bytes, 512) : ix->rec_bytes;
   if (!ix->agent) {
-    const int t = ix->agent_threads > 0 ? ix->agent_threads : default_agent_threads(file);
-    ix->agent.reset(new fa::Agent(file ? nullptr : (const uint8_t *)ix->rec_host, ix->fd,
-                                  ix->direct_io, ix->slot, ix->rec_bytes, io, t));
+    ix->agent.reset(new_agent(ix, ix->agent_threads));
+    if (!ix->agent) return fail(ANN_ENOMEM, "agent");
   }
   if (nq <= ix->tcap && pslots <= ix->tslots) return ANN_OK;
   const int64_t cap = std::max<int64_t>({nq, ix->tcap, 1024});
@@ -395,6 +421,43 @@ int ann_save_index(const char *dir, const void *vectors, const int32_t *adjacenc
   return ANN_OK;
 }
 
+int ann_save_records_striped(const void *vectors, const int32_t *adjacency, int64_t n, int32_t d,
+                             int32_t dtype, int32_t R, int32_t slot_bytes,
+                             const char *const *paths, int32_t stripes) {
+  if (!vectors || !adjacency || !paths) return fail(ANN_EINVAL, "NULL argument");
+  if (stripes < 1 || stripes > fa::kMaxStripes)
+    return fail(ANN_EINVAL, "stripes=%d not in [1, %d]", stripes, fa::kMaxStripes);
+  if (n < 1 || d < 1 || R < 1 || (dtype != ANN_U8 && dtype != ANN_I8 && dtype != ANN_F32))
+    return fail(ANN_EINVAL, "bad sizes");
+  const int32_t vb = d * elem_bytes(dtype), vp = (int32_t)round_up(vb, 16);
+  if (slot_bytes < vp + 4 * R || slot_bytes % 16 != 0)
+    return fail(ANN_EINVAL, "slot_bytes=%d must be a multiple of 16 and >= %d", slot_bytes, vp + 4 * R);
+  std::vector<uint8_t> rec((size_t)slot_bytes);
+  for (int32_t s = 0; s < stripes; s++) {
+    if (!paths[s]) return fail(ANN_EINVAL, "stripe path %d is NULL", s);
+    FILE *f = std::fopen(paths[s], "wb");
+    if (!f) return fail(ANN_EIO, "cannot create %s: %s", paths[s], std::strerror(errno));
+    bool ok = true;
+    // stripe s holds records s, s + S, s + 2S, ... back to back
+    const int64_t chunk = std::max<int64_t>(1, (32ll << 20) / slot_bytes);
+    std::vector<uint8_t> buf((size_t)(chunk * slot_bytes));
+    int64_t inbuf = 0;
+    for (int64_t i = s; i < n && ok; i += stripes) {
+      pack_records(i, i + 1, vb, vp, R, slot_bytes, (const uint8_t *)vectors, adjacency,
+                   buf.data() + inbuf * slot_bytes);
+      inbuf++;
+      if (inbuf == chunk) {
+        ok = std::fwrite(buf.data(), 1, (size_t)(inbuf * slot_bytes), f) == (size_t)(inbuf * slot_bytes);
+        inbuf = 0;
+      }
+    }
+    if (ok && inbuf)
+      ok = std::fwrite(buf.data(), 1, (size_t)(inbuf * slot_bytes), f) == (size_t)(inbuf * slot_bytes);
+    if (!sync_close(f) || !ok) return fail(ANN_EIO, "write of %s failed", paths[s]);
+  }
+  return ANN_OK;
+}
+
 int ann_build_index(const void *vectors, int64_t n, int32_t d, int32_t dtype, int32_t R,
                     int32_t slot_bytes, uint64_t seed, const char *out_dir) {
   if (!vectors || !out_dir) return fail(ANN_EINVAL, "NULL argument");
@@ -418,8 +481,20 @@ int ann_build_index(const void *vectors, int64_t n, int32_t d, int32_t dtype, in
 }
 
 int ann_load_records(const char *dir, int32_t tier, const char *records_path, ann_index **out) {
-  if (!out || !dir) return fail(ANN_EINVAL, "NULL argument");
+  if (!dir) return fail(ANN_EINVAL, "NULL argument");
+  const std::string def = std::string(dir) + "/records.bin";
+  const char *path = records_path ? records_path : def.c_str();
+  return ann_load_records_striped(dir, tier, &path, 1, out);
+}
+
+int ann_load_records_striped(const char *dir, int32_t tier, const char *const *paths,
+                             int32_t stripes, ann_index **out) {
+  if (!out || !dir || !paths) return fail(ANN_EINVAL, "NULL argument");
   *out = nullptr;
+  if (stripes < 1 || stripes > fa::kMaxStripes)
+    return fail(ANN_EINVAL, "stripes=%d not in [1, %d]", stripes, fa::kMaxStripes);
+  for (int32_t s = 0; s < stripes; s++)
+    if (!paths[s]) return fail(ANN_EINVAL, "stripe path %d is NULL", s);
   if (tier != ANN_TIER_HBM && tier != ANN_TIER_HOST && tier != ANN_TIER_FILE)
     return fail(ANN_EINVAL, "tier=%d", tier);
   const std::string base(dir);
@@ -461,28 +536,53 @@ int ann_load_records(const char *dir, int32_t tier, const char *records_path, an
   if (!rc) rc = build_nav(ix, vecs.data());
   vecs.clear();
   vecs.shrink_to_fit();
-  const std::string rpath = records_path ? std::string(records_path) : base + "/records.bin";
-  if (!rc) {
+  // stripe s holds records s, s + S, ...: ceil((n - s) / S) slots
+  for (int32_t s = 0; s < stripes && !rc; s++) {
     struct stat st;
-    if (stat(rpath.c_str(), &st) != 0 || st.st_size < n * slot)
-      rc = fail(ANN_EIO, "%s missing or shorter than %lld records", rpath.c_str(), (long long)n);
+    const int64_t need = (n - s + stripes - 1) / stripes * slot;
+    if (stat(paths[s], &st) != 0 || st.st_size < need)
+      rc = fail(ANN_EIO, "%s missing or shorter than its %lld records", paths[s],
+                (long long)(need / slot));
   }
   if (!rc && tier == ANN_TIER_FILE) {
     // O_DIRECT when the slot is a multiple of the 512 B sector and the file
-    // system accepts it; buffered reads otherwise.
-    ix->fd = slot % 512 == 0 ? open(rpath.c_str(), O_RDONLY | O_DIRECT) : -1;
-    ix->direct_io = ix->fd >= 0;
-    if (ix->fd < 0) ix->fd = open(rpath.c_str(), O_RDONLY);
-    if (ix->fd < 0) rc = fail(ANN_EIO, "cannot open %s: %s", rpath.c_str(), std::strerror(errno));
-  } else if (!rc) {
-    RecordSource src;
-    src.fd = open(rpath.c_str(), O_RDONLY);
-    if (src.fd < 0) {
-      rc = fail(ANN_EIO, "cannot open %s", rpath.c_str());
-    } else {
-      rc = build_records(ix, src);
-      close(src.fd);
+    // system accepts it for every stripe; buffered reads otherwise.
+    bool direct = slot % 512 == 0;
+    for (int32_t s = 0; s < stripes && !rc; s++) {
+      int f = direct ? open(paths[s], O_RDONLY | O_DIRECT) : -1;
+      if (f < 0 && direct) {  // fall back for every stripe
+        direct = false;
+        for (const int g : ix->fds) close(g);
+        ix->fds.clear();
+        s = -1;
+        continue;
+      }
+      if (f < 0) f = open(paths[s], O_RDONLY);
+      if (f < 0) {
+        rc = fail(ANN_EIO, "cannot open %s: %s", paths[s], std::strerror(errno));
+        break;
+      }
+      ix->fds.push_back(f);
     }
+    ix->direct_io = direct;
+    if (!ix->fds.empty()) ix->fd = ix->fds[0];
+  } else if (!rc) {
+    std::vector<int> fds;
+    for (int32_t s = 0; s < stripes && !rc; s++) {
+      const int f = open(paths[s], O_RDONLY);
+      if (f < 0)
+        rc = fail(ANN_EIO, "cannot open %s", paths[s]);
+      else
+        fds.push_back(f);
+    }
+    if (!rc) {
+      RecordSource src;
+      src.fd = fds[0];
+      src.stripes = fds.data();
+      src.nstripes = stripes;
+      rc = build_records(ix, src);
+    }
+    for (const int f : fds) close(f);
   }
   if (rc) {
     release(ix);
@@ -498,6 +598,7 @@ int ann_index_info_get(const ann_index *ix, ann_index_info *out) {
   out->entry = ix->entry; out->slot_bytes = ix->slot; out->tier = ix->tier;
   out->nav_stride = ix->nav_stride; out->rec_bytes = ix->rec_bytes; out->hbm_bytes = ix->hbm_bytes;
   out->direct_io = ix->direct_io ? 1 : 0;
+  out->stripes = ix->tier == ANN_TIER_FILE ? (int32_t)ix->fds.size() : 0;
   out->pq_m = ix->pq_m;
   out->nav_full = ix->nav ? 1 : 0;
   return ANN_OK;
@@ -568,6 +669,28 @@ int ann_agent_configure(ann_index *ix, int32_t threads, int32_t delay_node, int3
   ix->faults.delay_us = delay_us;
   ix->faults.fail_node = fail_node;
   ix->faults.drop_node = drop_node;
+  return ANN_OK;
+}
+
+int ann_agent_profile_get(const ann_index *ix, ann_agent_profile *out) {
+  if (!ix || !out) return fail(ANN_EINVAL, "NULL argument");
+  *out = ann_agent_profile{};
+  const fa::Agent *a = ix->agent.get();
+  if (!a) return ANN_OK;
+  const fa::AgentStats &s = a->stats;
+  out->requests = s.requests.load();
+  out->bytes = s.bytes.load();
+  out->errors = s.errors.load();
+  out->passes = s.passes.load();
+  out->busy_passes = s.busy_passes.load();
+  out->scan_ns = s.scan_ns.load();
+  out->copy_ns = s.copy_ns.load();
+  out->io_ns = s.io_ns.load();
+  out->max_batch = s.max_batch.load();
+  out->threads = a->threads();
+  out->async_io = a->async_io() ? 1 : 0;
+  out->stripes = ix->tier == ANN_TIER_FILE ? (int32_t)ix->fds.size() : 1;
+  for (int i = 0; i < fa::kMaxStripes; i++) out->stripe_requests[i] = s.stripe_requests[i].load();
   return ANN_OK;
 }
 
@@ -659,6 +782,8 @@ int prepare_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, 
     return fail(ANN_EINVAL, "the full-precision navigation copy was released; use ANN_NAV_PQ");
   if (o.pq_scoring < 0 || o.pq_scoring > ANN_PQ_CACHE)
     return fail(ANN_EINVAL, "pq_scoring=%d", o.pq_scoring);
+  if (o.poll_backoff < 0 || o.poll_backoff > 1024)
+    return fail(ANN_EINVAL, "poll_backoff=%d not in [0, 1024]", o.poll_backoff);
   if (o.navigation == ANN_NAV_PQ && o.sync_grain)
     return fail(ANN_ENOTSUP, "kernel-grained search scores with the full-precision copy only");
   if (nq > 0x7FFFFFFFll) return fail(ANN_EINVAL, "nq=%lld too large", (long long)nq);
@@ -765,6 +890,7 @@ int ann_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, int3
   a.stage = dev_ptr(ix->stage);
   a.stage_stride = ix->stage_stride;
   a.spin_limit = o.spin_limit ? o.spin_limit : (1u << 24);
+  a.poll_nap = o.poll_backoff > 0 ? (uint32_t)o.poll_backoff : 32u;
   a.status = ix->d_status;
   if (!a.req || !a.cpl || !a.stage) return fail(ANN_EIO, "transport buffers not mapped");
   ix->agent->faults = ix->faults;
@@ -971,9 +1097,7 @@ int ann_internal_server_transport(ann_index *ix, int32_t requested, int32_t *tr,
   if (t == ANN_TRANSPORT_AGENT) {
     const bool file = ix->tier == ANN_TIER_FILE;
     const int32_t io = file && ix->direct_io ? (int32_t)round_up(ix->rec_bytes, 512) : ix->rec_bytes;
-    const int th = ix->agent_threads > 0 ? ix->agent_threads : default_agent_threads(file);
-    *agent = new (std::nothrow) fa::Agent(file ? nullptr : (const uint8_t *)ix->rec_host, ix->fd,
-                                          ix->direct_io, ix->slot, ix->rec_bytes, io, th);
+    *agent = new_agent(ix, ix->agent_threads);
     if (!*agent) return fail(ANN_ENOMEM, "server agent");
     (*agent)->faults = ix->faults;
     *stage_stride = round_up(io, 512);

@@ -53,6 +53,7 @@ struct SearchArgs {
   int64_t stage_stride;
   int32_t pslots;          // request slots per query: at least the requests in flight
   uint32_t spin_limit;     // polls of a completion word before the query times out
+  uint32_t poll_nap;       // longest pause between two polls, in 1024-cycle units
   int32_t *status;         // nq per-query status, device: 0, -5 (read error), -110 (timeout)
   uint32_t *line_seq;      // optional, device: last request number per transport line, kept
                            // across the queries a line serves (persistent server waves)

@@ -606,10 +606,11 @@ struct Searcher {
           c = kTimedOut;
           break;
         }
-        // back off (up to ~1.7 us) so that thousands of waiting waves do not
-        // flood the host link with polls
+        // back off, doubling up to poll_nap x 1024 cycles (~14 us by
+        // default): thousands of waiting waves must not flood the host link
+        // with polls, which compete with the staged records' reads
         for (uint32_t i = 0; i < nap; i++) __builtin_amdgcn_s_sleep(16);
-        nap = nap < 4 ? nap * 2 : 4;
+        nap = nap < A.poll_nap ? nap * 2 : A.poll_nap;
       }
     }
     c = (uint32_t)__builtin_amdgcn_readfirstlane((int)c);
@@ -623,15 +624,14 @@ struct Searcher {
     // The staged bytes are read with system-scope loads, issued after the
     // completion word was seen; they bypass the GPU caches, so no acquire
     // fence (which would invalidate the whole L2 on every record) is needed.
+    // Two 8 B loads per lane: each instruction reads the record's lines once
+    // (four 4 B loads would cross the host link four times per line).
     const int ch = lane < A.rec_chunks ? lane : A.rec_chunks - 1;
-    const uint32_t *src =
-        (const uint32_t *)(A.stage + (io.line * A.pslots + pslot(s)) * A.stage_stride + 16 * ch);
-    uint4 r;
-    r.x = __hip_atomic_load(src + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    r.y = __hip_atomic_load(src + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    r.z = __hip_atomic_load(src + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    r.w = __hip_atomic_load(src + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    return r;
+    const uint64_t *src =
+        (const uint64_t *)(A.stage + (io.line * A.pslots + pslot(s)) * A.stage_stride + 16 * ch);
+    const uint64_t lo = __hip_atomic_load(src + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    const uint64_t hi = __hip_atomic_load(src + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    return make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
   }
 
   // Part 1 of processing node u: stage its record (false if it failed).

@@ -459,6 +459,7 @@ int ann_server_open(ann_index *ix, size_t hbm_budget_bytes, const ann_server_opt
     s->args.base.cpl = mapped(s->h_cpl);
     s->args.base.stage = mapped(s->h_tstage);
     s->args.base.spin_limit = o.spin_limit ? o.spin_limit : (1u << 24);
+    s->args.base.poll_nap = 32u;
     s->args.base.line_seq = s->d_line_seq;
     if (!s->args.base.req || !s->args.base.cpl || !s->args.base.stage) {
       server_free(s);

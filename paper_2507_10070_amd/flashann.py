@@ -30,7 +30,8 @@ EXPORTED = ["ann_index_create", "ann_index_info_get", "ann_search", "ann_index_f
             "ann_graph_launch", "ann_graph_free", "ann_server_open", "ann_server_submit",
             "ann_server_poll", "ann_server_stats_get", "ann_server_close", "ann_clock_us",
             "ann_server_submit_batch", "ann_server_poll_into", "ann_index_set_pq",
-            "ann_index_pq_codes", "ann_search_noalloc"]
+            "ann_index_pq_codes", "ann_search_noalloc", "ann_save_records_striped",
+            "ann_load_records_striped", "ann_agent_profile_get"]
 
 
 class AnnError(RuntimeError):
@@ -48,7 +49,8 @@ class SearchOptions(ctypes.Structure):
                 ("spin_limit", ctypes.c_uint32), ("d_L", ctypes.c_void_p),
                 ("d_k", ctypes.c_void_p), ("d_order", ctypes.c_void_p),
                 ("persistent", ctypes.c_int32), ("sync_grain", ctypes.c_int32),
-                ("navigation", ctypes.c_int32), ("pq_scoring", ctypes.c_int32)]
+                ("navigation", ctypes.c_int32), ("pq_scoring", ctypes.c_int32),
+                ("poll_backoff", ctypes.c_int32)]
 
 
 class IndexInfo(ctypes.Structure):
@@ -57,7 +59,16 @@ class IndexInfo(ctypes.Structure):
                 ("tier", ctypes.c_int32), ("nav_stride", ctypes.c_int32),
                 ("rec_bytes", ctypes.c_int32), ("hbm_bytes", ctypes.c_int64),
                 ("direct_io", ctypes.c_int32), ("pq_m", ctypes.c_int32),
-                ("nav_full", ctypes.c_int32)]
+                ("nav_full", ctypes.c_int32), ("stripes", ctypes.c_int32)]
+
+
+class AgentProfile(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in ("requests", "bytes", "errors", "passes",
+                                                "busy_passes", "scan_ns", "copy_ns", "io_ns",
+                                                "max_batch")] + \
+               [("threads", ctypes.c_int32), ("async_io", ctypes.c_int32),
+                ("stripes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("stripe_requests", ctypes.c_uint64 * 16)]
 
 
 class ServerOptions(ctypes.Structure):
@@ -118,6 +129,13 @@ def load_library(path: str = LIB_PATH):
     lib.ann_agent_configure.restype = ctypes.c_int
     lib.ann_agent_stats.argtypes = [vp, u64p, u64p, u64p]
     lib.ann_agent_stats.restype = ctypes.c_int
+    lib.ann_agent_profile_get.argtypes = [vp, ctypes.POINTER(AgentProfile)]
+    lib.ann_agent_profile_get.restype = ctypes.c_int
+    lib.ann_save_records_striped.argtypes = [vp, vp, i64, i32, i32, i32, i32,
+                                             ctypes.POINTER(cp), i32]
+    lib.ann_save_records_striped.restype = ctypes.c_int
+    lib.ann_load_records_striped.argtypes = [cp, i32, ctypes.POINTER(cp), i32, ctypes.POINTER(vp)]
+    lib.ann_load_records_striped.restype = ctypes.c_int
     lib.ann_index_set_pq.argtypes = [vp, vp, i32, i32]
     lib.ann_index_set_pq.restype = ctypes.c_int
     lib.ann_index_pq_codes.argtypes = [vp, vp]
@@ -178,6 +196,17 @@ def save_index(path: str, vectors: np.ndarray, adjacency: np.ndarray, entry: int
                                          int(slot_bytes)))
 
 
+def save_records_striped(vectors: np.ndarray, adjacency: np.ndarray, slot_bytes: int,
+                         stripe_paths) -> None:
+    """ann_save_records_striped: record v goes to slot v // S of file v % S."""
+    vectors = np.ascontiguousarray(vectors)
+    adjacency = np.ascontiguousarray(adjacency, dtype=np.int32)
+    arr = (ctypes.c_char_p * len(stripe_paths))(*[p.encode() for p in stripe_paths])
+    _check(load_library().ann_save_records_striped(
+        vectors.ctypes.data, adjacency.ctypes.data, vectors.shape[0], vectors.shape[1],
+        DTYPE_CODES[vectors.dtype], adjacency.shape[1], int(slot_bytes), arr, len(stripe_paths)))
+
+
 def build_index(path: str, vectors: np.ndarray, R: int, slot_bytes: int, seed: int) -> None:
     """ann_build_index: construct the graph and write the index directory."""
     vectors = np.ascontiguousarray(vectors)
@@ -217,6 +246,31 @@ class Index:
         _check(load_library().ann_agent_stats(self.handle, ctypes.byref(r), ctypes.byref(b),
                                               ctypes.byref(e)))
         return {"requests": r.value, "bytes": b.value, "errors": e.value}
+
+    def agent_profile(self) -> dict:
+        """ann_agent_profile_get: counters and time split of the agent threads."""
+        p = AgentProfile()
+        _check(load_library().ann_agent_profile_get(self.handle, ctypes.byref(p)))
+        out = {f: getattr(p, f) for f, _ in AgentProfile._fields_
+               if f not in ("reserved", "stripe_requests")}
+        out["stripe_requests"] = list(p.stripe_requests)[:max(1, p.stripes)]
+        return out
+
+    @classmethod
+    def load_striped(cls, path: str, stripe_paths, tier: int = TIER_FILE) -> "Index":
+        """ann_load_records_striped: an index directory whose records are
+        striped over the files `stripe_paths` (record v in file v % S)."""
+        self = cls.__new__(cls)
+        self._h = None
+        arr = (ctypes.c_char_p * len(stripe_paths))(*[p.encode() for p in stripe_paths])
+        h = ctypes.c_void_p()
+        _check(load_library().ann_load_records_striped(path.encode(), int(tier), arr,
+                                                       len(stripe_paths), ctypes.byref(h)))
+        self._h = h
+        info = self.info()
+        self.dtype = _CODE_DTYPES[info["dtype"]]
+        self.d = info["d"]
+        return self
 
     def __init__(self, vectors: np.ndarray, adjacency: np.ndarray, entry: int,
                  slot_bytes: int, tier: int = TIER_HBM):
@@ -296,7 +350,8 @@ def _check_buffer(name, t, dtypes, numel, dev):
 
 def _prepare(index, queries, k, L, R, delay, beam_width, hash_bits, waves_per_block, stats,
              trace, times, phases, transport, spin_limit, L_per_query, k_per_query, order,
-             persistent, out, sync_grain=0, navigation=NAV_FULL, pq_scoring=PQ_AUTO):
+             persistent, out, sync_grain=0, navigation=NAV_FULL, pq_scoring=PQ_AUTO,
+             poll_backoff=0):
     import torch
 
     if queries.dim() != 2 or queries.shape[1] != index.d:
@@ -338,7 +393,7 @@ def _prepare(index, queries, k, L, R, delay, beam_width, hash_bits, waves_per_bl
                          trace.shape[1] if trace is not None else 0, _ptr(times), _ptr(phases),
                          transport, spin_limit, _ptr(L_per_query), _ptr(k_per_query), _ptr(order),
                          1 if persistent else 0, int(sync_grain), int(navigation),
-                         int(pq_scoring))
+                         int(pq_scoring), int(poll_backoff))
     return nq, ids, dists, steps, opts
 
 
@@ -347,7 +402,7 @@ def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
            trace=None, times=None, phases=None, transport: int = TRANSPORT_AUTO,
            spin_limit: int = 0, L_per_query=None, k_per_query=None, order=None,
            persistent: bool = False, stream=None, out=None, sync_grain: int = SYNC_QUERY,
-           navigation: int = NAV_FULL, pq_scoring: int = PQ_AUTO):
+           navigation: int = NAV_FULL, pq_scoring: int = PQ_AUTO, poll_backoff: int = 0):
     """ann_search on torch CUDA tensors.
 
     queries: [nq, d] device tensor of the index dtype (uint8/int8/float32).
@@ -373,7 +428,7 @@ def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
                                            waves_per_block, stats, trace, times, phases,
                                            transport, spin_limit, L_per_query, k_per_query,
                                            order, persistent, out, sync_grain, navigation,
-                                           pq_scoring)
+                                           pq_scoring, poll_backoff)
     st = stream if stream is not None else torch.cuda.current_stream(queries.device)
     _check(load_library().ann_search(index.handle, queries.data_ptr(), nq, k, L, R,
                                      ctypes.byref(opts), ids.data_ptr(), dists.data_ptr(),

@@ -1,13 +1,22 @@
 // CPU exercise of the query-grained record transport: threads play the GPU
 // waves (same structs, same atomics), the real agent serves them.  Built with
-// ThreadSanitizer by tests/test_agent_protocol.py.
+// ThreadSanitizer and AddressSanitizer by tests/test_agent_protocol.py.
 //
 // Each fake wave keeps up to `depth` requests outstanding (1: strict, 2: one
 // step stale, P: a full pipeline of P slots), consumes them in order, waits on
 // each completion word with acquire loads, and checks the staged bytes
 // against the record store.  Faults: a slow node (straggler) and a failing
 // node (error completion).
+//
+// Usage: agent_test NQ AGENTS [mode [dir]]; mode "mem" (records in memory,
+// default), "wrap" (memory, request numbers crossing their wrap point),
+// "file" (one record file in dir, O_DIRECT + asynchronous reads where the
+// file system allows) or "stripes" (three striped record files in dir).
+#include <fcntl.h>
+#include <unistd.h>
+
 #include <atomic>
+#include <string>
 #include <cstdio>
 #include <deque>
 #include <cstring>
@@ -30,12 +39,34 @@ int main(int argc, char **argv) {
   const int agents = argc > 2 ? atoi(argv[2]) : 3;
   // request numbers already used per line: "wrap" starts just below the
   // point where they wrap around, so every line crosses it
-  const bool wrap = argc > 3 && std::strcmp(argv[3], "wrap") == 0;
+  const std::string mode = argc > 3 ? argv[3] : "mem";
+  const bool wrap = mode == "wrap";
+  const bool file = mode == "file" || mode == "stripes";
+  const int nstripes = mode == "stripes" ? 3 : 1;
+  const std::string dir = argc > 4 ? argv[4] : "/tmp";
   const int steps = 200;
   std::vector<uint8_t> records(n * slot);
   for (int64_t i = 0; i < n * slot; i++) records[i] = (uint8_t)((i * 2654435761ull) >> 13);
 
-  fa::Agent agent(records.data(), -1, false, slot, (int32_t)copy, (int32_t)copy, agents);
+  // record files: record v is slot v / S of file v % S
+  std::vector<int> fds;
+  bool direct = true;
+  for (int s = 0; file && s < nstripes; s++) {
+    const std::string path = dir + "/stripe" + std::to_string(s) + ".bin";
+    FILE *f = std::fopen(path.c_str(), "wb");
+    if (!f) return 2;
+    for (int64_t v = s; v < n; v += nstripes) std::fwrite(&records[v * slot], 1, slot, f);
+    std::fclose(f);
+    int fd = open(path.c_str(), O_RDONLY | O_DIRECT);
+    if (fd < 0) {
+      direct = false;
+      fd = open(path.c_str(), O_RDONLY);
+    }
+    if (fd < 0) return 2;
+    fds.push_back(fd);
+  }
+  fa::Agent agent(file ? nullptr : records.data(), fds.data(), (int)fds.size(), file && direct,
+                  slot, (int32_t)copy, file && direct ? 512 : (int32_t)copy, agents, 16);
   agent.faults.delay_node = 7;
   agent.faults.delay_us = 300;
   agent.faults.fail_node = 11;
@@ -113,7 +144,17 @@ int main(int argc, char **argv) {
   while (__atomic_load_n(&cpl[1], __ATOMIC_ACQUIRE) != 1u) std::this_thread::yield();
   bad += check(std::memcmp(&stage[1 * stride], &records[42 * slot], copy) == 0, "re-armed serve");
   agent.disarm();
-  std::printf("%s: %lld queries x %d requests, %d agents, %d injected failures\n",
-              bad ? "FAIL" : "OK", (long long)nq, steps, agents, failures_seen.load());
+  if (file) {
+    uint64_t per_stripe = 0;
+    for (int s = 0; s < nstripes; s++) per_stripe += agent.stats.stripe_requests[s].load();
+    bad += check(per_stripe == agent.stats.requests.load(), "requests counted per stripe");
+    for (int s = 0; s < nstripes; s++)
+      bad += check(agent.stats.stripe_requests[s].load() > 0, "every stripe served");
+    bad += check(agent.async_io() == direct, "asynchronous reads with O_DIRECT");
+  }
+  for (int fd : fds) close(fd);
+  std::printf("%s: %lld queries x %d requests, %d agents, %d injected failures, mode %s%s\n",
+              bad ? "FAIL" : "OK", (long long)nq, steps, agents, failures_seen.load(),
+              mode.c_str(), file ? (direct ? " (O_DIRECT, asynchronous)" : " (buffered)") : "");
   return bad ? 1 : 0;
 }

@@ -38,3 +38,23 @@ def test_agent_protocol_sequence_wrap(tmp_path):
     exe = _build(tmp_path, "address")
     r = subprocess.run([exe, "32", "3", "wrap"], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stdout + r.stderr
+
+
+def test_agent_file_async_reads(tmp_path):
+    """Records in a file read with O_DIRECT through Linux asynchronous I/O:
+    every staged record and completion right, faults per request."""
+    exe = _build(tmp_path, "address")
+    r = subprocess.run([exe, "48", "3", "file", str(tmp_path)], capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    print(r.stdout)
+
+
+def test_agent_striped_files_tsan(tmp_path):
+    """Three striped record files (record v in file v % 3), served by agent
+    threads under ThreadSanitizer; every stripe serves its share."""
+    exe = _build(tmp_path, "thread")
+    r = subprocess.run([exe, "40", "2", "stripes", str(tmp_path)], capture_output=True,
+                       text=True, timeout=300, env=dict(os.environ, TSAN_OPTIONS="halt_on_error=1"))
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "ThreadSanitizer" not in r.stderr

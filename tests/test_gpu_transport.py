@@ -214,3 +214,67 @@ def test_kernel_grained_agent_parity(cfg1, tmp_path):
     with fa.Index.load(d, fa.TIER_FILE) as fix:
         assert_same(run(fix, q, 10, 64, delay=0, sync_grain=fa.SYNC_KERNEL,
                         spin_limit=1 << 22), ref)
+
+
+@pytest.mark.parametrize("stripes", [1, 2, 4])
+def test_striped_records_parity(cfg1, tmp_path, stripes):
+    """Records striped over S files (record v in file v % S, as over S
+    storage devices): the file tier read by the agents' asynchronous reads,
+    and the host tier loaded from the stripes, give the oracle's results
+    bit-exactly; every stripe serves its share of the reads."""
+    base, q, adj, entry = cfg1
+    d = str(tmp_path / "ix")
+    fa.save_index(d, base, adj, entry, 512)
+    paths = [str(tmp_path / ("stripe%d.bin" % s)) for s in range(stripes)]
+    fa.save_records_striped(base, adj, 512, paths)
+    ref = {delay: oracle.search(base, adj, entry, q, 10, 64, delay=delay, trace_cap=400)
+           for delay in (0, 1)}
+    with fa.Index.load_striped(d, paths, fa.TIER_FILE) as ix:
+        info = ix.info()
+        assert info["stripes"] == stripes
+        for delay in (0, 1):
+            g = run(ix, q, 10, 64, delay=delay, trace_cap=400)
+            assert_same(g, ref[delay])
+            np.testing.assert_array_equal(g["trace"], ref[delay]["trace"])
+        prof = ix.agent_profile()
+        print("agent profile", prof)
+        assert prof["stripes"] == stripes and prof["errors"] == 0
+        assert sum(prof["stripe_requests"]) == prof["requests"]
+        assert prof["requests"] == int(ref[0]["steps"].sum() + ref[1]["steps"].sum())
+        if stripes > 1:
+            assert min(prof["stripe_requests"]) > 0
+        if info["direct_io"]:
+            assert prof["async_io"] == 1
+    with fa.Index.load_striped(d, paths, fa.TIER_HOST) as hix:
+        assert_same(run(hix, q, 10, 64, delay=1), ref[1])
+        assert_same(run(hix, q, 10, 64, delay=1, transport=fa.TRANSPORT_AGENT), ref[1])
+
+
+def test_striped_records_faults_and_validation(cfg1, tmp_path):
+    base, q, adj, entry = cfg1
+    d = str(tmp_path / "ix")
+    fa.save_index(d, base, adj, entry, 512)
+    paths = [str(tmp_path / ("s%d.bin" % s)) for s in range(3)]
+    fa.save_records_striped(base, adj, 512, paths)
+    ref = oracle.search(base, adj, entry, q, 10, 64, delay=1, trace_cap=400)
+    bad_node = _node_in_some_traces(ref)
+    hit = np.array([(row == bad_node).any() for row in ref["trace"]])
+    with fa.Index.load_striped(d, paths, fa.TIER_FILE) as ix:
+        ix.configure_agent(threads=2, fail_node=bad_node)
+        qd = torch.from_numpy(q).to("cuda:0")
+        ids = torch.empty((len(q), 10), dtype=torch.int32, device="cuda:0")
+        dists = torch.empty((len(q), 10), dtype=torch.int32, device="cuda:0")
+        steps = torch.empty((len(q),), dtype=torch.int32, device="cuda:0")
+        with pytest.raises(fa.AnnError) as e:
+            fa.search(ix, qd, k=10, L=64, delay=1, out=(ids, dists, steps))
+        assert e.value.code == -5
+        g = {"ids": ids.cpu().numpy(), "dists": dists.cpu().numpy().view(np.uint32),
+             "steps": steps.cpu().numpy().view(np.uint32)}
+        assert (g["ids"][hit] == -1).all()
+        assert_same(g, ref, rows=~hit)
+    with pytest.raises(fa.AnnError) as e:      # a stripe too short for its records
+        fa.Index.load_striped(d, paths[:2], fa.TIER_FILE)
+    assert e.value.code == -5
+    with pytest.raises(fa.AnnError) as e:
+        fa.save_records_striped(base, adj, 512, [str(tmp_path / ("x%d" % s)) for s in range(17)])
+    assert e.value.code == -22
