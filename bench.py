@@ -439,6 +439,108 @@ def pq_scale_run(fa, torch, dev, n):
     print(json.dumps({"pq_scale": res}, default=float), flush=True)
 
 
+def f32_file_leg(fa, torch, dev, n, R_values, nq, L, keep_dir=None):
+    """The f32/96 workload with 4 KB record slots in a file: n unit vectors
+    from a 1,024-component mixture (sigma 0.1 before normalisation), nq
+    queries, k = 10, list size L; per degree R, a real graph, the index files
+    (records padded to 4,096 B, read with O_DIRECT by the host agents),
+    relaxed and strict QPS with recall@10, and the per-expansion fetch and
+    compute times T_f, T_c of the strict schedule (the two stages Eq. 6 of
+    the degree selection balances).  With keep_dir, the last degree's index
+    directory, graph and queries stay there for the sampled oracle check
+    (tests/fullsize_f32_parity.py)."""
+    import shutil
+    import tempfile
+
+    import numpy as np
+
+    import synth
+    from paper_2507_10070_amd import degree_selector
+
+    cfg = synth.WORKLOADS["10m-f32-96"]
+    t = time.time()
+    base, q = synth.make_dataset(cfg, n=n, nq=nq)
+    log("f32-file: %d x 96 f32 vectors, %d queries in %.1fs" % (n, nq, time.time() - t))
+    # exact 10th-neighbour distances (fp32 GEMM expansion; recall allows the
+    # expansion's rounding, 1e-5 relative, as the parity tolerance does)
+    torch.backends.cuda.matmul.allow_tf32 = False
+    x = torch.from_numpy(base).to(dev)
+    xx = (x * x).sum(1)
+    kth = []
+    for s0 in range(0, nq, 250):
+        qq = torch.from_numpy(q[s0:s0 + 250]).to(dev)
+        dd = (qq * qq).sum(1, keepdim=True) + xx[None] - 2.0 * (qq @ x.T)
+        kth.append(torch.topk(dd, 10, dim=1, largest=False).values[:, 9].cpu())
+        del dd
+    kth = torch.cat(kth).numpy().astype(np.float64)
+    del x, xx
+    torch.cuda.empty_cache()
+    qd = torch.from_numpy(q).to(dev)
+    khz = fa.device_clock_khz()
+    os.environ["FLASHANN_BUILD_PROGRESS"] = "1"
+    rows = []
+    for R in R_values:
+        t = time.time()
+        adj, entry = synth.build_graph(base, R, 3003, threads=min(16, os.cpu_count() or 1))
+        t_graph = time.time() - t
+        log("f32-file: graph R=%d in %.1fs" % (R, t_graph))
+        last = keep_dir is not None and R == R_values[-1]
+        tmpd = keep_dir if last else tempfile.mkdtemp(
+            prefix="flashann_f32_", dir=os.environ.get("TMPDIR", "/tmp"))
+        try:
+            t = time.time()
+            fa.save_index(tmpd, base, adj, entry, 4096)
+            t_save = time.time() - t
+            if last:
+                np.save(os.path.join(tmpd, "adj.npy"), adj)
+                np.save(os.path.join(tmpd, "queries.npy"), q)
+            del adj
+            log("f32-file: R=%d index files (%.1f GB of records) written in %.1fs"
+                % (R, n * 4096 / 1e9, t_save))
+            with fa.Index.load(tmpd, fa.TIER_FILE) as ix:
+                row = {"R": R, "L": L, "graph_build_s": round(t_graph, 1),
+                       "write_s": round(t_save, 1), "direct_io": ix.info()["direct_io"]}
+                fa.search(ix, qd[:500].contiguous(), k=10, L=L, delay=1)  # warm-up
+                for name, delay in (("relaxed", 1), ("strict", 0)):
+                    p0 = ix.agent_profile()
+                    t = time.perf_counter()
+                    _, dist, steps = fa.search(ix, qd, k=10, L=L, delay=delay)
+                    torch.cuda.synchronize()
+                    el = time.perf_counter() - t
+                    p1 = ix.agent_profile()
+                    dv = dist.cpu().numpy().astype(np.float64)
+                    rec = float(np.minimum((dv <= kth[:, None] * (1 + 1e-5)).sum(1), 10).mean() / 10)
+                    row[name] = {"qps": round(nq / el, 1), "recall@10": round(rec, 4),
+                                 "mean_steps": round(float(steps.cpu().numpy().view(np.uint32).mean()), 2),
+                                 "reads_per_s": round((p1["requests"] - p0["requests"]) / el, 1)}
+                # stage times of Eq. 6 on this graph: strict schedule, stamps,
+                # median of three runs (their spread is the noise the
+                # degree selector's fit allows for)
+                tf, tc = [], []
+                for _ in range(3):
+                    phases = torch.zeros((nq, 2), dtype=torch.int64, device=dev)
+                    _, _, steps = fa.search(ix, qd, k=10, L=L, delay=0, phases=phases)
+                    torch.cuda.synchronize()
+                    ph = phases.cpu().numpy().sum(0).astype(np.float64)
+                    ns = float(steps.cpu().numpy().view(np.uint32).astype(np.int64).sum())
+                    tf.append(ph[0] / ns / khz * 1e3)
+                    tc.append(ph[1] / ns / khz * 1e3)
+                row["T_f_us"] = round(float(np.median(tf)), 3)
+                row["T_c_us"] = round(float(np.median(tc)), 3)
+                row["T_f_spread_us"] = round(float(np.ptp(tf)), 3)
+            rows.append(row)
+            log("f32-file: %s" % row)
+        finally:
+            if not last:
+                shutil.rmtree(tmpd, ignore_errors=True)
+    out = {"workload": "%d x 96 f32 (1,024-component mixture), 4,096 B record slots in a file"
+           % n, "queries": nq, "k": 10, "L": L, "rows": rows}
+    if len(rows) > 1:
+        out["selected_R"], out["fit"] = degree_selector.select_fitted(rows)
+        out["selected_R_raw"] = degree_selector.select(rows)
+    return out
+
+
 def batched_file_leg(fa, torch, dev, n, nq_total):
     """Batched form at scale: n int8 vectors of d = 100 (4,096-component
     mixture), degree-48 graph, 512 B records in a file read with O_DIRECT by
@@ -546,6 +648,17 @@ def main():
     ap.add_argument("--batched-file-n", type=int, default=0,
                     help="also run the batched form at scale: this many int8/100 vectors, "
                          "records in a file (off by default: minutes of graph build)")
+    ap.add_argument("--f32-file-n", type=int, default=0,
+                    help="opt-in: the f32/96 workload with 4 KB record slots in a file at this "
+                         "size (10M = 41 GB of records), one real graph per --f32-R degree")
+    ap.add_argument("--f32-R", type=int, nargs="+", default=[32, 48, 64, 96])
+    ap.add_argument("--f32-L", type=int, default=128)
+    ap.add_argument("--f32-nq", type=int, default=10000)
+    ap.add_argument("--f32-keep", default=None,
+                    help="keep the last degree's index directory here (for the sampled "
+                         "oracle check)")
+    ap.add_argument("--f32-only", action="store_true",
+                    help="run only the f32 file leg and print its JSON")
     ap.add_argument("--no-hbm-tier", action="store_true",
                     help="skip the same search with the records in HBM")
     ap.add_argument("--no-transports", action="store_true",
@@ -583,6 +696,13 @@ def main():
         return
     if args.pq_n:
         pq_scale_run(fa, torch, dev, args.pq_n)
+        return
+    if args.f32_only:
+        if not args.f32_file_n:
+            sys.exit("--f32-only needs --f32-file-n")
+        res = f32_file_leg(fa, torch, dev, args.f32_file_n, args.f32_R, args.f32_nq, args.f32_L,
+                           args.f32_keep)
+        print(json.dumps({"f32_file": res}), flush=True)
         return
     cfg = synth.WORKLOADS["1m-u8-128"]
     n = args.n or cfg.n
@@ -796,6 +916,10 @@ def main():
     batched_file = None
     if args.batched_file_n:
         batched_file = batched_file_leg(fa, torch, dev, args.batched_file_n, args.batched_queries)
+    f32_file = None
+    if args.f32_file_n:
+        f32_file = f32_file_leg(fa, torch, dev, args.f32_file_n, args.f32_R, args.f32_nq,
+                                args.f32_L, args.f32_keep)
 
     # ---- the same index with its records in HBM: the kernel without the host
     # link in the way (where the HBM roofline applies)
@@ -1001,6 +1125,7 @@ def main():
         "schedules": schedules,
         "batched": batched,
         "batched_file": batched_file,
+        "f32_file": f32_file,
         "records_in_hbm": hbm_tier,
         "pq_navigation": pq,
         "transports": transports,
