@@ -127,10 +127,11 @@ def stored_traffic(workload, L):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if (t.get("kernel_hash") != kernel_source_hash() or t.get("workload") != workload
-            or t.get("L") != L):
-        return None
-    return t.get("traffic_bytes_per_launch")
+    h = kernel_source_hash()
+    for e in t.get("entries", [t]):
+        if e.get("kernel_hash") == h and e.get("workload") == workload and e.get("L") == L:
+            return e.get("traffic_bytes_per_launch")
+    return None
 
 
 def serving_leg(fa, ix, queries, kth, budget, L_op):
@@ -806,8 +807,9 @@ def main():
     torch.cuda.synchronize()
     link_peak = 4 * (1 << 30) / (e0.elapsed_time(e1) / 1e3) / 1e9
     del src, dst
-    workload = "1M-u8-128-R64-512B-host-10kq" if (n, nq, tier) == (cfg.n, cfg.nq, fa.TIER_HOST) \
-        else "custom"
+    workload = "custom"
+    if (n, nq) == (cfg.n, cfg.nq):
+        workload = "1M-u8-128-R64-512B-%s-10kq" % ("host" if tier == fa.TIER_HOST else "hbm")
     hbm_ach = hbm_bytes / sec / 1e9
     roofline = {"bound": "hbm", "binding": "host_link" if link_bytes else "hbm",
                 "achieved": round(hbm_ach, 2), "peak": HBM_PEAK_GBS,
