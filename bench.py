@@ -440,7 +440,7 @@ def pq_scale_run(fa, torch, dev, n):
     print(json.dumps({"pq_scale": res}, default=float), flush=True)
 
 
-def f32_file_leg(fa, torch, dev, n, R_values, nq, L, keep_dir=None):
+def f32_file_leg(fa, torch, dev, n, R_values, nq, L, keep_dir=None, tier="file"):
     """The f32/96 workload with 4 KB record slots in a file: n unit vectors
     from a 1,024-component mixture (sigma 0.1 before normalisation), nq
     queries, k = 10, list size L; per degree R, a real graph, the index files
@@ -449,7 +449,8 @@ def f32_file_leg(fa, torch, dev, n, R_values, nq, L, keep_dir=None):
     compute times T_f, T_c of the strict schedule (the two stages Eq. 6 of
     the degree selection balances).  With keep_dir, the last degree's index
     directory, graph and queries stay there for the sampled oracle check
-    (tests/fullsize_f32_parity.py)."""
+    (tests/fullsize_f32_parity.py).  tier "host" or "hbm" keeps the same 4 KB
+    slots in pinned DRAM or in HBM instead (the kernel without the disk)."""
     import shutil
     import tempfile
 
@@ -498,22 +499,38 @@ def f32_file_leg(fa, torch, dev, n, R_values, nq, L, keep_dir=None):
             del adj
             log("f32-file: R=%d index files (%.1f GB of records) written in %.1fs"
                 % (R, n * 4096 / 1e9, t_save))
-            with fa.Index.load(tmpd, fa.TIER_FILE) as ix:
-                row = {"R": R, "L": L, "graph_build_s": round(t_graph, 1),
+            t_tier = {"file": fa.TIER_FILE, "host": fa.TIER_HOST, "hbm": fa.TIER_HBM}[tier]
+            with fa.Index.load(tmpd, t_tier) as ix:
+                row = {"R": R, "L": L, "tier": tier, "graph_build_s": round(t_graph, 1),
                        "write_s": round(t_save, 1), "direct_io": ix.info()["direct_io"]}
                 fa.search(ix, qd[:500].contiguous(), k=10, L=L, delay=1)  # warm-up
                 for name, delay in (("relaxed", 1), ("strict", 0)):
                     p0 = ix.agent_profile()
+                    reps = 1 if tier == "file" else 5
                     t = time.perf_counter()
-                    _, dist, steps = fa.search(ix, qd, k=10, L=L, delay=delay)
+                    for _ in range(reps):
+                        _, dist, steps = fa.search(ix, qd, k=10, L=L, delay=delay)
                     torch.cuda.synchronize()
-                    el = time.perf_counter() - t
+                    el = (time.perf_counter() - t) / reps
                     p1 = ix.agent_profile()
                     dv = dist.cpu().numpy().astype(np.float64)
                     rec = float(np.minimum((dv <= kth[:, None] * (1 + 1e-5)).sum(1), 10).mean() / 10)
                     row[name] = {"qps": round(nq / el, 1), "recall@10": round(rec, 4),
                                  "mean_steps": round(float(steps.cpu().numpy().view(np.uint32).mean()), 2),
-                                 "reads_per_s": round((p1["requests"] - p0["requests"]) / el, 1)}
+                                 "reads_per_s": round((p1["requests"] - p0["requests"]) / el / reps, 1)}
+                # algorithmic bytes of one relaxed launch (the kernel's own
+                # counters): rows scored x row stride from HBM, expansions x
+                # record bytes from the record tier
+                st = torch.zeros(3, dtype=torch.int64, device=dev)
+                fa.search(ix, qd, k=10, L=L, delay=1, stats=st)
+                torch.cuda.synchronize()
+                stv = st.cpu().numpy()
+                info = ix.info()
+                row["nav_bytes_per_launch"] = int(stv[1]) * info["nav_stride"]
+                row["record_bytes_per_launch"] = int(stv[0]) * info["rec_bytes"]
+                sec = nq / row["relaxed"]["qps"]
+                row["relaxed"]["algorithmic_GBps"] = round(
+                    (row["nav_bytes_per_launch"] + row["record_bytes_per_launch"]) / sec / 1e9, 1)
                 # stage times of Eq. 6 on this graph: strict schedule, stamps,
                 # median of three runs (their spread is the noise the
                 # degree selector's fit allows for)
@@ -534,8 +551,8 @@ def f32_file_leg(fa, torch, dev, n, R_values, nq, L, keep_dir=None):
         finally:
             if not last:
                 shutil.rmtree(tmpd, ignore_errors=True)
-    out = {"workload": "%d x 96 f32 (1,024-component mixture), 4,096 B record slots in a file"
-           % n, "queries": nq, "k": 10, "L": L, "rows": rows}
+    out = {"workload": "%d x 96 f32 (1,024-component mixture), 4,096 B record slots, %s tier"
+           % (n, tier), "queries": nq, "k": 10, "L": L, "rows": rows}
     if len(rows) > 1:
         out["selected_R"], out["fit"] = degree_selector.select_fitted(rows)
         out["selected_R_raw"] = degree_selector.select(rows)
@@ -658,6 +675,7 @@ def main():
     ap.add_argument("--f32-keep", default=None,
                     help="keep the last degree's index directory here (for the sampled "
                          "oracle check)")
+    ap.add_argument("--f32-tier", choices=("file", "host", "hbm"), default="file")
     ap.add_argument("--f32-only", action="store_true",
                     help="run only the f32 file leg and print its JSON")
     ap.add_argument("--no-hbm-tier", action="store_true",
@@ -702,7 +720,7 @@ def main():
         if not args.f32_file_n:
             sys.exit("--f32-only needs --f32-file-n")
         res = f32_file_leg(fa, torch, dev, args.f32_file_n, args.f32_R, args.f32_nq, args.f32_L,
-                           args.f32_keep)
+                           args.f32_keep, args.f32_tier)
         print(json.dumps({"f32_file": res}), flush=True)
         return
     cfg = synth.WORKLOADS["1m-u8-128"]
@@ -921,7 +939,7 @@ def main():
     f32_file = None
     if args.f32_file_n:
         f32_file = f32_file_leg(fa, torch, dev, args.f32_file_n, args.f32_R, args.f32_nq,
-                                args.f32_L, args.f32_keep)
+                                args.f32_L, args.f32_keep, args.f32_tier)
 
     # ---- the same index with its records in HBM: the kernel without the host
     # link in the way (where the HBM roofline applies)
