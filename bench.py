@@ -559,6 +559,107 @@ def f32_file_leg(fa, torch, dev, n, R_values, nq, L, keep_dir=None, tier="file")
     return out
 
 
+def serving_file_leg(fa, torch, dev, n, nq=10000, m=2000):
+    """The serving form with records in a file: n u8/128 vectors of the
+    4,096-component mixture, degree-64 graph, 512 B records in a file read
+    with O_DIRECT by the server's own host agents; requests draw k from
+    {10, 100} and L from the swept values with L >= max(k, L_op), L_op the
+    smallest L whose recall@10 reaches 0.95 on a 2,000-query sample.
+    Saturation from an m-query burst, then open-loop Poisson arrivals at
+    0.25, 0.5, 0.75 and 0.9 of it (m queries each), latency from the
+    intended arrival to the result."""
+    import shutil
+    import tempfile
+
+    import numpy as np
+
+    import synth
+
+    cfg = synth.WORKLOADS["100m-u8-128"]
+    t = time.time()
+    base, q = synth.make_dataset(cfg, n=n, nq=nq)
+    log("serving-file: %d x 128 u8 vectors, %d queries in %.1fs" % (n, nq, time.time() - t))
+    kth = ground_truth(base, q, 10, torch, dev)
+    os.environ["FLASHANN_BUILD_PROGRESS"] = "1"
+    t = time.time()
+    adj, entry = synth.build_graph(base, cfg.R, 3000 + cfg.seed_offset,
+                                   threads=min(16, os.cpu_count() or 1))
+    t_graph = time.time() - t
+    log("serving-file: graph R=%d in %.1fs" % (cfg.R, t_graph))
+    tmpd = tempfile.mkdtemp(prefix="flashann_serve_", dir=os.environ.get("TMPDIR", "/tmp"))
+    try:
+        t = time.time()
+        fa.save_index(tmpd, base, adj, entry, cfg.slot)
+        t_save = time.time() - t
+        del adj
+        out = {"workload": "%d x 128 u8 (4,096-component mixture), R=64, 512 B records in a "
+                           "file (O_DIRECT), served by the server's own agents" % n,
+               "graph_build_s": round(t_graph, 1), "write_s": round(t_save, 1)}
+        with fa.Index.load(tmpd, fa.TIER_FILE) as ix:
+            out["direct_io"] = ix.info()["direct_io"]
+            qs = torch.from_numpy(q[:2000]).to(dev)
+            L_op = L_SWEEP[-1]
+            sweep = []
+            for L in L_SWEEP:
+                _, d_, s_ = fa.search(ix, qs, k=10, L=L, delay=1)
+                torch.cuda.synchronize()
+                rec = recall_at(d_.cpu().numpy().view(np.uint32), kth[:2000])
+                sweep.append({"L": L, "recall@10": round(rec, 4)})
+                if rec >= 0.95:
+                    L_op = L
+                    break
+            out["L_op"], out["sweep"] = L_op, sweep
+            log("serving-file: L_op %d (%s)" % (L_op, sweep))
+            rng = np.random.default_rng(29)
+            Lset = [L for L in L_SWEEP if L >= L_op]
+
+            def mix(cnt):
+                ks = rng.choice(np.array([10, 100], np.int32), cnt)
+                return ks, np.array([rng.choice([L for L in Lset if L >= k]) for k in ks],
+                                    np.int32)
+
+            def recall(res):
+                qi = (res["tags"] % nq).astype(np.int64)
+                d10 = res["dists"][:, :10].astype(np.float64)
+                return float((np.minimum((d10 <= kth[qi][:, None]).sum(1), 10) / 10.0).mean())
+
+            with fa.Server(ix, hbm_budget_bytes=256 << 20) as srv:
+                ks, Ls = mix(m)
+                # queries the L sweep did not touch: their records are cold,
+                # as they are for the arrivals that follow
+                idx = 2000 + rng.integers(0, nq - 2000, m)
+                t0 = fa.clock_us()
+                srv.submit_batch(q[idx], ks, Ls, idx.astype(np.uint64))
+                res = srv.drain(m, timeout_s=300)
+                qmax = m / ((res["done_us"].max() - t0) / 1e6)
+                out["saturation_qps"] = round(qmax, 1)
+                out["saturation_recall@10"] = round(recall(res), 4)
+                out["failed_reads"] = int((res["status"] != 0).sum())
+                rates = []
+                for frac in (0.25, 0.5, 0.75, 0.9):
+                    lam = frac * qmax
+                    ks, Ls = mix(m)
+                    idx = 2000 + rng.integers(0, nq - 2000, m)
+                    start = fa.clock_us() + 20000.0
+                    arr = start + np.cumsum(rng.exponential(1e6 / lam, m))
+                    srv.submit_batch(q[idx], ks, Ls, idx.astype(np.uint64), arr)
+                    res = srv.drain(m, timeout_s=300)
+                    lat = (res["done_us"] - res["submit_us"]) / 1e3
+                    rates.append({"offered_qps": round(lam, 1), "queries": int(len(lat)),
+                                  "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
+                                  "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
+                                  "recall@10": round(recall(res), 4),
+                                  "failed_reads": int((res["status"] != 0).sum())})
+                    log("serving-file at %.0f QPS offered: %s" % (lam, rates[-1]))
+                out["rates"] = rates
+            prof = ix.agent_profile()
+            out["agent"] = {"threads": prof["threads"], "async_io": prof["async_io"]}
+    finally:
+        shutil.rmtree(tmpd, ignore_errors=True)
+    log("serving-file: %s" % out)
+    return out
+
+
 def batched_file_leg(fa, torch, dev, n, nq_total):
     """Batched form at scale: n int8 vectors of d = 100 (4,096-component
     mixture), degree-48 graph, 512 B records in a file read with O_DIRECT by
@@ -666,6 +767,11 @@ def main():
     ap.add_argument("--batched-file-n", type=int, default=0,
                     help="also run the batched form at scale: this many int8/100 vectors, "
                          "records in a file (off by default: minutes of graph build)")
+    ap.add_argument("--serving-file-n", type=int, default=0,
+                    help="opt-in: the serving form with records in a file at this size "
+                         "(u8/128, 4,096-component mixture, R=64); with --serving-file-only "
+                         "nothing else runs")
+    ap.add_argument("--serving-file-only", action="store_true")
     ap.add_argument("--f32-file-n", type=int, default=0,
                     help="opt-in: the f32/96 workload with 4 KB record slots in a file at this "
                          "size (10M = 41 GB of records), one real graph per --f32-R degree")
@@ -715,6 +821,12 @@ def main():
         return
     if args.pq_n:
         pq_scale_run(fa, torch, dev, args.pq_n)
+        return
+    if args.serving_file_only:
+        if not args.serving_file_n:
+            sys.exit("--serving-file-only needs --serving-file-n")
+        print(json.dumps({"serving_file": serving_file_leg(fa, torch, dev, args.serving_file_n)}),
+              flush=True)
         return
     if args.f32_only:
         if not args.f32_file_n:
@@ -936,6 +1048,9 @@ def main():
     batched_file = None
     if args.batched_file_n:
         batched_file = batched_file_leg(fa, torch, dev, args.batched_file_n, args.batched_queries)
+    serving_file = None
+    if args.serving_file_n:
+        serving_file = serving_file_leg(fa, torch, dev, args.serving_file_n)
     f32_file = None
     if args.f32_file_n:
         f32_file = f32_file_leg(fa, torch, dev, args.f32_file_n, args.f32_R, args.f32_nq,
@@ -1058,6 +1173,11 @@ def main():
             transports["agent_host"]["poll_backoff"] = {
                 str(pb): measure(ix, qd, op[1], 1, reps, poll_backoff=pb)["qps"] for pb in (4, 32, 128)}
             log("agent transport: %s" % transports["agent_host"])
+            if not args.no_serving:
+                # the server with its own host agents over the same DRAM records
+                transports["agent_host"]["serving"] = serving_burst(
+                    fa, ix, queries, kth, op[1], m=20000, where="records in pinned host DRAM, "
+                    "served through the host agents", transport=fa.TRANSPORT_AGENT)
             kg = timed(op[1], 0, 3, 1, sync_grain=fa.SYNC_KERNEL)
             transports["direct_host"] = {
                 "queries": nq, "L": op[1],
@@ -1146,6 +1266,7 @@ def main():
         "batched": batched,
         "batched_file": batched_file,
         "f32_file": f32_file,
+        "serving_file": serving_file,
         "records_in_hbm": hbm_tier,
         "pq_navigation": pq,
         "transports": transports,
