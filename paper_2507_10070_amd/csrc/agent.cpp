@@ -287,9 +287,10 @@ void Agent::run(int t) {
   Io io;
   if (aio_depth_ > 0) {
     io.depth = aio_depth_;
-    if (sys_io_setup((unsigned)io.depth, &io.ctx) != 0 ||
-        posix_memalign((void **)&io.bufs, 4096, (size_t)io_bytes_ * (size_t)io.depth) != 0) {
-      io.ctx = 0;  // fall back to synchronous reads in this thread
+    if (posix_memalign((void **)&io.bufs, 4096, (size_t)io_bytes_ * (size_t)io.depth) != 0) {
+      io.bufs = nullptr;  // fall back to synchronous reads in this thread
+    } else if (sys_io_setup((unsigned)io.depth, &io.ctx) != 0) {
+      io.ctx = 0;  // likewise (e.g. the system's limit of AIO contexts is reached)
     } else {
       io.cbs.resize((size_t)io.depth);
       io.held.resize((size_t)io.depth);
