@@ -1173,6 +1173,17 @@ def main():
             transports["agent_host"]["poll_backoff"] = {
                 str(pb): measure(ix, qd, op[1], 1, reps, poll_backoff=pb)["qps"] for pb in (4, 32, 128)}
             log("agent transport: %s" % transports["agent_host"])
+            # the relaxed pipeline where fetch latency, not bandwidth, binds:
+            # fewer queries in flight through the agents
+            conc = {}
+            for m in (256, 1024, 4096):
+                qm = qd[:m].contiguous()
+                conc[str(m)] = {name: measure(ix, qm, op[1], delay, max(reps, 3))["qps"]
+                                for name, delay in (("relaxed", 1), ("strict", 0))}
+                conc[str(m)]["relaxed_vs_strict"] = round(conc[str(m)]["relaxed"] /
+                                                          conc[str(m)]["strict"], 3)
+            transports["agent_host"]["concurrency"] = conc
+            log("agent transport by queries in flight: %s" % conc)
             if not args.no_serving:
                 # the server with its own host agents over the same DRAM records
                 transports["agent_host"]["serving"] = serving_burst(
