@@ -38,19 +38,11 @@ T0 = time.time()
 
 
 def ground_truth(base, queries, k, torch, dev):
-    """Exact k-th neighbour distance per query (harness only: a plain fp32 GEMM
-    expansion, exact for u8/i8 data since every partial sum is an integer
-    below 2^24)."""
-    torch.backends.cuda.matmul.allow_tf32 = False
-    x = torch.from_numpy(base).to(dev).float()
-    xx = (x * x).sum(1)
-    out = []
-    for s in range(0, queries.shape[0], 1000):
-        q = torch.from_numpy(queries[s:s + 1000]).to(dev).float()
-        d = (q * q).sum(1, keepdim=True) + xx[None, :] - 2.0 * (q @ x.T)
-        out.append(torch.topk(d, k, dim=1, largest=False).values[:, k - 1].cpu())
-    del x, xx
-    return torch.cat(out).numpy().astype("float64")
+    """Exact k-th neighbour distance per query (paper_2507_10070_amd.recall:
+    a GPU full scan in int32-indexable chunks, spot-checked on the CPU)."""
+    from paper_2507_10070_amd.recall import exact_kth
+
+    return exact_kth(base, queries, k, dev)
 
 
 def recall_at(dists_u32, kth):
@@ -465,18 +457,7 @@ def f32_file_leg(fa, torch, dev, n, R_values, nq, L, keep_dir=None, tier="file")
     log("f32-file: %d x 96 f32 vectors, %d queries in %.1fs" % (n, nq, time.time() - t))
     # exact 10th-neighbour distances (fp32 GEMM expansion; recall allows the
     # expansion's rounding, 1e-5 relative, as the parity tolerance does)
-    torch.backends.cuda.matmul.allow_tf32 = False
-    x = torch.from_numpy(base).to(dev)
-    xx = (x * x).sum(1)
-    kth = []
-    for s0 in range(0, nq, 250):
-        qq = torch.from_numpy(q[s0:s0 + 250]).to(dev)
-        dd = (qq * qq).sum(1, keepdim=True) + xx[None] - 2.0 * (qq @ x.T)
-        kth.append(torch.topk(dd, 10, dim=1, largest=False).values[:, 9].cpu())
-        del dd
-    kth = torch.cat(kth).numpy().astype(np.float64)
-    del x, xx
-    torch.cuda.empty_cache()
+    kth = ground_truth(base, q, 10, torch, dev)
     qd = torch.from_numpy(q).to(dev)
     khz = fa.device_clock_khz()
     os.environ["FLASHANN_BUILD_PROGRESS"] = "1"
@@ -683,18 +664,8 @@ def batched_file_leg(fa, torch, dev, n, nq_total):
     adj, entry = synth.build_graph(base, 48, 3004, threads=min(16, os.cpu_count() or 1))
     t_graph = time.time() - t
     log("batched-file: graph R=48 in %.1fs" % t_graph)
-    # exact 10th-neighbour distance of the first 1,000 queries (fp32 GEMM,
-    # exact for int8 data: every partial sum is an integer below 2^24)
-    x = torch.from_numpy(base).to(dev).float()
-    xx = (x * x).sum(1)
-    kth = []
-    for s0 in range(0, 1000, 50):
-        qq = torch.from_numpy(q[s0:s0 + 50]).to(dev).float()
-        dd = (qq * qq).sum(1, keepdim=True) + xx[None] - 2.0 * (qq @ x.T)
-        kth.append(torch.topk(dd, 10, dim=1, largest=False).values[:, 9].cpu())
-    kth = torch.cat(kth).numpy().astype(np.float64)
-    del x, xx, dd
-    torch.cuda.empty_cache()
+    # exact 10th-neighbour distance of the first 1,000 queries
+    kth = ground_truth(base, q[:1000], 10, torch, dev)
     tmpd = tempfile.mkdtemp(prefix="flashann_batched_", dir=os.environ.get("TMPDIR", "/tmp"))
     try:
         t = time.time()

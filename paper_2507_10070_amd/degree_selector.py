@@ -134,16 +134,9 @@ def validate(R_values, n, d, dtype, components, slot, tier, nq, seed=11,
     base = synth.make_base(n, d, dtype, components, seed)
     q = synth.make_queries(nq, d, dtype, components, seed, seed + 1)
     qd = torch.from_numpy(q).to("cuda:0")
-    torch.backends.cuda.matmul.allow_tf32 = False
-    x = torch.from_numpy(base).to("cuda:0").float()
-    xx = (x * x).sum(1)
-    kth = []
-    for s in range(0, nq, 1000):
-        qq = qd[s:s + 1000].float()
-        dd = (qq * qq).sum(1, keepdim=True) + xx[None] - 2.0 * (qq @ x.T)
-        kth.append(torch.topk(dd, 10, dim=1, largest=False).values[:, 9])
-    kth = torch.cat(kth).cpu().numpy().astype(np.float64)
-    del x, xx
+    from .recall import exact_kth
+
+    kth = exact_kth(base, q, 10, "cuda:0")
     out = []
     for R in R_values:
         t = time.time()
