@@ -1029,28 +1029,53 @@ def main():
 
     # ---- the same index with its records in HBM: the kernel without the host
     # link in the way (where the HBM roofline applies)
+    # Both threads-per-query tiles: one query per wave64 (the keys "strict"
+    # and "relaxed") and two queries per wave ("two_per_wave", at the default
+    # 2^10-slot hash and at 2^9, which lets more queries share a CU's LDS).
     hbm_tier = None
     if tier == fa.TIER_HOST and not args.no_hbm_tier:
         with fa.Index(base, adj, entry, cfg.slot, fa.TIER_HBM) as hix:
-            hbm_tier = {}
-            for name, delay in (("strict", 0), ("relaxed", 1)):
+            def hbm_measure(delay, **kw):
                 st_ = torch.zeros(3, dtype=torch.int64, device=dev)
-                fa.search(hix, qd, k=k, L=op[1], delay=delay, out=out, stream=stream, stats=st_)
+                fa.search(hix, qd, k=k, L=op[1], delay=delay, out=out, stream=stream, stats=st_,
+                          **kw)
                 torch.cuda.synchronize()
                 s_ = st_.cpu().numpy()
                 ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
                 ev[0].record(stream)
                 for _ in range(5):
-                    fa.search(hix, qd, k=k, L=op[1], delay=delay, out=out, stream=stream)
+                    fa.search(hix, qd, k=k, L=op[1], delay=delay, out=out, stream=stream, **kw)
                 ev[1].record(stream)
                 torch.cuda.synchronize()
                 ms_h = ev[0].elapsed_time(ev[1]) / 5
                 byt = int(s_[0]) * info["rec_bytes"] + int(s_[1]) * info["nav_stride"] + \
                     nq * (cfg.d + 8 * k + 4)
-                hbm_tier[name] = {"qps": round(nq / (ms_h / 1e3), 1), "ms_per_step": round(ms_h, 4),
-                                  "algorithmic_GBps": round(byt / (ms_h / 1e3) / 1e9, 1),
-                                  "hbm_frac": round(byt / (ms_h / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+                return {"qps": round(nq / (ms_h / 1e3), 1), "ms_per_step": round(ms_h, 4),
+                        "algorithmic_GBps": round(byt / (ms_h / 1e3) / 1e9, 1),
+                        "hbm_frac": round(byt / (ms_h / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+            hbm_tier = {}
+            for name, delay in (("strict", 0), ("relaxed", 1)):
+                hbm_tier[name] = hbm_measure(delay)
+            pair = {}
+            for name, delay in (("strict", 0), ("relaxed", 1)):
+                for hb in (10, 9):
+                    pair["%s_hash%d" % (name, hb)] = hbm_measure(delay, query_lanes=32,
+                                                                 hash_bits=hb)
+            hbm_tier["two_per_wave"] = pair
             log("records in HBM: %s" % hbm_tier)
+        # the same choice with records in host DRAM (bound by the host link)
+        t0 = time.time()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        fa.search(ix, qd, k=k, L=op[1], delay=1, out=out, stream=stream, query_lanes=32)
+        ev[0].record(stream)
+        for _ in range(5):
+            fa.search(ix, qd, k=k, L=op[1], delay=1, out=out, stream=stream, query_lanes=32)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        hbm_tier["two_per_wave_host_relaxed_qps"] = round(nq / (ev[0].elapsed_time(ev[1]) / 5e3), 1)
+        log("two queries per wave, records in DRAM: %.0f QPS (%.1fs)"
+            % (hbm_tier["two_per_wave_host_relaxed_qps"], time.time() - t0))
 
     # ---- compressed navigation: PQ codes in HBM, exact re-rank from records,
     # on this workload (isotropic clusters: the hard case for PQ) and on one of

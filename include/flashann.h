@@ -110,8 +110,9 @@ typedef struct {
   int32_t beam_width;      /* W, nodes selected per iteration (default 1);
                               (delay + 1) * W <= 8 nodes may be in flight */
   int32_t hash_bits;       /* log2 of the per-query visited-hash slots (0 = default 10) */
-  int32_t waves_per_block; /* queries per workgroup, 1..4 (0 = 4, or 2 or 1 when
-                              the LDS of a workgroup cannot hold 4 queries) */
+  int32_t waves_per_block; /* waves per workgroup, 1..4 (0 = 4, or 2 or 1 when
+                              the LDS of a workgroup cannot hold its queries);
+                              one query per wave unless query_lanes = 32 */
   unsigned long long *d_stats; /* optional device counters, 3 x u64, accumulated:
                                   [0] expansions [1] neighbour distances computed
                                   [2] records whose own vector disagreed with the
@@ -170,6 +171,15 @@ typedef struct {
                               completion word, in units of 1024 GPU cycles
                               (about 0.43 us); pauses double from one unit up
                               to it.  0 = 32.  Results do not depend on it. */
+  int32_t query_lanes;     /* lanes per query, the threads-per-query tile: 0 or 64
+                              = one query per wave64; 32 = two queries per wave,
+                              one per half (the paper runs one query per 32-lane
+                              warp, section 4.2).  32 needs the direct transport,
+                              full-precision navigation, sync_grain 0, delay 0 or
+                              1 with beam_width 1, and records of at most 512 B,
+                              else ANN_ENOTSUP.  waves_per_block stays a count of
+                              waves, so a workgroup then holds 2 x that many
+                              queries.  Results do not depend on it. */
 } ann_search_opts;
 
 /*

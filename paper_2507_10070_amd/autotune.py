@@ -2,9 +2,11 @@
 
 Two kinds of parameters are tuned on a representative batch:
 
-* tiles that do not change results -- queries per workgroup, visited-hash
-  size, persistent or one-shot grid, with compressed navigation the way PQ
-  distances are formed (`pq_scoring`: LDS table or centroids from the cache),
+* tiles that do not change results -- threads per query (a whole wave64,
+  or half a wave with two queries per wave), waves per workgroup,
+  visited-hash size, persistent or one-shot grid, with compressed navigation
+  the way PQ distances are formed (`pq_scoring`: LDS table or centroids from
+  the cache),
   and for uneven batches (per-query L) the processing order: as given, or
   longest list first (`longest_first`);
 * schedule parameters that change the search path but keep it valid -- the
@@ -32,9 +34,10 @@ SPACE = {
     "waves_per_block": (1, 2, 4),
     "hash_bits": (8, 9, 10, 11, 12),
     "persistent": (False, True),
+    "query_lanes": (64, 32),
 }
 DEFAULT = {"delay": 1, "beam_width": 1, "waves_per_block": 4, "hash_bits": 10,
-           "persistent": False}
+           "persistent": False, "query_lanes": 64}
 SEMANTIC = ("delay", "beam_width")
 MAX_IN_FLIGHT = 8   # (delay + 1) * beam_width limit of the kernels
 
@@ -56,7 +59,10 @@ def cache_key(index, L: int, nq: int, uneven: bool = False, pq: bool = False) ->
 
 
 def valid(params) -> bool:
-    return (params.get("delay", 1) + 1) * params.get("beam_width", 1) <= MAX_IN_FLIGHT
+    delay, beam = params.get("delay", 1), params.get("beam_width", 1)
+    if params.get("query_lanes", 64) == 32 and (delay > 1 or beam != 1):
+        return False  # two queries per wave: strict or one-step-stale, beam 1
+    return (delay + 1) * beam <= MAX_IN_FLIGHT
 
 
 def search_kwargs(params, extra):
@@ -117,6 +123,10 @@ def tune(index, queries, k, L, space=None, reps=3, cache_path=DEFAULT_CACHE, use
         space.setdefault("longest_first", (False, True))
     if extra.get("navigation", 0) == 1 and extra.get("pq_scoring") is None:
         space.setdefault("pq_scoring", (2, 1))  # cache, table
+    # two queries per wave: direct transport (not a file tier), full navigation
+    if extra.get("navigation", 0) == 1 or extra.get("transport", 0) == 2 or \
+            index.info()["tier"] == 2:
+        space.pop("query_lanes", None)
     cur = dict(start or DEFAULT)
     cur = {n: cur.get(n, DEFAULT.get(n, space[n][0])) for n in space}
     if score is None:  # no quality measure: results-neutral parameters only

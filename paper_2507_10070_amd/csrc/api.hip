@@ -786,6 +786,15 @@ int prepare_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, 
     return fail(ANN_EINVAL, "poll_backoff=%d not in [0, 1024]", o.poll_backoff);
   if (o.navigation == ANN_NAV_PQ && o.sync_grain)
     return fail(ANN_ENOTSUP, "kernel-grained search scores with the full-precision copy only");
+  if (o.query_lanes == 0) o.query_lanes = 64;
+  if (o.query_lanes != 64 && o.query_lanes != 32)
+    return fail(ANN_EINVAL, "query_lanes=%d must be 32 or 64", o.query_lanes);
+  if (o.query_lanes == 32 &&
+      (transport != ANN_TRANSPORT_DIRECT || o.navigation != ANN_NAV_FULL || o.sync_grain ||
+       o.delay > 1 || o.beam_width != 1 || ix->rec_chunks > 32))
+    return fail(ANN_ENOTSUP, "two queries per wave (query_lanes 32) run the direct transport, "
+                             "full-precision navigation, delay 0 or 1 with beam 1 and records "
+                             "of at most 512 B (these are %d B)", 16 * ix->rec_chunks);
   if (nq > 0x7FFFFFFFll) return fail(ANN_EINVAL, "nq=%lld too large", (long long)nq);
   *o_out = o;
   *transport_out = transport;
@@ -830,16 +839,18 @@ int prepare_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, 
   a.beam = o.beam_width;
   a.pslots = std::max(2, (o.delay + 1) * o.beam_width);
   if (o.navigation == ANN_NAV_PQ) set_pq_args(ix, o.pq_scoring, &a);
+  a.qlanes = o.query_lanes;
   a.lds_per_wave = fa::search_lds_bytes(a.Lcap, a.nav_stride, a.hash_bits,
-                                        a.pq_m ? a.k : 0, a.pq_floats);
-  // the default queries per workgroup shrinks to what the LDS holds
+                                        a.pq_m ? a.k : 0, a.pq_floats, a.qlanes);
+  // the default waves per workgroup shrinks to what the LDS holds
+  const int per_wave = 64 / a.qlanes;
   while (auto_wpb && o.waves_per_block > 1 &&
-         (int64_t)a.lds_per_wave * o.waves_per_block > 160 * 1024)
+         (int64_t)a.lds_per_wave * o.waves_per_block * per_wave > 160 * 1024)
     o.waves_per_block /= 2;
   *o_out = o;
-  if ((int64_t)a.lds_per_wave * o.waves_per_block > 160 * 1024)
+  if ((int64_t)a.lds_per_wave * o.waves_per_block * per_wave > 160 * 1024)
     return fail(ANN_EINVAL, "LDS need %u B per query x %d exceeds 160 KiB", a.lds_per_wave,
-                o.waves_per_block);
+                o.waves_per_block * per_wave);
   return ANN_OK;
 }
 

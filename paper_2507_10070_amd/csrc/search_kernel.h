@@ -73,13 +73,17 @@ struct SearchArgs {
   const uint8_t *pq_codes;
   const float *pq_cb;
   int32_t pq_m, pq_dsub, pq_direct, pq_floats;
-  uint32_t lds_per_wave;
+  uint32_t lds_per_wave;   // LDS bytes of one query's region
+  int32_t qlanes;          // lanes per query: 64 (one query per wave) or 32
+                           // (two per wave: TR_DIRECT, NAV_FULL, strict or
+                           // one-step-stale, records of at most 512 B)
 };
 
-// Per-wave LDS bytes; kcap (result capacity, the batch k) and pq_floats
-// (SearchArgs::pq_floats) only for compressed navigation.
+// LDS bytes of one query's region; kcap (result capacity, the batch k) and
+// pq_floats (SearchArgs::pq_floats) only for compressed navigation; qlanes
+// the lanes per query.
 uint32_t search_lds_bytes(int Lcap, int nav_stride, int hash_bits, int kcap = 0,
-                          int pq_floats = 0);
+                          int pq_floats = 0, int qlanes = 64);
 // Continuous-batching server: a persistent kernel whose waves take queries
 // from a ring in device memory as the host publishes them.
 //   ring entry (entry_bytes): u32 seq+1, u32 result slot, u32 k | L << 16,

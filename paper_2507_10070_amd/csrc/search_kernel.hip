@@ -77,6 +77,49 @@ __device__ __forceinline__ uint32_t mbcnt(uint64_t mask) {
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// ------------------------------------------------------- lanes per query
+// A query runs on a group of G lanes: the whole wave (G = 64), or one half of
+// it (G = 32, two queries per wave).  The forms below are the wave-wide
+// operations restricted to the caller's group.  A mask holds the group's
+// lanes in bits [0, G); a broadcast reads a lane of the caller's own group.
+// With G = 64 each is the plain wave operation; with G = 32 the halves may
+// follow different paths (each half's control flow depends on its own query
+// only), so broadcasts go through ds_bpermute, which takes a per-lane source.
+template <int G>
+__device__ __forceinline__ int group_lane() {
+  return G == 64 ? lane_id() : (lane_id() & (G - 1));
+}
+template <int G>
+__device__ __forceinline__ uint64_t gballot(bool p) {
+  const uint64_t b = __ballot(p);
+  if constexpr (G == 64) return b;
+  else return (lane_id() & 32) ? (b >> 32) : (b & 0xFFFFFFFFull);
+}
+// Set bits of a group mask below the caller's group lane.
+template <int G>
+__device__ __forceinline__ uint32_t gmbcnt(uint64_t m) {
+  if constexpr (G == 64) return mbcnt(m);
+  else return (lane_id() & 32) ? __builtin_amdgcn_mbcnt_hi((uint32_t)m, 0u)
+                               : __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u);
+}
+// Value of x in group lane j (j the same for every lane of the group).
+template <int G>
+__device__ __forceinline__ uint32_t gread(uint32_t x, int j) {
+  if constexpr (G == 64) return (uint32_t)__builtin_amdgcn_readlane((int)x, j);
+  else return (uint32_t)__builtin_amdgcn_ds_bpermute(((lane_id() & 32) + j) << 2, (int)x);
+}
+template <int G>
+__device__ __forceinline__ uint64_t gread64(uint64_t x, int j) {
+  if constexpr (G == 64) return readlane64(x, j);
+  else return ((uint64_t)gread<G>((uint32_t)(x >> 32), j) << 32) | gread<G>((uint32_t)x, j);
+}
+// Value of x in the group's first lane (every lane of the group active).
+template <int G>
+__device__ __forceinline__ uint32_t gfirst(uint32_t x) {
+  if constexpr (G == 64) return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+  else return gread<G>(x, 0);
+}
+
 // Number of entries of a[0..cnt) whose masked key is below `key`.
 __device__ __forceinline__ int lower_bound(const uint64_t *a, int cnt, uint64_t key) {
   int lo = 0, hi = cnt;
@@ -203,16 +246,18 @@ struct WaveLds {
                    // are read from the cache instead, the query as d floats
 };
 
+// One query's LDS region; G lanes per query (batches of G neighbours, a
+// record of at most 16 G bytes).
 __host__ __device__ inline LdsLayout lds_layout(int Lcap, int nav_stride, int hash_bits,
-                                                int kcap, int pq_floats) {
+                                                int kcap, int pq_floats, int G = 64) {
   LdsLayout o;
   uint32_t off = 0;
   o.cand = off; off += 8u * (uint32_t)Lcap;
-  o.nk = off; off += 8u * 64u;
-  o.stage = off; off += 16u * 64u;
+  o.nk = off; off += 8u * (uint32_t)G;
+  o.stage = off; off += 16u * (uint32_t)G;
   o.qbuf = off; off += (uint32_t)nav_stride;
-  o.ids = off; off += 4u * 64u;
-  o.dsc = off; off += 4u * 64u;
+  o.ids = off; off += 4u * (uint32_t)G;
+  o.dsc = off; off += 4u * (uint32_t)G;
   o.hash = off; off += 4u << hash_bits;
   o.fifo = off; off += 8u * (uint32_t)kMaxPipe;
   o.res = off; off += 8u * (uint32_t)kcap;
@@ -267,14 +312,14 @@ __device__ __forceinline__ float query_elem(const uint8_t *qbuf, int i) {
   return ((const float *)qbuf)[i];
 }
 
-template <int DT, int CPL, int TR, int NAV = NAV_FULL>
+template <int DT, int CPL, int TR, int NAV = NAV_FULL, int G = 64>
 struct Searcher {
   using D = Dist<DT>;
   using Acc = typename D::Acc;
 
   const SearchArgs &A;
   WaveLds S;
-  int lane, sub, grp;
+  int lane, sub, grp;   // lane within the query's group; 8-lane row group
   uint4 qv[CPL];
   Acc qq;
   int nc;
@@ -290,11 +335,11 @@ struct Searcher {
   __device__ __forceinline__ Searcher(const SearchArgs &args, uint8_t *base, int64_t query,
                                       const QueryIO &qio)
       : A(args), io(qio), qi(query) {
-    lane = lane_id();
+    lane = group_lane<G>();
     sub = lane & 7;
     grp = lane >> 3;
     const LdsLayout lay = lds_layout(A.Lcap, A.nav_stride, A.hash_bits,
-                                     NAV == NAV_PQ ? A.k : 0, NAV == NAV_PQ ? A.pq_floats : 0);
+                                     NAV == NAV_PQ ? A.k : 0, NAV == NAV_PQ ? A.pq_floats : 0, G);
     S.cand = (uint64_t *)(base + lay.cand);
     S.nk = (uint64_t *)(base + lay.nk);
     S.stage = (uint4 *)(base + lay.stage);
@@ -310,13 +355,13 @@ struct Searcher {
     // query -> LDS, zero padded to the row stride
     const uint8_t *q = io.q;
     if (io.coherent) {
-      for (int w = lane; w < A.nav_stride / 4; w += 64)
+      for (int w = lane; w < A.nav_stride / 4; w += G)
         ((uint32_t *)S.qbuf)[w] = __hip_atomic_load((const uint32_t *)q + w, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_SYSTEM);
     } else {
-      for (int b = lane; b < A.nav_stride; b += 64) S.qbuf[b] = b < A.qbytes ? q[b] : (uint8_t)0;
+      for (int b = lane; b < A.nav_stride; b += G) S.qbuf[b] = b < A.qbytes ? q[b] : (uint8_t)0;
     }
-    for (int s = lane; s < (1 << A.hash_bits); s += 64) S.hash[s] = kEmpty;
+    for (int s = lane; s < (1 << A.hash_bits); s += G) S.hash[s] = kEmpty;
     __builtin_amdgcn_wave_barrier();
     Acc a = Acc(0);
 #pragma unroll
@@ -328,13 +373,13 @@ struct Searcher {
     nres = 0;
     if (NAV == NAV_PQ && A.pq_direct) {
       // centroids read from the cache per scored code: the query as floats
-      for (int i = lane; i < A.pq_m * A.pq_dsub; i += 64) S.tab[i] = query_elem<DT>(S.qbuf, i);
+      for (int i = lane; i < A.pq_m * A.pq_dsub; i += G) S.tab[i] = query_elem<DT>(S.qbuf, i);
       __builtin_amdgcn_wave_barrier();
     } else if (NAV == NAV_PQ) {
       // distance table: entry m*256 + c is the squared distance of query
       // subspace m to centroid c (fmaf over its dimensions in order)
       const int ds = A.pq_dsub;
-      for (int e = lane; e < A.pq_m * kPqKsub; e += 64) {
+      for (int e = lane; e < A.pq_m * kPqKsub; e += G) {
         const int q0 = (e >> 8) * ds;
         const float *c = A.pq_cb + (int64_t)e * ds;
         float acc = 0.0f;
@@ -405,19 +450,19 @@ struct Searcher {
     else return c1.w;
   }
 
-  // Centroid loads of subspaces [GI*G, GI*G + G), d/M = DS in {4, 8},
-  // G = 32 / DS (8 x 16 B per lane); every index a compile-time constant.
+  // Centroid loads of subspaces [GI*SG, GI*SG + SG), d/M = DS in {4, 8},
+  // SG = 32 / DS (8 x 16 B per lane); every index a compile-time constant.
   template <int DS, int GI>
   __device__ __forceinline__ void pq_load(const uint4 c0, const uint4 c1,
                                           float4 (&v)[32 / DS][DS / 4]) const {
-    constexpr int G = 32 / DS;
+    constexpr int SG = 32 / DS;
 #pragma unroll
-    for (int u = 0; u < G; u++) {
-      const int m = GI * G + u;
+    for (int u = 0; u < SG; u++) {
+      const int m = GI * SG + u;
       const int mm = m < A.pq_m ? m : A.pq_m - 1;  // past pq_m: a valid row, unused
       uint32_t w;
-      if ((u >> 2) == 0) w = code_word<(GI * G) / 4>(c0, c1);
-      else w = code_word<(GI * G) / 4 + ((G - 1) >> 2)>(c0, c1);
+      if ((u >> 2) == 0) w = code_word<(GI * SG) / 4>(c0, c1);
+      else w = code_word<(GI * SG) / 4 + ((SG - 1) >> 2)>(c0, c1);
       const uint32_t c = (w >> (8 * (m & 3))) & 0xFFu;
       const float4 *cc = (const float4 *)(A.pq_cb + ((int64_t)mm * kPqKsub + c) * DS);
 #pragma unroll
@@ -425,14 +470,14 @@ struct Searcher {
     }
   }
 
-  // s += the sub-distances of subspaces [GI*G, GI*G + G) in subspace order.
+  // s += the sub-distances of subspaces [GI*SG, GI*SG + SG) in subspace order.
   template <int DS, int GI>
   __device__ __forceinline__ float pq_add(const float4 (&v)[32 / DS][DS / 4], float s) const {
-    constexpr int G = 32 / DS;
+    constexpr int SG = 32 / DS;
 #pragma unroll
-    for (int u = 0; u < G; u++) {
-      if (GI * G + u < A.pq_m) {
-        const float4 *q = (const float4 *)(S.tab + (GI * G + u) * DS);
+    for (int u = 0; u < SG; u++) {
+      if (GI * SG + u < A.pq_m) {
+        const float4 *q = (const float4 *)(S.tab + (GI * SG + u) * DS);
         float acc = 0.0f, t;
 #pragma unroll
         for (int h = 0; h < DS / 4; h++) {
@@ -453,10 +498,10 @@ struct Searcher {
   template <int DS, int GI>
   __device__ __forceinline__ float pq_pipe(const uint4 c0, const uint4 c1, float s,
                                            const float4 (&cur)[32 / DS][DS / 4]) const {
-    constexpr int G = 32 / DS;
-    if constexpr ((GI + 1) * G < kPqMaxM) {
-      if ((GI + 1) * G < A.pq_m) {
-        float4 nxt[G][DS / 4];
+    constexpr int SG = 32 / DS;
+    if constexpr ((GI + 1) * SG < kPqMaxM) {
+      if ((GI + 1) * SG < A.pq_m) {
+        float4 nxt[SG][DS / 4];
         pq_load<DS, GI + 1>(c0, c1, nxt);
         s = pq_add<DS, GI>(cur, s);
         return pq_pipe<DS, GI + 1>(c0, c1, s, nxt);
@@ -524,10 +569,10 @@ struct Searcher {
   // guarantees termination regardless.
   __device__ __forceinline__ uint64_t select() {
     if ((int64_t)steps >= A.n || failed) return kNoKey;
-    for (int base = 0; base < nc; base += 64) {
+    for (int base = 0; base < nc; base += G) {
       const int i = base + lane;
       const bool un = i < nc && !((uint32_t)S.cand[i] & kFlag);
-      const uint64_t b = __ballot(un);
+      const uint64_t b = gballot<G>(un);
       if (b) {
         const int idx = base + __ffsll((unsigned long long)b) - 1;
         const uint64_t key = S.cand[idx];
@@ -613,7 +658,7 @@ struct Searcher {
         nap = nap < A.poll_nap ? nap * 2 : A.poll_nap;
       }
     }
-    c = (uint32_t)__builtin_amdgcn_readfirstlane((int)c);
+    c = gfirst<G>(c);
     if (c == kTimedOut || (c & kCplErr)) {
       failed = true;
       if (lane == 0 && io.status)
@@ -643,7 +688,7 @@ struct Searcher {
     return true;
   }
 
-  // Neighbours [b0, b0+64) of the staged record: visited filter and
+  // Neighbours [b0, b0+G) of the staged record: visited filter and
   // compaction.  Returns the number of new ids (written to S.ids).
   __device__ __forceinline__ int filter(int b0) {
     const int j = b0 + lane;
@@ -651,19 +696,20 @@ struct Searcher {
     if (j < A.R) x = ((const int32_t *)((const uint8_t *)S.stage + A.ids_off))[j];
     bool fresh = false;
     if (x >= 0 && (int64_t)x < A.n) fresh = hash_insert(S.hash, A.hash_bits, (uint32_t)x);
-    const uint64_t m = __ballot(fresh);
-    if (fresh) S.ids[mbcnt(m)] = (uint32_t)x;
+    const uint64_t m = gballot<G>(fresh);
+    if (fresh) S.ids[gmbcnt<G>(m)] = (uint32_t)x;
     __builtin_amdgcn_wave_barrier();
     return __popcll((unsigned long long)m);
   }
 
-  // Gather + distances of rows [p0, p0 + 8*PB) of S.ids[0..m): 8 rows per
-  // pass, 8 lanes per row, the loads of all PB passes issued before the
-  // first reduction.  Rows past m re-read row 0 so that no load sits under a
+  // Gather + distances of rows [p0, p0 + RPP*PB) of S.ids[0..m): RPP = G/8
+  // rows per pass, 8 lanes per row, the loads of all PB passes issued before
+  // the first reduction.  Rows past m re-read row 0 so that no load sits under a
   // branch.  WITH_FETCH issues the record fetch of `fid` into `frec` right
   // after the gathers, in straight-line code, so the compiler's wait before
   // each pass leaves that fetch in flight.
   static constexpr int PB = (8 / CPL) > 0 ? (8 / CPL) : 1;
+  static constexpr int RPP = G / 8;
 
   template <bool WITH_FETCH>
   __device__ __forceinline__ void gather_block(int m, int p0, uint32_t fid, bool freal,
@@ -671,7 +717,7 @@ struct Searcher {
     uint4 r[PB][CPL];
 #pragma unroll
     for (int pb = 0; pb < PB; pb++) {
-      const int row = p0 + 8 * pb + grp;
+      const int row = p0 + RPP * pb + grp;
       const uint8_t *p = A.nav + (int64_t)S.ids[row < m ? row : 0] * A.nav_stride;
 #pragma unroll
       for (int c = 0; c < CPL; c++) r[pb][c] = *(const uint4 *)(p + 16 * (sub + 8 * c));
@@ -679,7 +725,7 @@ struct Searcher {
     if (WITH_FETCH) frec = issue(fid, freal);
 #pragma unroll
     for (int pb = 0; pb < PB; pb++) {
-      const int row = p0 + 8 * pb + grp;
+      const int row = p0 + RPP * pb + grp;
       Acc a = Acc(0);
 #pragma unroll
       for (int c = 0; c < CPL; c++) a = D::partial(qv[c], r[pb][c], a);
@@ -719,7 +765,7 @@ struct Searcher {
       const bool dup = r < nc && kmask(S.cand[r]) == key;
       if (dup || r >= L) key = kNoKey;
     }
-    uint64_t live = __ballot(key != kNoKey);
+    uint64_t live = gballot<G>(key != kNoKey);
     if (live == 0) return;
     int cnt, below;
     for (;;) {
@@ -727,7 +773,7 @@ struct Searcher {
       cnt = __popcll((unsigned long long)live);
       __builtin_amdgcn_wave_barrier();
       if (key != kNoKey) {
-        const uint32_t p = mbcnt(live);
+        const uint32_t p = gmbcnt<G>(live);
         S.nk[p] = key;
         S.ids[p] = (uint32_t)r;
       }
@@ -744,16 +790,16 @@ struct Searcher {
         dupl |= (kj == key) && (j < lane);
       }
       dupl = dupl && lane < cnt;
-      const uint64_t drop = __ballot(dupl);
+      const uint64_t drop = gballot<G>(dupl);
       if (drop == 0) break;
       if (dupl) key = kNoKey;
-      live = __ballot(key != kNoKey);
+      live = gballot<G>(key != kNoKey);
     }
     // old entries move right by the number of smaller new keys; walk chunks
     // from the top so that no unread entry is overwritten
-    const int nchunks = (nc + 63) >> 6;
+    const int nchunks = (nc + G - 1) / G;
     for (int t = nchunks - 1; t >= 0; t--) {
-      const int i = 64 * t + lane;
+      const int i = G * t + lane;
       uint64_t e = 0;
       int pos = L;
       if (i < nc) {
@@ -772,38 +818,62 @@ struct Searcher {
     __builtin_amdgcn_wave_barrier();
   }
 
-  // merge() for lists of at most 64 entries: the list is held one entry per
-  // lane, so every comparison is a register compare and a ballot.  The new
-  // keys are visited in lane order; key j is dropped if it equals a list entry
-  // or ranks at L or beyond, else it survives (and later equal keys are
-  // dropped).  A survivor lands at (list entries below it) + (survivors below
-  // it); a list entry moves right by the survivors below it.
-  __device__ __forceinline__ void merge_small(int m) {
-    const uint64_t cf = lane < nc ? S.cand[lane] : kNoKey;  // entry with its flag
-    const uint64_t c = lane < nc ? kmask(cf) : kNoKey;
+  // merge() for lists of at most E * G entries: the list is held in registers,
+  // entry i in group lane i % G of register i / G, so every comparison is a
+  // register compare and a ballot.  The new keys are visited in lane order;
+  // key j is dropped if it equals a list entry or ranks at L or beyond, else
+  // it survives (and later equal keys are dropped).  A survivor lands at
+  // (list entries below it) + (survivors below it); a list entry moves right
+  // by the survivors below it.
+  template <int E>
+  __device__ __forceinline__ void merge_reg(int m) {
+    uint64_t cf[E], c[E];  // entries with their flags; masked keys
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+      const int i = G * e + lane;
+      cf[e] = i < nc ? S.cand[i] : kNoKey;
+      c[e] = i < nc ? kmask(cf[e]) : kNoKey;
+    }
     uint64_t key = kNoKey;
     if (lane < m) key = ((uint64_t)S.dsc[lane] << 32) | S.ids[lane];
-    if (nc >= L && key >= readlane64(c, L - 1)) key = kNoKey;
-    uint64_t todo = __ballot(key != kNoKey);
+    if (nc >= L) {
+      uint64_t last = c[0];
+#pragma unroll
+      for (int e = 1; e < E; e++) last = (L - 1) / G == e ? c[e] : last;
+      if (key >= gread64<G>(last, (L - 1) % G)) key = kNoKey;
+    }
+    uint64_t todo = gballot<G>(key != kNoKey);
     if (todo == 0) return;
-    int shift = 0, below = 0, r = 0;
+    int shift[E], below = 0, r = 0;
+#pragma unroll
+    for (int e = 0; e < E; e++) shift[e] = 0;
     uint64_t taken = 0;
     while (todo) {
       const int j = __ffsll((unsigned long long)todo) - 1;
       todo &= todo - 1;
-      const uint64_t kj = readlane64(key, j);
-      if (__ballot(c == kj) != 0) continue;                 // already listed
-      const int rj = __popcll((unsigned long long)__ballot(c < kj));
+      const uint64_t kj = gread64<G>(key, j);
+      bool listed = false;
+#pragma unroll
+      for (int e = 0; e < E; e++) listed |= c[e] == kj;
+      if (gballot<G>(listed) != 0) continue;                // already listed
+      int rj = 0;
+#pragma unroll
+      for (int e = 0; e < E; e++) rj += __popcll((unsigned long long)gballot<G>(c[e] < kj));
       if (rj >= L) continue;                                 // beyond the first L
-      todo &= ~__ballot(key == kj);                          // later equal keys
+      todo &= ~gballot<G>(key == kj);                        // later equal keys
       taken |= 1ull << j;
       if (lane == j) r = rj;
-      shift += kj < c ? 1 : 0;
+#pragma unroll
+      for (int e = 0; e < E; e++) shift[e] += kj < c[e] ? 1 : 0;
       below += kj < key ? 1 : 0;
     }
     const bool surv = (taken >> lane) & 1ull;
     __builtin_amdgcn_wave_barrier();
-    if (lane < nc && lane + shift < L) S.cand[lane + shift] = cf;
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+      const int i = G * e + lane;
+      if (i < nc && i + shift[e] < L) S.cand[i + shift[e]] = cf[e];
+    }
     if (surv && r + below < L) S.cand[r + below] = key;
     const int added = __popcll((unsigned long long)taken);
     nc = nc + added < L ? nc + added : L;
@@ -840,8 +910,7 @@ struct Searcher {
         a = D::partial(qv[c], r, a);
       }
     }
-    const uint32_t dist =
-        (uint32_t)__builtin_amdgcn_readfirstlane((int)D::finish(qq, group8_sum(a)));
+    const uint32_t dist = gfirst<G>(D::finish(qq, group8_sum(a)));
     res_insert(((uint64_t)dist << 32) | ((uint32_t)key & ~kFlag));
   }
 
@@ -851,16 +920,16 @@ struct Searcher {
     if (nres >= k && key >= S.res[k - 1]) return;
     int pos = 0;
     bool dup = false;
-    for (int b = 0; b < nres; b += 64) {
+    for (int b = 0; b < nres; b += G) {
       const int i = b + lane;
       const uint64_t e = i < nres ? S.res[i] : kNoKey;
-      pos += __popcll((unsigned long long)__ballot(e < key));
-      dup |= __ballot(e == key) != 0;
+      pos += __popcll((unsigned long long)gballot<G>(e < key));
+      dup |= gballot<G>(e == key) != 0;
     }
     if (dup) return;
     const int top = nres < k ? nres : k - 1;  // entries [pos, top) move to [pos+1, top+1)
-    for (int t = (top - 1) >> 6; t >= 0 && 64 * t + 63 >= pos; t--) {
-      const int i = 64 * t + lane;
+    for (int t = (top - 1) / G; t >= 0 && G * t + G - 1 >= pos; t--) {
+      const int i = G * t + lane;
       const bool mv = i >= pos && i < top;
       uint64_t e = 0;
       if (mv) e = S.res[i];
@@ -874,21 +943,22 @@ struct Searcher {
   }
 
   // Gather blocks the caller scores before finish_batch: NAV_FULL one block
-  // of 8 * PB rows, NAV_PQ the whole batch.
-  static constexpr int kFirst = NAV == NAV_PQ ? 64 : 8 * PB;
+  // of RPP * PB rows, NAV_PQ the whole batch.
+  static constexpr int kFirst = NAV == NAV_PQ ? G : RPP * PB;
 
-  // Score and merge neighbours [b0, b0 + 64) of the staged record, starting
-  // at gather block p_start (earlier blocks were done by the caller).
+  // Score and merge the m new neighbours of one filtered batch, starting at
+  // gather block p_start (earlier blocks were done by the caller).
   __device__ __forceinline__ void finish_batch(int m, int p_start) {
     uint4 unused;
     if (NAV == NAV_PQ) {
       if (p_start == 0) gather_pq<false>(m, 0u, false, unused);
     } else {
-      for (int p0 = p_start; p0 < m; p0 += 8 * PB) gather_block<false>(m, p0, 0u, false, unused);
+      for (int p0 = p_start; p0 < m; p0 += RPP * PB) gather_block<false>(m, p0, 0u, false, unused);
     }
     __builtin_amdgcn_wave_barrier();
     rows += (uint32_t)m;
-    if (L <= 64) merge_small(m);
+    if (L <= G) merge_reg<1>(m);
+    else if (G == 32 && L <= 64) merge_reg<2>(m);
     else merge(m);
   }
 
@@ -918,7 +988,7 @@ struct Searcher {
     } else if (RELAXED) {
       frec = issue(fid, freal);
     }
-    for (int b0 = 64; b0 < A.R; b0 += 64) {
+    for (int b0 = G; b0 < A.R; b0 += G) {
       const int mb = filter(b0);
       if (mb > 0) finish_batch(mb, 0);
     }
@@ -927,7 +997,7 @@ struct Searcher {
   __device__ __forceinline__ void finish_query() {
     const uint64_t *out = NAV == NAV_PQ ? S.res : S.cand;
     const int nout = NAV == NAV_PQ ? nres : nc;
-    for (int j = lane; j < io.width; j += 64) {
+    for (int j = lane; j < io.width; j += G) {
       int32_t id = -1;
       uint32_t dist = DT == DT_F32 ? 0x7F800000u : 0xFFFFFFFFu;
       if (j < nout && j < k && !failed) {
@@ -967,11 +1037,11 @@ struct Searcher {
 // in-flight record registers have static names; a slot whose id word holds
 // kNoKey is an empty pipeline slot.
 // One query, start to finish, in the wave's LDS region.
-template <int DT, int CPL, int DELAY, int TR, int NAV = NAV_FULL>
+template <int DT, int CPL, int DELAY, int TR, int NAV = NAV_FULL, int G = 64>
 __device__ __forceinline__ void run_query(const SearchArgs &A, uint8_t *lds, int64_t qi,
                                           const QueryIO &io) {
   const unsigned long long t_start = A.times ? __builtin_amdgcn_s_memrealtime() : 0ull;
-  Searcher<DT, CPL, TR, NAV> s(A, lds, qi, io);
+  Searcher<DT, CPL, TR, NAV, G> s(A, lds, qi, io);
   s.init_entry();
   if (DELAY == SCHED_GENERIC) {
     // Any staleness delta and beam width W (section 4.1.2, with W nodes taken
@@ -1081,63 +1151,79 @@ __device__ __forceinline__ void run_query(const SearchArgs &A, uint8_t *lds, int
   }
 }
 
-template <int DT, int CPL, int DELAY, int TR, bool PERSIST, int NAV>
+// G lanes per query: each block of 64 * waves_per_block threads runs
+// 64 / G queries per wave, query region r = threadIdx.x / G of the block's LDS.
+template <int DT, int CPL, int DELAY, int TR, bool PERSIST, int NAV, int G>
 __global__ void __launch_bounds__(256) search_kernel(SearchArgs A) {
   extern __shared__ __align__(16) uint8_t smem[];
-  const int wave = threadIdx.x >> 6;
-  uint8_t *lds = smem + (size_t)wave * A.lds_per_wave;
+  const int region = threadIdx.x / G;
+  uint8_t *lds = smem + (size_t)region * A.lds_per_wave;
   if (!PERSIST) {
-    const int64_t qi = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    const int64_t qi = (int64_t)blockIdx.x * (blockDim.x / G) + region;
     if (qi >= A.nq) return;
-    run_query<DT, CPL, DELAY, TR, NAV>(A, lds, qi, batch_io(A, qi));
+    run_query<DT, CPL, DELAY, TR, NAV, G>(A, lds, qi, batch_io(A, qi));
     return;
   }
   // Persistent: take queries from the work counter until none is left; every
-  // wave leaves once the counter has passed nq.
+  // group leaves once the counter has passed nq (the two halves of a wave
+  // take their queries independently).
   for (;;) {
     uint32_t t = 0;
-    if (lane_id() == 0) t = atomicAdd(A.work, 1u);
-    t = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
+    if (group_lane<G>() == 0) t = atomicAdd(A.work, 1u);
+    t = gfirst<G>(t);
     if ((int64_t)t >= A.nq) break;
     const int64_t qi = A.order ? (int64_t)A.order[t] : (int64_t)t;
     if (qi < 0 || qi >= A.nq) continue;  // not a permutation entry: skipped
-    run_query<DT, CPL, DELAY, TR, NAV>(A, lds, qi, batch_io(A, qi));
+    run_query<DT, CPL, DELAY, TR, NAV, G>(A, lds, qi, batch_io(A, qi));
     __builtin_amdgcn_wave_barrier();
   }
 }
 
-template <int DT, int CPL, int DELAY, int TR, int NAV>
+template <int DT, int CPL, int DELAY, int TR, int NAV, int G>
 static hipError_t launch_t(const SearchArgs &a, int waves_per_block, bool persistent,
                            hipStream_t st) {
-  const size_t lds = (size_t)a.lds_per_wave * waves_per_block;
+  const int per_block = waves_per_block * (64 / G);  // queries per block
+  const size_t lds = (size_t)a.lds_per_wave * per_block;
   const int threads = 64 * waves_per_block;
   if (!persistent) {
-    const int64_t blocks = (a.nq + waves_per_block - 1) / waves_per_block;
-    hipLaunchKernelGGL((search_kernel<DT, CPL, DELAY, TR, false, NAV>), dim3((unsigned)blocks),
+    const int64_t blocks = (a.nq + per_block - 1) / per_block;
+    hipLaunchKernelGGL((search_kernel<DT, CPL, DELAY, TR, false, NAV, G>), dim3((unsigned)blocks),
                        dim3(threads), lds, st, a);
     return hipGetLastError();
   }
   int per_cu = 0, dev = 0, cus = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per_cu, (const void *)search_kernel<DT, CPL, DELAY, TR, true, NAV>, threads, lds);
+      &per_cu, (const void *)search_kernel<DT, CPL, DELAY, TR, true, NAV, G>, threads, lds);
   if (e != hipSuccess) return e;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
   if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
     return e;
   int64_t blocks = (int64_t)(per_cu > 0 ? per_cu : 1) * cus;
-  const int64_t need = (a.nq + waves_per_block - 1) / waves_per_block;
+  const int64_t need = (a.nq + per_block - 1) / per_block;
   if (blocks > need) blocks = need;
-  hipLaunchKernelGGL((search_kernel<DT, CPL, DELAY, TR, true, NAV>), dim3((unsigned)blocks),
+  hipLaunchKernelGGL((search_kernel<DT, CPL, DELAY, TR, true, NAV, G>), dim3((unsigned)blocks),
                      dim3(threads), lds, st, a);
   return hipGetLastError();
 }
 
+// Two queries per wave (a.qlanes == 32) are built for the direct transport,
+// full-precision navigation and the strict and one-step-stale schedules;
+// the host validates the rest (records of at most 512 B).
 template <int DT, int CPL, int TR, int NAV>
 static hipError_t launch_d(const SearchArgs &a, int wpb, bool pers, hipStream_t st) {
   if (a.delay < 0 || a.beam < 1 || (a.delay + 1) * a.beam > kMaxPipe) return hipErrorInvalidValue;
-  if (a.beam == 1 && a.delay == 0) return launch_t<DT, CPL, SCHED_STRICT, TR, NAV>(a, wpb, pers, st);
-  if (a.beam == 1 && a.delay == 1) return launch_t<DT, CPL, SCHED_RELAXED, TR, NAV>(a, wpb, pers, st);
-  return launch_t<DT, CPL, SCHED_GENERIC, TR, NAV>(a, wpb, pers, st);
+  if (a.qlanes == 32) {
+    if constexpr (TR == TR_DIRECT && NAV == NAV_FULL) {
+      if (a.rec_chunks > 32 || a.beam != 1 || a.delay > 1) return hipErrorInvalidValue;
+      if (a.delay == 0) return launch_t<DT, CPL, SCHED_STRICT, TR, NAV, 32>(a, wpb, pers, st);
+      return launch_t<DT, CPL, SCHED_RELAXED, TR, NAV, 32>(a, wpb, pers, st);
+    }
+    return hipErrorInvalidValue;
+  }
+  if (a.qlanes != 0 && a.qlanes != 64) return hipErrorInvalidValue;
+  if (a.beam == 1 && a.delay == 0) return launch_t<DT, CPL, SCHED_STRICT, TR, NAV, 64>(a, wpb, pers, st);
+  if (a.beam == 1 && a.delay == 1) return launch_t<DT, CPL, SCHED_RELAXED, TR, NAV, 64>(a, wpb, pers, st);
+  return launch_t<DT, CPL, SCHED_GENERIC, TR, NAV, 64>(a, wpb, pers, st);
 }
 
 template <int DT, int CPL, int NAV>
@@ -1367,8 +1453,9 @@ hipError_t launch_lockstep(const SearchArgs &a, uint32_t *ctl, int dtype, int tr
   }
 }
 
-uint32_t search_lds_bytes(int Lcap, int nav_stride, int hash_bits, int kcap, int pq_floats) {
-  return lds_layout(Lcap, nav_stride, hash_bits, kcap, pq_floats).bytes;
+uint32_t search_lds_bytes(int Lcap, int nav_stride, int hash_bits, int kcap, int pq_floats,
+                          int qlanes) {
+  return lds_layout(Lcap, nav_stride, hash_bits, kcap, pq_floats, qlanes).bytes;
 }
 
 // The batch and server kernels of each element type and navigation mode are

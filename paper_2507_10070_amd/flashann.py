@@ -50,7 +50,7 @@ class SearchOptions(ctypes.Structure):
                 ("d_k", ctypes.c_void_p), ("d_order", ctypes.c_void_p),
                 ("persistent", ctypes.c_int32), ("sync_grain", ctypes.c_int32),
                 ("navigation", ctypes.c_int32), ("pq_scoring", ctypes.c_int32),
-                ("poll_backoff", ctypes.c_int32)]
+                ("poll_backoff", ctypes.c_int32), ("query_lanes", ctypes.c_int32)]
 
 
 class IndexInfo(ctypes.Structure):
@@ -351,7 +351,7 @@ def _check_buffer(name, t, dtypes, numel, dev):
 def _prepare(index, queries, k, L, R, delay, beam_width, hash_bits, waves_per_block, stats,
              trace, times, phases, transport, spin_limit, L_per_query, k_per_query, order,
              persistent, out, sync_grain=0, navigation=NAV_FULL, pq_scoring=PQ_AUTO,
-             poll_backoff=0):
+             poll_backoff=0, query_lanes=0):
     import torch
 
     if queries.dim() != 2 or queries.shape[1] != index.d:
@@ -393,7 +393,7 @@ def _prepare(index, queries, k, L, R, delay, beam_width, hash_bits, waves_per_bl
                          trace.shape[1] if trace is not None else 0, _ptr(times), _ptr(phases),
                          transport, spin_limit, _ptr(L_per_query), _ptr(k_per_query), _ptr(order),
                          1 if persistent else 0, int(sync_grain), int(navigation),
-                         int(pq_scoring), int(poll_backoff))
+                         int(pq_scoring), int(poll_backoff), int(query_lanes))
     return nq, ids, dists, steps, opts
 
 
@@ -402,7 +402,8 @@ def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
            trace=None, times=None, phases=None, transport: int = TRANSPORT_AUTO,
            spin_limit: int = 0, L_per_query=None, k_per_query=None, order=None,
            persistent: bool = False, stream=None, out=None, sync_grain: int = SYNC_QUERY,
-           navigation: int = NAV_FULL, pq_scoring: int = PQ_AUTO, poll_backoff: int = 0):
+           navigation: int = NAV_FULL, pq_scoring: int = PQ_AUTO, poll_backoff: int = 0,
+           query_lanes: int = 0):
     """ann_search on torch CUDA tensors.
 
     queries: [nq, d] device tensor of the index dtype (uint8/int8/float32).
@@ -419,6 +420,9 @@ def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
     list; results re-ranked by exact distance from the records).
     pq_scoring: PQ_AUTO, PQ_TABLE (per-query LDS table) or PQ_CACHE
     (centroids from the cache); the results are the same.
+    query_lanes: 0/64 (one query per wave64) or 32 (two queries per wave;
+    direct transport, full navigation, delay <= 1, beam 1, records <= 512 B);
+    the results are the same.
     Returns (ids int32 [nq,k], dists [nq,k] int32-viewed uint32 or float32,
     steps int32-viewed uint32 [nq]), all on the device.
     """
@@ -428,7 +432,7 @@ def search(index: Index, queries, k: int, L: int, R: int = 0, delay: int = 1,
                                            waves_per_block, stats, trace, times, phases,
                                            transport, spin_limit, L_per_query, k_per_query,
                                            order, persistent, out, sync_grain, navigation,
-                                           pq_scoring, poll_backoff)
+                                           pq_scoring, poll_backoff, query_lanes)
     st = stream if stream is not None else torch.cuda.current_stream(queries.device)
     _check(load_library().ann_search(index.handle, queries.data_ptr(), nq, k, L, R,
                                      ctypes.byref(opts), ids.data_ptr(), dists.data_ptr(),
@@ -473,11 +477,12 @@ class SearchGraph:
     def __init__(self, index: Index, queries, k: int, L: int, stream, R: int = 0,
                  delay: int = 1, hash_bits: int = 0, waves_per_block: int = 0,
                  L_per_query=None, k_per_query=None, order=None, out=None, beam_width: int = 1,
-                 navigation: int = NAV_FULL):
+                 navigation: int = NAV_FULL, query_lanes: int = 0):
         nq, ids, dists, steps, opts = _prepare(index, queries, k, L, R, delay, beam_width, hash_bits,
                                                waves_per_block, None, None, None, None,
                                                TRANSPORT_DIRECT, 0, L_per_query, k_per_query,
-                                               order, True, out, 0, navigation)
+                                               order, True, out, 0, navigation,
+                                               query_lanes=query_lanes)
         self._keep = (index, queries, ids, dists, steps, L_per_query, k_per_query, order)
         self.ids, self.dists, self.steps = ids, dists, steps
         self.stream = stream

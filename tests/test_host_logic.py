@@ -52,6 +52,17 @@ def test_autotune_in_flight_limit():
     assert autotune.valid({"delay": 7, "beam_width": 1})
 
 
+def test_autotune_two_queries_per_wave_schedules():
+    """Half-wave queries run the strict and one-step-stale schedules with
+    beam width 1 only; the tuner never proposes another combination."""
+    for delay in (0, 1):
+        assert autotune.valid({"delay": delay, "beam_width": 1, "query_lanes": 32})
+    for delay, beam in ((2, 1), (0, 2), (1, 2), (3, 1)):
+        assert not autotune.valid({"delay": delay, "beam_width": beam, "query_lanes": 32})
+        assert autotune.valid({"delay": delay, "beam_width": beam, "query_lanes": 64})
+    assert autotune.DEFAULT["query_lanes"] == 64 and 32 in autotune.SPACE["query_lanes"]
+
+
 def test_bench_refuses_more_than_one_gpu():
     """The benchmark runs on one GPU; any other count exits with a message
     before touching a device."""
