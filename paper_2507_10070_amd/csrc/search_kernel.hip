@@ -2,13 +2,14 @@
 // strict or with the dependency-relaxed fetch schedule of FlashANNS
 // (arXiv 2507.10070, section 4.1).
 //
-// One wavefront (64 lanes) runs one query.  Per wave, LDS holds
+// One wavefront (64 lanes) runs one query, or each half of a wave runs one
+// (G = 32 lanes per query; see "lanes per query" below).  Per query, LDS holds
 //   cand[Lcap]  the candidate list: u64 keys (distance << 32 | id), sorted
 //               ascending; bit 31 of the id word is the "expanded" flag
-//   nk[64]      new keys of the batch being merged, compacted
-//   stage[64]   the record being processed (16 B per lane)
+//   nk[G]       new keys of the batch being merged, compacted
+//   stage[G]    the record being processed (16 B per lane)
 //   qbuf        the query, zero-padded to the navigation row stride
-//   ids/dsc     per-batch neighbour ids and their distances
+//   ids/dsc     per-batch (G neighbours) ids and their distances
 //   hash[H]     visited set: exact ids in buckets of 8 slots, may forget
 //   fifo[8]     generic schedule: keys of the nodes in flight, oldest first
 // Forgetting is harmless: a forgotten node is either still in the list (its
