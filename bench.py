@@ -712,6 +712,66 @@ def batched_file_leg(fa, torch, dev, n, nq_total):
     return out
 
 
+def hot_cache_leg(fa, torch, dev, ix, qd, cfg, k, op, info, out, stream,
+                  fractions=(0.01, 0.05, 0.1, 0.2), n_train=10000):
+    """Headline index and queries with a hot-record cache in HBM.  The hot
+    set is the most-expanded nodes of n_train training queries drawn from the
+    same mixture with another seed (never the timed queries).  Per cache size:
+    the share of the timed queries' expansions it serves (from traces), QPS of
+    both schedules at their operating L, and the record bytes per second that
+    still cross the host link."""
+    import numpy as np
+
+    import synth
+
+    n = info["n"]
+    qt = synth.gmm.make_queries(n_train, cfg.d, cfg.dtype, cfg.components, 1000 + cfg.seed_offset,
+                                7000 + cfg.seed_offset)
+    qtd = torch.from_numpy(qt).to(dev)
+    cap = 512
+
+    def visits(queries, L):
+        tr = torch.full((queries.shape[0], cap), -1, dtype=torch.int32, device=dev)
+        fa.search(ix, queries, k=k, L=L, delay=1, trace=tr, stream=stream)
+        torch.cuda.synchronize()
+        t = tr[tr >= 0].long()
+        return torch.bincount(t, minlength=n)
+
+    hot_order = torch.argsort(visits(qtd, op[1]), descending=True, stable=True).cpu().numpy()
+    test_visits = visits(qd, op[1])
+    total = float(test_visits.sum().item())
+
+    def timed(L, delay, reps=10):
+        fa.search(ix, qd, k=k, L=L, delay=delay, out=out, stream=stream)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        for _ in range(reps):
+            fa.search(ix, qd, k=k, L=L, delay=delay, out=out, stream=stream)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps
+
+    rows = []
+    try:
+        for f in fractions:
+            m = int(f * n)
+            ids = hot_order[:m]
+            ix.set_record_cache(ids)
+            covered = float(test_visits[torch.from_numpy(ids).to(dev).long()].sum().item()) / total
+            ms = {d: timed(op[d], d) for d in (0, 1)}
+            link = (1.0 - covered) * total * info["rec_bytes"]
+            rows.append({"fraction": f, "records": m,
+                         "cache_MB": round(m * info["slot_bytes"] / 1e6, 1),
+                         "expansions_served": round(covered, 4),
+                         "relaxed_qps": round(qd.shape[0] / (ms[1] / 1e3), 1),
+                         "strict_qps": round(qd.shape[0] / (ms[0] / 1e3), 1),
+                         "link_GBps_relaxed": round(link / (ms[1] / 1e3) / 1e9, 2)})
+    finally:
+        ix.set_record_cache([])
+    return {"hot_set": "most-expanded nodes of %d training queries (another seed), relaxed, L=%d"
+                       % (n_train, op[1]), "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -755,6 +815,8 @@ def main():
     ap.add_argument("--f32-tier", choices=("file", "host", "hbm"), default="file")
     ap.add_argument("--f32-only", action="store_true",
                     help="run only the f32 file leg and print its JSON")
+    ap.add_argument("--no-hot-cache", action="store_true",
+                    help="skip the hot-record cache measurement")
     ap.add_argument("--no-hbm-tier", action="store_true",
                     help="skip the same search with the records in HBM")
     ap.add_argument("--no-transports", action="store_true",
@@ -1077,6 +1139,13 @@ def main():
         log("two queries per wave, records in DRAM: %.0f QPS (%.1fs)"
             % (hbm_tier["two_per_wave_host_relaxed_qps"], time.time() - t0))
 
+    # ---- hot-record cache: the most-visited records of a separate sample of
+    # training queries copied into HBM, the rest read over the host link
+    hot_cache = None
+    if tier == fa.TIER_HOST and not args.no_hot_cache:
+        hot_cache = hot_cache_leg(fa, torch, dev, ix, qd, cfg, k, op, info, out, stream)
+        log("hot-record cache: %s" % hot_cache)
+
     # ---- compressed navigation: PQ codes in HBM, exact re-rank from records,
     # on this workload (isotropic clusters: the hard case for PQ) and on one of
     # intrinsic dimension 16 (the structure of real descriptors)
@@ -1275,6 +1344,7 @@ def main():
         "f32_file": f32_file,
         "serving_file": serving_file,
         "records_in_hbm": hbm_tier,
+        "hot_record_cache": hot_cache,
         "pq_navigation": pq,
         "transports": transports,
         "serving": serving,

@@ -99,6 +99,8 @@ typedef struct {
   int32_t pq_m;       /* PQ subspaces of the codes in HBM (0 = none) */
   int32_t nav_full;   /* 1 while the full-precision navigation copy is held */
   int32_t stripes;    /* ANN_TIER_FILE: record files the records are striped over */
+  int32_t reserved;
+  int64_t cached_records; /* records copied into the hot-record cache (0 = none) */
 } ann_index_info;
 
 /* Search options; a NULL pointer means {delay = 1, beam_width = 1, defaults}. */
@@ -311,6 +313,28 @@ int ann_agent_profile_get(const ann_index *ix, ann_agent_profile *out);
  * server is open on the index), ANN_ENOMEM.
  */
 int ann_index_set_pq(ann_index *ix, const float *codebooks, int32_t m, int32_t flags);
+
+/*
+ * ann_index_set_record_cache -- hot-record cache in device memory.  Not a
+ * step of the paper's method (its records live in storage, section 4.2) but
+ * a layout for GPUs whose memory can hold a share of the records: searches
+ * through the direct transport read the records of the cached nodes from
+ * device memory and every other record from host memory, as before.  The
+ * bytes read are the same, so results do not change; only the host-link
+ * traffic does.  A node's cache slot is looked up (one 4 B load from a
+ * device map of n entries) when the node is selected for expansion.
+ *   ids    host, count distinct node ids in [0, n) whose records are copied
+ *          (typically the most-visited nodes of a sample of queries); copied,
+ *          caller keeps ownership
+ *   count  0 releases the cache
+ * Device memory: count x slot_bytes + 4 n bytes.  ANN_TIER_HOST indexes only
+ * (HBM-tier records are all in device memory).  Batch searches through the
+ * direct transport use it; the agent transport and the server do not.  Synchronous: waits for all device work before replacing
+ * the cache; graphs captured before the call must not be replayed after it.
+ * Errors: ANN_EINVAL (ids out of range or repeated, count > n), ANN_ENOTSUP
+ * (other tiers), ANN_EBUSY (a server is open on the index), ANN_ENOMEM.
+ */
+int ann_index_set_record_cache(ann_index *ix, const int32_t *ids, int64_t count);
 /* ann_index_pq_codes -- copy the PQ codes to `host_codes` (caller-owned,
  * n x m bytes, row i = the m subspace codes of node i).  Synchronous.
  * Errors: ANN_EINVAL (NULL, or no codes). */

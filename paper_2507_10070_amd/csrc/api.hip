@@ -62,6 +62,10 @@ struct ann_index {
   uint8_t *pq_codes = nullptr;      // device, n x kPqStride
   float *pq_cb = nullptr;           // device, pq_m x 256 x (d / pq_m)
   int32_t pq_m = 0;
+  // hot-record cache (direct transport, host tier)
+  uint8_t *d_cache = nullptr;       // device, cache_count x slot: record copies
+  int32_t *d_cache_map = nullptr;   // device, n: cache slot of each node or -1
+  int64_t cache_count = 0;
   std::atomic<int> servers{0};      // servers open on this index
 };
 
@@ -117,6 +121,8 @@ void release(ann_index *ix) {
   if (ix->nav) (void)hipFree(ix->nav);
   if (ix->pq_codes) (void)hipFree(ix->pq_codes);
   if (ix->pq_cb) (void)hipFree(ix->pq_cb);
+  if (ix->d_cache) (void)hipFree(ix->d_cache);
+  if (ix->d_cache_map) (void)hipFree(ix->d_cache_map);
   if (ix->rec_hbm) (void)hipFree(ix->rec_hbm);
   if (ix->rec_host) (void)hipHostFree(ix->rec_host);
   for (const int f : ix->fds)
@@ -601,6 +607,8 @@ int ann_index_info_get(const ann_index *ix, ann_index_info *out) {
   out->stripes = ix->tier == ANN_TIER_FILE ? (int32_t)ix->fds.size() : 0;
   out->pq_m = ix->pq_m;
   out->nav_full = ix->nav ? 1 : 0;
+  out->reserved = 0;
+  out->cached_records = ix->cache_count;
   return ANN_OK;
 }
 
@@ -839,6 +847,10 @@ int prepare_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, 
   a.beam = o.beam_width;
   a.pslots = std::max(2, (o.delay + 1) * o.beam_width);
   if (o.navigation == ANN_NAV_PQ) set_pq_args(ix, o.pq_scoring, &a);
+  if (transport == ANN_TRANSPORT_DIRECT && ix->cache_count > 0) {
+    a.cache = ix->d_cache;
+    a.cache_map = ix->d_cache_map;
+  }
   a.qlanes = o.query_lanes;
   a.lds_per_wave = fa::search_lds_bytes(a.Lcap, a.nav_stride, a.hash_bits,
                                         a.pq_m ? a.k : 0, a.pq_floats, a.qlanes);
@@ -1146,6 +1158,7 @@ int ann_internal_server_args(ann_index *ix, int32_t k_max, int32_t L_max, int32_
   a.entry = ix->entry;
   a.hash_bits = hash_bits;
   if (navigation == ANN_NAV_PQ) set_pq_args(ix, pq_scoring, &a);
+  // the server does not read the hot-record cache (a.cache stays null)
   a.lds_per_wave = fa::search_lds_bytes(a.Lcap, a.nav_stride, a.hash_bits, a.pq_m ? a.k : 0,
                                         a.pq_floats);
   *dtype = ix->dtype;
@@ -1161,6 +1174,66 @@ int ann_device_clock_khz(int32_t *khz) {
   if (e == hipSuccess) e = hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, dev);
   if (e != hipSuccess) return hip_fail(e, "wall clock rate");
   *khz = v;
+  return ANN_OK;
+}
+
+int ann_index_set_record_cache(ann_index *ix, const int32_t *ids, int64_t count) {
+  if (!ix) return fail(ANN_EINVAL, "index is NULL");
+  if (count < 0 || count > ix->n)
+    return fail(ANN_EINVAL, "count=%lld not in [0, n=%lld]", (long long)count, (long long)ix->n);
+  if (count > 0 && !ids) return fail(ANN_EINVAL, "ids is NULL");
+  if (count > 0 && ix->tier != ANN_TIER_HOST)
+    return fail(ANN_ENOTSUP, "the record cache serves records in host memory (ANN_TIER_HOST)");
+  if (ix->servers.load() > 0)
+    return fail(ANN_EBUSY, "a server is open on this index; close it first");
+  std::vector<int32_t> map;
+  if (count > 0) {
+    map.assign((size_t)ix->n, -1);
+    for (int64_t i = 0; i < count; i++) {
+      const int32_t v = ids[i];
+      if (v < 0 || v >= ix->n) return fail(ANN_EINVAL, "ids[%lld]=%d not in [0, n)", (long long)i, v);
+      if (map[(size_t)v] >= 0) return fail(ANN_EINVAL, "ids[%lld]=%d listed twice", (long long)i, v);
+      map[(size_t)v] = (int32_t)i;
+    }
+  }
+  // searches still reading the cache being replaced finish first
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "record cache");
+  if (ix->d_cache) (void)hipFree(ix->d_cache);
+  if (ix->d_cache_map) (void)hipFree(ix->d_cache_map);
+  ix->hbm_bytes -= ix->cache_count * ix->slot + (ix->cache_count ? ix->n * 4 : 0);
+  ix->d_cache = nullptr;
+  ix->d_cache_map = nullptr;
+  ix->cache_count = 0;
+  if (count == 0) return ANN_OK;
+  const size_t cbytes = (size_t)count * (size_t)ix->slot;
+  e = hipMalloc(&ix->d_cache, cbytes);
+  if (e == hipSuccess) e = hipMalloc(&ix->d_cache_map, sizeof(int32_t) * (size_t)ix->n);
+  if (e == hipSuccess)
+    e = hipMemcpy(ix->d_cache_map, map.data(), sizeof(int32_t) * (size_t)ix->n,
+                  hipMemcpyHostToDevice);
+  // the copies are gathered in host chunks of up to 64 MiB
+  const int64_t per = std::max<int64_t>(1, (64ll << 20) / ix->slot);
+  std::vector<uint8_t> buf;
+  for (int64_t b = 0; e == hipSuccess && b < count; b += per) {
+    const int64_t m = std::min<int64_t>(per, count - b);
+    buf.resize((size_t)m * (size_t)ix->slot);
+    for (int64_t i = 0; i < m; i++)
+      std::memcpy(buf.data() + (size_t)i * ix->slot,
+                  (const uint8_t *)ix->rec_host + (size_t)ids[b + i] * (size_t)ix->slot,
+                  (size_t)ix->slot);
+    e = hipMemcpy(ix->d_cache + (size_t)b * ix->slot, buf.data(), (size_t)m * ix->slot,
+                  hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    if (ix->d_cache) (void)hipFree(ix->d_cache);
+    if (ix->d_cache_map) (void)hipFree(ix->d_cache_map);
+    ix->d_cache = nullptr;
+    ix->d_cache_map = nullptr;
+    return hip_fail(e, "record cache");
+  }
+  ix->cache_count = count;
+  ix->hbm_bytes += count * ix->slot + ix->n * 4;
   return ANN_OK;
 }
 

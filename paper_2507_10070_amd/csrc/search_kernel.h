@@ -73,6 +73,10 @@ struct SearchArgs {
   const uint8_t *pq_codes;
   const float *pq_cb;
   int32_t pq_m, pq_dsub, pq_direct, pq_floats;
+  // optional hot-record cache (TR_DIRECT): cache_map[v] = slot of node v's
+  // record copy in `cache` (device memory, slot-strided), or -1
+  const uint8_t *cache;
+  const int32_t *cache_map;
   uint32_t lds_per_wave;   // LDS bytes of one query's region
   int32_t qlanes;          // lanes per query: 64 (one query per wave) or 32
                            // (two per wave: TR_DIRECT, NAV_FULL, strict or

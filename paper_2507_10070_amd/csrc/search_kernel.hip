@@ -331,6 +331,8 @@ struct Searcher {
   uint32_t steps, rows, mismatches;
   uint32_t seq;   // TR_AGENT: last request number of this query
   bool failed;    // TR_AGENT: a record read failed or timed out
+  uint32_t sel_id;   // hot-record cache: the last selected node and its cache
+  int32_t sel_slot;  // slot, looked up at selection (kEmpty / -1: none)
   unsigned long long t_fetch, t_comp;  // summed phase ticks (strict, optional)
 
   __device__ __forceinline__ Searcher(const SearchArgs &args, uint8_t *base, int64_t query,
@@ -396,6 +398,8 @@ struct Searcher {
     // request numbers continue per line when lines outlive queries
     seq = A.line_seq ? A.line_seq[io.line] : 0u;
     failed = false;
+    sel_id = kEmpty;
+    sel_slot = -1;
     t_fetch = t_comp = 0;
   }
 
@@ -577,6 +581,12 @@ struct Searcher {
       if (b) {
         const int idx = base + __ffsll((unsigned long long)b) - 1;
         const uint64_t key = S.cand[idx];
+        if (TR == TR_DIRECT && A.cache_map) {
+          // the cache slot of the node whose record is fetched next, loaded
+          // now so that the fetch does not wait for it behind the gathers
+          sel_id = (uint32_t)key & ~kFlag;
+          sel_slot = A.cache_map[sel_id];
+        }
         __builtin_amdgcn_wave_barrier();
         if (lane == 0) {
           S.cand[idx] = key | kFlag;
@@ -593,10 +603,19 @@ struct Searcher {
 
   // Record fetch: lane i loads bytes [16i, 16i+16) of the record.  Lanes past
   // the record re-read its last chunk, so the load has no branch around it
-  // and the compiler can count it exactly when it places its waits.
+  // and the compiler can count it exactly when it places its waits.  With a
+  // hot-record cache, a cached node's copy in device memory is read instead
+  // (same bytes); the slot of the last selected node was looked up at
+  // selection, any other node's (the generic schedule's FIFO) is looked up here.
   __device__ __forceinline__ uint4 fetch(uint32_t v) const {
     const int c = lane < A.rec_chunks ? lane : A.rec_chunks - 1;
-    return *(const uint4 *)(A.records + (int64_t)v * A.slot + 16 * c);
+    const uint8_t *rec = A.records + (int64_t)v * A.slot;
+    if (A.cache_map) {
+      int32_t s = sel_slot;
+      if (v != sel_id) s = A.cache_map[v];
+      if (s >= 0) rec = A.cache + (int64_t)s * A.slot;
+    }
+    return *(const uint4 *)(rec + 16 * c);
   }
 
   // Request slot of request number s (TR_AGENT).  At most pslots requests of

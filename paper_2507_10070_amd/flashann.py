@@ -31,7 +31,7 @@ EXPORTED = ["ann_index_create", "ann_index_info_get", "ann_search", "ann_index_f
             "ann_server_poll", "ann_server_stats_get", "ann_server_close", "ann_clock_us",
             "ann_server_submit_batch", "ann_server_poll_into", "ann_index_set_pq",
             "ann_index_pq_codes", "ann_search_noalloc", "ann_save_records_striped",
-            "ann_load_records_striped", "ann_agent_profile_get"]
+            "ann_load_records_striped", "ann_agent_profile_get", "ann_index_set_record_cache"]
 
 
 class AnnError(RuntimeError):
@@ -59,7 +59,8 @@ class IndexInfo(ctypes.Structure):
                 ("tier", ctypes.c_int32), ("nav_stride", ctypes.c_int32),
                 ("rec_bytes", ctypes.c_int32), ("hbm_bytes", ctypes.c_int64),
                 ("direct_io", ctypes.c_int32), ("pq_m", ctypes.c_int32),
-                ("nav_full", ctypes.c_int32), ("stripes", ctypes.c_int32)]
+                ("nav_full", ctypes.c_int32), ("stripes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("cached_records", ctypes.c_int64)]
 
 
 class AgentProfile(ctypes.Structure):
@@ -138,6 +139,8 @@ def load_library(path: str = LIB_PATH):
     lib.ann_load_records_striped.restype = ctypes.c_int
     lib.ann_index_set_pq.argtypes = [vp, vp, i32, i32]
     lib.ann_index_set_pq.restype = ctypes.c_int
+    lib.ann_index_set_record_cache.argtypes = [vp, vp, i64]
+    lib.ann_index_set_record_cache.restype = ctypes.c_int
     lib.ann_index_pq_codes.argtypes = [vp, vp]
     lib.ann_index_pq_codes.restype = ctypes.c_int
     lib.ann_search_graph.argtypes = [vp, vp, i64, i32, i32, i32, ctypes.POINTER(SearchOptions),
@@ -304,6 +307,16 @@ class Index:
             raise ValueError("codebooks must be [M, 256, d / M] float32")
         _check(load_library().ann_index_set_pq(self.handle, cb.ctypes.data, cb.shape[0],
                                                PQ_DROP_NAV if drop_nav else 0))
+
+    def set_record_cache(self, ids) -> None:
+        """ann_index_set_record_cache: keep copies of the records of nodes
+        `ids` (distinct, host int array) in device memory; searches through
+        the direct transport read those records there.  Results do not
+        change.  An empty array releases the cache."""
+        a = np.ascontiguousarray(np.asarray(ids).reshape(-1), dtype=np.int32)
+        _check(load_library().ann_index_set_record_cache(self.handle,
+                                                         a.ctypes.data if a.size else None,
+                                                         int(a.size)))
 
     def pq_codes(self) -> np.ndarray:
         """ann_index_pq_codes: the PQ codes, [n, M] uint8 on the host."""
