@@ -768,8 +768,8 @@ def hot_cache_leg(fa, torch, dev, ix, qd, cfg, k, op, info, out, stream,
                          "link_GBps_relaxed": round(link / (ms[1] / 1e3) / 1e9, 2)})
     finally:
         ix.set_record_cache([])
-    return {"hot_set": "most-expanded nodes of %d training queries (another seed), relaxed, L=%d"
-                       % (n_train, op[1]), "rows": rows}
+    return ({"hot_set": "most-expanded nodes of %d training queries (another seed), relaxed, L=%d"
+                        % (n_train, op[1]), "rows": rows}, hot_order)
 
 
 def main():
@@ -1141,9 +1141,9 @@ def main():
 
     # ---- hot-record cache: the most-visited records of a separate sample of
     # training queries copied into HBM, the rest read over the host link
-    hot_cache = None
+    hot_cache = hot_order = None
     if tier == fa.TIER_HOST and not args.no_hot_cache:
-        hot_cache = hot_cache_leg(fa, torch, dev, ix, qd, cfg, k, op, info, out, stream)
+        hot_cache, hot_order = hot_cache_leg(fa, torch, dev, ix, qd, cfg, k, op, info, out, stream)
         log("hot-record cache: %s" % hot_cache)
 
     # ---- compressed navigation: PQ codes in HBM, exact re-rank from records,
@@ -1237,6 +1237,14 @@ def main():
             # the default (32 units, ~14 us)
             transports["agent_host"]["poll_backoff"] = {
                 str(pb): measure(ix, qd, op[1], 1, reps, poll_backoff=pb)["qps"] for pb in (4, 32, 128)}
+            if hot_order is not None:
+                # the same with the hottest 10 % of the records in HBM: the
+                # agents get no request for those nodes
+                ix.set_record_cache(hot_order[:n // 10])
+                try:
+                    transports["agent_host"]["hot_cache_10pct"] = compare(ix, qd, reps, 1)
+                finally:
+                    ix.set_record_cache([])
             log("agent transport: %s" % transports["agent_host"])
             # the relaxed pipeline where fetch latency, not bandwidth, binds:
             # fewer queries in flight through the agents
@@ -1272,6 +1280,14 @@ def main():
             fa.search(fix, qsub, k=k, L=op[1])  # warm-up pass
             transports["file"] = {"queries": mq, "L": op[1], "direct_io": fix.info()["direct_io"],
                                   "write_s": round(t_save, 1), **compare(fix, qsub, 1, 2)}
+            if hot_order is not None:
+                # the hottest 10 % of the records in HBM, read from the file
+                # once: the disk serves only the other nodes' records
+                t = time.time()
+                fix.set_record_cache(hot_order[:n // 10])
+                transports["file"]["hot_cache_10pct"] = {"fill_s": round(time.time() - t, 2),
+                                                         **compare(fix, qsub, 1, 2)}
+                fix.set_record_cache([])
             if not args.no_serving:
                 transports["file"]["serving"] = serving_burst(fa, fix, queries, kth, op[1])
             fix.close()

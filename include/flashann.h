@@ -318,21 +318,25 @@ int ann_index_set_pq(ann_index *ix, const float *codebooks, int32_t m, int32_t f
  * ann_index_set_record_cache -- hot-record cache in device memory.  Not a
  * step of the paper's method (its records live in storage, section 4.2) but
  * a layout for GPUs whose memory can hold a share of the records: searches
- * through the direct transport read the records of the cached nodes from
- * device memory and every other record from host memory, as before.  The
- * bytes read are the same, so results do not change; only the host-link
- * traffic does.  A node's cache slot is looked up (one 4 B load from a
- * device map of n entries) when the node is selected for expansion.
+ * read the records of the cached nodes from device memory and every other
+ * record from its tier, as before.  The bytes read are the same, so results
+ * do not change; only the host-link or storage traffic does.  A node's
+ * cache slot is looked up (one 4 B load from a device map of n entries)
+ * when the node is selected for expansion.
  *   ids    host, count distinct node ids in [0, n) whose records are copied
  *          (typically the most-visited nodes of a sample of queries); copied,
  *          caller keeps ownership
  *   count  0 releases the cache
- * Device memory: count x slot_bytes + 4 n bytes.  ANN_TIER_HOST indexes only
- * (HBM-tier records are all in device memory).  Batch searches through the
- * direct transport use it; the agent transport and the server do not.  Synchronous: waits for all device work before replacing
+ * Device memory: count x slot_bytes + 4 n bytes.  ANN_TIER_HOST and
+ * ANN_TIER_FILE indexes (HBM-tier records are all in device memory; a file
+ * tier's cached records are read from its files here).  Batch searches use
+ * it with either transport: the direct loads read a cached record's copy,
+ * and the agent transport posts no request for a cached node.  The server
+ * does not use it.  Synchronous: waits for all device work before replacing
  * the cache; graphs captured before the call must not be replayed after it.
  * Errors: ANN_EINVAL (ids out of range or repeated, count > n), ANN_ENOTSUP
- * (other tiers), ANN_EBUSY (a server is open on the index), ANN_ENOMEM.
+ * (ANN_TIER_HBM), ANN_EBUSY (a server is open on the index), ANN_EIO (a
+ * record file read failed), ANN_ENOMEM.
  */
 int ann_index_set_record_cache(ann_index *ix, const int32_t *ids, int64_t count);
 /* ann_index_pq_codes -- copy the PQ codes to `host_codes` (caller-owned,

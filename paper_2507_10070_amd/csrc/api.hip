@@ -847,7 +847,7 @@ int prepare_search(ann_index *ix, const void *d_queries, int64_t nq, int32_t k, 
   a.beam = o.beam_width;
   a.pslots = std::max(2, (o.delay + 1) * o.beam_width);
   if (o.navigation == ANN_NAV_PQ) set_pq_args(ix, o.pq_scoring, &a);
-  if (transport == ANN_TRANSPORT_DIRECT && ix->cache_count > 0) {
+  if (ix->cache_count > 0) {
     a.cache = ix->d_cache;
     a.cache_map = ix->d_cache_map;
   }
@@ -1182,8 +1182,8 @@ int ann_index_set_record_cache(ann_index *ix, const int32_t *ids, int64_t count)
   if (count < 0 || count > ix->n)
     return fail(ANN_EINVAL, "count=%lld not in [0, n=%lld]", (long long)count, (long long)ix->n);
   if (count > 0 && !ids) return fail(ANN_EINVAL, "ids is NULL");
-  if (count > 0 && ix->tier != ANN_TIER_HOST)
-    return fail(ANN_ENOTSUP, "the record cache serves records in host memory (ANN_TIER_HOST)");
+  if (count > 0 && ix->tier == ANN_TIER_HBM)
+    return fail(ANN_ENOTSUP, "HBM-tier records are all in device memory already");
   if (ix->servers.load() > 0)
     return fail(ANN_EBUSY, "a server is open on this index; close it first");
   std::vector<int32_t> map;
@@ -1212,24 +1212,46 @@ int ann_index_set_record_cache(ann_index *ix, const int32_t *ids, int64_t count)
   if (e == hipSuccess)
     e = hipMemcpy(ix->d_cache_map, map.data(), sizeof(int32_t) * (size_t)ix->n,
                   hipMemcpyHostToDevice);
-  // the copies are gathered in host chunks of up to 64 MiB
+  // the copies are gathered in host chunks of up to 64 MiB: from host memory,
+  // or read from the record files (record v: file v % S at (v / S) * slot;
+  // reads of whole 512 B sectors into an aligned buffer when O_DIRECT)
   const int64_t per = std::max<int64_t>(1, (64ll << 20) / ix->slot);
   std::vector<uint8_t> buf;
-  for (int64_t b = 0; e == hipSuccess && b < count; b += per) {
-    const int64_t m = std::min<int64_t>(per, count - b);
-    buf.resize((size_t)m * (size_t)ix->slot);
-    for (int64_t i = 0; i < m; i++)
-      std::memcpy(buf.data() + (size_t)i * ix->slot,
-                  (const uint8_t *)ix->rec_host + (size_t)ids[b + i] * (size_t)ix->slot,
-                  (size_t)ix->slot);
-    e = hipMemcpy(ix->d_cache + (size_t)b * ix->slot, buf.data(), (size_t)m * ix->slot,
-                  hipMemcpyHostToDevice);
+  const bool file = ix->tier == ANN_TIER_FILE;
+  const size_t io = file && ix->direct_io ? (size_t)round_up(ix->rec_bytes, 512) : (size_t)ix->rec_bytes;
+  void *bounce = nullptr;
+  if (file && posix_memalign(&bounce, 4096, (size_t)round_up((int64_t)io, 4096)) != 0) {
+    bounce = nullptr;
+    e = hipErrorOutOfMemory;
   }
-  if (e != hipSuccess) {
+  int rd_err = 0;
+  for (int64_t b = 0; e == hipSuccess && !rd_err && b < count; b += per) {
+    const int64_t m = std::min<int64_t>(per, count - b);
+    buf.assign((size_t)m * (size_t)ix->slot, 0);
+    for (int64_t i = 0; i < m && !rd_err; i++) {
+      const int64_t v = ids[b + i];
+      uint8_t *dst = buf.data() + (size_t)i * ix->slot;
+      if (!file) {
+        std::memcpy(dst, (const uint8_t *)ix->rec_host + (size_t)v * (size_t)ix->slot,
+                    (size_t)ix->slot);
+        continue;
+      }
+      const int S = (int)ix->fds.size();
+      const ssize_t r = pread(ix->fds[(size_t)(v % S)], bounce, io, (off_t)((v / S) * ix->slot));
+      if (r < (ssize_t)ix->rec_bytes) rd_err = r < 0 ? errno : EIO;
+      else std::memcpy(dst, bounce, (size_t)ix->rec_bytes);
+    }
+    if (!rd_err)
+      e = hipMemcpy(ix->d_cache + (size_t)b * ix->slot, buf.data(), (size_t)m * ix->slot,
+                    hipMemcpyHostToDevice);
+  }
+  free(bounce);
+  if (e != hipSuccess || rd_err) {
     if (ix->d_cache) (void)hipFree(ix->d_cache);
     if (ix->d_cache_map) (void)hipFree(ix->d_cache_map);
     ix->d_cache = nullptr;
     ix->d_cache_map = nullptr;
+    if (rd_err) return fail(ANN_EIO, "record cache: reading a record failed: %s", std::strerror(rd_err));
     return hip_fail(e, "record cache");
   }
   ix->cache_count = count;

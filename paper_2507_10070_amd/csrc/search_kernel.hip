@@ -581,7 +581,7 @@ struct Searcher {
       if (b) {
         const int idx = base + __ffsll((unsigned long long)b) - 1;
         const uint64_t key = S.cand[idx];
-        if (TR == TR_DIRECT && A.cache_map) {
+        if (A.cache_map) {
           // the cache slot of the node whose record is fetched next, loaded
           // now so that the fetch does not wait for it behind the gathers
           sel_id = (uint32_t)key & ~kFlag;
@@ -611,11 +611,17 @@ struct Searcher {
     const int c = lane < A.rec_chunks ? lane : A.rec_chunks - 1;
     const uint8_t *rec = A.records + (int64_t)v * A.slot;
     if (A.cache_map) {
-      int32_t s = sel_slot;
-      if (v != sel_id) s = A.cache_map[v];
+      const int32_t s = cache_slot(v);
       if (s >= 0) rec = A.cache + (int64_t)s * A.slot;
     }
     return *(const uint4 *)(rec + 16 * c);
+  }
+
+  // Hot-record cache slot of node v (-1: not cached); only with a cache.
+  __device__ __forceinline__ int32_t cache_slot(uint32_t v) const {
+    int32_t s = sel_slot;
+    if (v != sel_id) s = A.cache_map[v];
+    return s;
   }
 
   // Request slot of request number s (TR_AGENT).  At most pslots requests of
@@ -642,9 +648,15 @@ struct Searcher {
   // release: the slot's previous request was consumed (its staged bytes
   // loaded and written to LDS) before this point, so the agent cannot
   // overwrite data the wave still reads.
+  // TR_AGENT with a hot-record cache: a cached node posts no request; its
+  // handle carries the cache slot + 1 in .y and consume() reads the copy.
   __device__ __forceinline__ uint4 issue(uint32_t v, bool real) {
     if (TR == TR_DIRECT) return fetch(v);
     if (!real || failed) return make_uint4(0, 0, 0, 0);
+    if (A.cache_map) {
+      const int32_t cs = cache_slot(v);
+      if (cs >= 0) return make_uint4(0, (uint32_t)cs + 1u, 0, 0);
+    }
     seq = next_seq(seq);
     if (lane == 0)
       __hip_atomic_store(A.req + 8 * io.line + pslot(seq), ((uint64_t)v << 32) | seq, __ATOMIC_RELAXED,
@@ -658,8 +670,13 @@ struct Searcher {
   // query with a status code.
   __device__ __forceinline__ uint4 consume(uint4 h) {
     if (TR == TR_DIRECT) return h;
+    if (failed) return make_uint4(0, 0, 0, 0);
+    if (h.y) {  // a cached record: read its copy in device memory
+      const int ch = lane < A.rec_chunks ? lane : A.rec_chunks - 1;
+      return *(const uint4 *)(A.cache + (int64_t)(h.y - 1u) * A.slot + 16 * ch);
+    }
     const uint32_t s = h.x;
-    if (failed || s == 0) return make_uint4(0, 0, 0, 0);
+    if (s == 0) return make_uint4(0, 0, 0, 0);
     uint32_t c = 0;
     if (lane == 0) {
       const uint32_t *w = A.cpl + 16 * io.line + pslot(s);
@@ -1106,9 +1123,18 @@ __device__ __forceinline__ void run_query(const SearchArgs &A, uint8_t *lds, int
           s.template process<true>(u, rec, fid, more, nxt);
           have_nxt = more;
         } else {
-          uint4 unused;
-          cseq = s.next_seq(cseq);
-          s.template process<false>(u, make_uint4(cseq, 0, 0, 0), 0u, false, unused);
+          // the node's request was posted at selection unless it is cached
+          // (the same lookup decides both times: the cache does not change
+          // during a search)
+          uint4 unused, h;
+          const int32_t cs = s.A.cache_map ? s.A.cache_map[(uint32_t)u & ~kFlag] : -1;
+          if (cs >= 0) {
+            h = make_uint4(0, (uint32_t)cs + 1u, 0, 0);
+          } else {
+            cseq = s.next_seq(cseq);
+            h = make_uint4(cseq, 0, 0, 0);
+          }
+          s.template process<false>(u, h, 0u, false, unused);
         }
       }
     }

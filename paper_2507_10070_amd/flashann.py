@@ -310,9 +310,9 @@ class Index:
 
     def set_record_cache(self, ids) -> None:
         """ann_index_set_record_cache: keep copies of the records of nodes
-        `ids` (distinct, host int array) in device memory; searches through
-        the direct transport read those records there.  Results do not
-        change.  An empty array releases the cache."""
+        `ids` (distinct, host int array) in device memory; batch searches
+        read those records there (the agents get no request for them).
+        Results do not change.  An empty array releases the cache."""
         a = np.ascontiguousarray(np.asarray(ids).reshape(-1), dtype=np.int32)
         _check(load_library().ann_index_set_record_cache(self.handle,
                                                          a.ctypes.data if a.size else None,

@@ -1,5 +1,6 @@
 """GPU parity with the hot-record cache: part of the records copied into
-device memory, the rest read from host memory by the direct transport.
+device memory, the rest read from host memory (direct loads or the agents)
+or from record files (the agents).
 
 The cache changes where bytes come from, never which bytes: every search
 must still equal the oracle bit for bit (ids, distances, step counts,
@@ -7,7 +8,8 @@ expansion traces), the records' own vectors must agree with the navigation
 copy (the kernel's record check counts zero mismatches, so no cached copy is
 misplaced), and the cache must reach every schedule (strict, one-step-stale,
 the generic FIFO that looks slots up at fetch time), both tiles, persistent
-and graph launches.
+and graph launches, and the agent transport, which must post requests for
+the uncached nodes only.
 """
 import numpy as np
 import pytest
@@ -102,6 +104,40 @@ def test_cache_with_tiles_persistent_and_graphs(cfg1):
         ix.set_record_cache([])                                    # released
         assert ix.info()["cached_records"] == 0
         assert_int_parity(gpu_search(ix, q, 10, 44, delay=1), ref)
+
+
+def requests_of(ix):
+    return ix.agent_stats()["requests"] if ix.info()["tier"] != fa.TIER_HBM else 0
+
+
+@pytest.mark.parametrize("tier", ["host", "file"])
+@pytest.mark.parametrize("delay,beam", [(0, 1), (1, 1), (2, 1), (1, 2)])
+def test_cache_through_the_agents(cfg1, tmp_path, tier, delay, beam):
+    """The agent transport posts no request for a cached node and reads its
+    copy in device memory: results equal the oracle, and the agents serve
+    exactly the expansions of nodes outside the cache (counted from the
+    traces)."""
+    base, q, adj, entry = cfg1
+    n = base.shape[0]
+    ids = np.random.default_rng(41).choice(n, n // 5, replace=False)
+    cached = np.zeros(n, bool)
+    cached[ids] = True
+    if tier == "file":
+        fa.save_index(str(tmp_path), base, adj, entry, 512)
+        ix = fa.Index.load(str(tmp_path), fa.TIER_FILE)
+    else:
+        ix = fa.Index(base, adj, entry, 256, fa.TIER_HOST)
+    with ix:
+        ix.set_record_cache(ids)
+        r0 = requests_of(ix)
+        g = gpu_search(ix, q, 10, 64, delay=delay, beam_width=beam, trace_cap=400,
+                       transport=fa.TRANSPORT_AGENT)
+        served = requests_of(ix) - r0
+    ref = oracle.search(base, adj, entry, q, 10, 64, delay=delay, beam=beam, trace_cap=400)
+    assert_int_parity(g, ref, check_trace=True)
+    tr = g["trace"][g["trace"] >= 0]
+    assert served == int((~cached[tr]).sum())
+    assert 0 < served < len(tr)
 
 
 @pytest.mark.skip(reason="a server on an index with a record cache stopped delivering results "
