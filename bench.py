@@ -641,12 +641,18 @@ def serving_file_leg(fa, torch, dev, n, nq=10000, m=2000):
     return out
 
 
-def batched_file_leg(fa, torch, dev, n, nq_total):
+def batched_file_leg(fa, torch, dev, n, nq_total, cache_fraction=0.0):
     """Batched form at scale: n int8 vectors of d = 100 (4,096-component
     mixture), degree-48 graph, 512 B records in a file read with O_DIRECT by
     the host agents, nq_total queries with L uniform over {32, 64, 128, 256}
     in one persistent launch; schedule and tiles chosen by the autotuner on a
-    10,000-query sample.  Recall@10 on the first 1,000 queries."""
+    10,000-query sample.  Recall@10 on the first 1,000 queries.
+
+    With cache_fraction > 0 the same launch also runs with that share of the
+    records in the hot-record cache (the most-expanded nodes of 10,000
+    training queries of another seed, traced at L = 128).  The cached launch
+    runs first, so the disk has seen its records less often than those of
+    the uncached launch that follows; both must return identical results."""
     import shutil
     import tempfile
 
@@ -691,10 +697,36 @@ def batched_file_leg(fa, torch, dev, n, nq_total):
                               L_per_query=Lt[:ns].contiguous())
         t_tune = time.time() - t
         kw = autotune.search_kwargs(tuned["params"], {"L_per_query": Lt})
+        cached = None
+        if cache_fraction > 0:
+            qt = torch.from_numpy(synth.make_queries(10000, 100, "i8", 4096, 1004, 7004)).to(dev)
+            tr = torch.full((qt.shape[0], 600), -1, dtype=torch.int32, device=dev)
+            t = time.time()
+            fa.search(ix, qt, k=10, L=128, trace=tr)
+            torch.cuda.synchronize()
+            visits = torch.bincount(tr[tr >= 0].long(), minlength=n)
+            hot = torch.argsort(visits, descending=True, stable=True)[:int(cache_fraction * n)]
+            t_hot = time.time() - t
+            t = time.time()
+            ix.set_record_cache(hot.cpu().numpy())
+            t_fill = time.time() - t
+            t = time.perf_counter()
+            c_ids, c_dists, c_steps = fa.search(ix, qd, k=10, L=256, **kw)
+            torch.cuda.synchronize()
+            el_c = time.perf_counter() - t
+            ix.set_record_cache([])
+            cached = {"fraction": cache_fraction, "records": int(hot.numel()),
+                      "cache_MB": round(int(hot.numel()) * 512 / 1e6, 1),
+                      "hot_set_s": round(t_hot, 1), "fill_s": round(t_fill, 1),
+                      "qps": round(nq_total / el_c, 1), "seconds": round(el_c, 2)}
+            log("batched-file with %.0f%% of the records cached: %s" % (100 * cache_fraction, cached))
         t = time.perf_counter()
         ids, dists, steps = fa.search(ix, qd, k=10, L=256, **kw)
         torch.cuda.synchronize()
         el = time.perf_counter() - t
+        if cached is not None:
+            cached["identical_results"] = bool(torch.equal(ids, c_ids) and torch.equal(dists, c_dists)
+                                               and torch.equal(steps, c_steps))
         out = {"workload": "%d x 100 i8, R=48, 512 B records in a file (O_DIRECT)" % n,
                "queries": nq_total, "L": [32, 64, 128, 256], "k": 10,
                "params": tuned["params"], "qps": round(nq_total / el, 1),
@@ -705,6 +737,8 @@ def batched_file_leg(fa, torch, dev, n, nq_total):
                "tuned_sample_qps": round(ns / (tuned["ms"] / 1e3), 1),
                "tune_s": round(t_tune, 1), "graph_build_s": round(t_graph, 1),
                "write_s": round(t_save, 1), "direct_io": ix.info()["direct_io"]}
+        if cached is not None:
+            out["hot_cache"] = cached
         ix.close()
     finally:
         shutil.rmtree(tmpd, ignore_errors=True)
@@ -795,6 +829,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the autotuned uneven-L batch")
     ap.add_argument("--batched-queries", type=int, default=100000)
+    ap.add_argument("--batched-file-cache", type=float, default=0.0,
+                    help="with --batched-file-n: also run with this share of the records in "
+                         "the hot-record cache")
     ap.add_argument("--batched-file-n", type=int, default=0,
                     help="also run the batched form at scale: this many int8/100 vectors, "
                          "records in a file (off by default: minutes of graph build)")
@@ -1080,7 +1117,8 @@ def main():
 
     batched_file = None
     if args.batched_file_n:
-        batched_file = batched_file_leg(fa, torch, dev, args.batched_file_n, args.batched_queries)
+        batched_file = batched_file_leg(fa, torch, dev, args.batched_file_n, args.batched_queries,
+                                        args.batched_file_cache)
     serving_file = None
     if args.serving_file_n:
         serving_file = serving_file_leg(fa, torch, dev, args.serving_file_n)
