@@ -329,10 +329,9 @@ int ann_index_set_pq(ann_index *ix, const float *codebooks, int32_t m, int32_t f
  *   count  0 releases the cache
  * Device memory: count x slot_bytes + 4 n bytes.  ANN_TIER_HOST and
  * ANN_TIER_FILE indexes (HBM-tier records are all in device memory; a file
- * tier's cached records are read from its files here).  Batch searches use
- * it with either transport: the direct loads read a cached record's copy,
- * and the agent transport posts no request for a cached node.  The server
- * does not use it.  Synchronous: waits for all device work before replacing
+ * tier's cached records are read from its files here).  Searches and
+ * servers use it with either transport: the direct loads read a cached
+ * record's copy, and the agent transport posts no request for a cached node.  Synchronous: waits for all device work before replacing
  * the cache; graphs captured before the call must not be replayed after it.
  * Errors: ANN_EINVAL (ids out of range or repeated, count > n), ANN_ENOTSUP
  * (ANN_TIER_HBM), ANN_EBUSY (a server is open on the index), ANN_EIO (a

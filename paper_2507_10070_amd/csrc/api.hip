@@ -1158,7 +1158,10 @@ int ann_internal_server_args(ann_index *ix, int32_t k_max, int32_t L_max, int32_
   a.entry = ix->entry;
   a.hash_bits = hash_bits;
   if (navigation == ANN_NAV_PQ) set_pq_args(ix, pq_scoring, &a);
-  // the server does not read the hot-record cache (a.cache stays null)
+  if (ix->cache_count > 0) {
+    a.cache = ix->d_cache;
+    a.cache_map = ix->d_cache_map;
+  }
   a.lds_per_wave = fa::search_lds_bytes(a.Lcap, a.nav_stride, a.hash_bits, a.pq_m ? a.k : 0,
                                         a.pq_floats);
   *dtype = ix->dtype;
