@@ -540,7 +540,7 @@ def f32_file_leg(fa, torch, dev, n, R_values, nq, L, keep_dir=None, tier="file")
     return out
 
 
-def serving_file_leg(fa, torch, dev, n, nq=10000, m=2000):
+def serving_file_leg(fa, torch, dev, n, nq=10000, m=2000, cache_fraction=0.0):
     """The serving form with records in a file: n u8/128 vectors of the
     4,096-component mixture, degree-64 graph, 512 B records in a file read
     with O_DIRECT by the server's own host agents; requests draw k from
@@ -548,7 +548,10 @@ def serving_file_leg(fa, torch, dev, n, nq=10000, m=2000):
     smallest L whose recall@10 reaches 0.95 on a 2,000-query sample.
     Saturation from an m-query burst, then open-loop Poisson arrivals at
     0.25, 0.5, 0.75 and 0.9 of it (m queries each), latency from the
-    intended arrival to the result."""
+    intended arrival to the result.  With cache_fraction > 0 the same
+    requests are first served with that share of the records in the
+    hot-record cache (most-expanded nodes of 10,000 training queries of
+    another seed), then without it."""
     import shutil
     import tempfile
 
@@ -591,48 +594,76 @@ def serving_file_leg(fa, torch, dev, n, nq=10000, m=2000):
                     break
             out["L_op"], out["sweep"] = L_op, sweep
             log("serving-file: L_op %d (%s)" % (L_op, sweep))
-            rng = np.random.default_rng(29)
             Lset = [L for L in L_SWEEP if L >= L_op]
-
-            def mix(cnt):
-                ks = rng.choice(np.array([10, 100], np.int32), cnt)
-                return ks, np.array([rng.choice([L for L in Lset if L >= k]) for k in ks],
-                                    np.int32)
 
             def recall(res):
                 qi = (res["tags"] % nq).astype(np.int64)
                 d10 = res["dists"][:, :10].astype(np.float64)
                 return float((np.minimum((d10 <= kth[qi][:, None]).sum(1), 10) / 10.0).mean())
 
-            with fa.Server(ix, hbm_budget_bytes=256 << 20) as srv:
-                ks, Ls = mix(m)
-                # queries the L sweep did not touch: their records are cold,
-                # as they are for the arrivals that follow
-                idx = 2000 + rng.integers(0, nq - 2000, m)
-                t0 = fa.clock_us()
-                srv.submit_batch(q[idx], ks, Ls, idx.astype(np.uint64))
-                res = srv.drain(m, timeout_s=300)
-                qmax = m / ((res["done_us"].max() - t0) / 1e6)
-                out["saturation_qps"] = round(qmax, 1)
-                out["saturation_recall@10"] = round(recall(res), 4)
-                out["failed_reads"] = int((res["status"] != 0).sum())
-                rates = []
-                for frac in (0.25, 0.5, 0.75, 0.9):
-                    lam = frac * qmax
+            def serve():
+                rng = np.random.default_rng(29)
+
+                def mix(cnt):
+                    ks = rng.choice(np.array([10, 100], np.int32), cnt)
+                    return ks, np.array([rng.choice([L for L in Lset if L >= k]) for k in ks],
+                                        np.int32)
+
+                res_out = {}
+                with fa.Server(ix, hbm_budget_bytes=256 << 20) as srv:
                     ks, Ls = mix(m)
+                    # queries the L sweep did not touch: their records are cold,
+                    # as they are for the arrivals that follow
                     idx = 2000 + rng.integers(0, nq - 2000, m)
-                    start = fa.clock_us() + 20000.0
-                    arr = start + np.cumsum(rng.exponential(1e6 / lam, m))
-                    srv.submit_batch(q[idx], ks, Ls, idx.astype(np.uint64), arr)
+                    t0 = fa.clock_us()
+                    srv.submit_batch(q[idx], ks, Ls, idx.astype(np.uint64))
                     res = srv.drain(m, timeout_s=300)
-                    lat = (res["done_us"] - res["submit_us"]) / 1e3
-                    rates.append({"offered_qps": round(lam, 1), "queries": int(len(lat)),
-                                  "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
-                                  "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
-                                  "recall@10": round(recall(res), 4),
-                                  "failed_reads": int((res["status"] != 0).sum())})
-                    log("serving-file at %.0f QPS offered: %s" % (lam, rates[-1]))
-                out["rates"] = rates
+                    qmax = m / ((res["done_us"].max() - t0) / 1e6)
+                    res_out["saturation_qps"] = round(qmax, 1)
+                    res_out["saturation_recall@10"] = round(recall(res), 4)
+                    res_out["failed_reads"] = int((res["status"] != 0).sum())
+                    rates = []
+                    for frac in (0.25, 0.5, 0.75, 0.9):
+                        lam = frac * qmax
+                        ks, Ls = mix(m)
+                        idx = 2000 + rng.integers(0, nq - 2000, m)
+                        start = fa.clock_us() + 20000.0
+                        arr = start + np.cumsum(rng.exponential(1e6 / lam, m))
+                        srv.submit_batch(q[idx], ks, Ls, idx.astype(np.uint64), arr)
+                        res = srv.drain(m, timeout_s=300)
+                        lat = (res["done_us"] - res["submit_us"]) / 1e3
+                        rates.append({"offered_qps": round(lam, 1), "queries": int(len(lat)),
+                                      "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
+                                      "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
+                                      "recall@10": round(recall(res), 4),
+                                      "failed_reads": int((res["status"] != 0).sum())})
+                        log("serving-file at %.0f QPS offered: %s" % (lam, rates[-1]))
+                    res_out["rates"] = rates
+                return res_out
+
+            if cache_fraction > 0:
+                # hot set from training queries of another seed, traced at L_op
+                qt = torch.from_numpy(synth.gmm.make_queries(10000, cfg.d, cfg.dtype, cfg.components,
+                                                             1000 + cfg.seed_offset,
+                                                             7000 + cfg.seed_offset)).to(dev)
+                tr = torch.full((qt.shape[0], 600), -1, dtype=torch.int32, device=dev)
+                t = time.time()
+                fa.search(ix, qt, k=10, L=max(L_op, 64), trace=tr)
+                torch.cuda.synchronize()
+                visits = torch.bincount(tr[tr >= 0].long(), minlength=n)
+                hot = torch.argsort(visits, descending=True, stable=True)[:int(cache_fraction * n)]
+                t_hot = time.time() - t
+                t = time.time()
+                ix.set_record_cache(hot.cpu().numpy())
+                t_fill = time.time() - t
+                cached = serve()
+                ix.set_record_cache([])
+                cached.update({"fraction": cache_fraction, "records": int(hot.numel()),
+                               "hot_set_s": round(t_hot, 1), "fill_s": round(t_fill, 1)})
+                out["hot_cache"] = cached
+                log("serving-file with %.0f%% of the records cached: %s"
+                    % (100 * cache_fraction, cached))
+            out.update(serve())
             prof = ix.agent_profile()
             out["agent"] = {"threads": prof["threads"], "async_io": prof["async_io"]}
     finally:
@@ -829,6 +860,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the autotuned uneven-L batch")
     ap.add_argument("--batched-queries", type=int, default=100000)
+    ap.add_argument("--serving-file-cache", type=float, default=0.0,
+                    help="with --serving-file-n: also serve with this share of the records in "
+                         "the hot-record cache")
     ap.add_argument("--batched-file-cache", type=float, default=0.0,
                     help="with --batched-file-n: also run with this share of the records in "
                          "the hot-record cache")
@@ -895,7 +929,8 @@ def main():
     if args.serving_file_only:
         if not args.serving_file_n:
             sys.exit("--serving-file-only needs --serving-file-n")
-        print(json.dumps({"serving_file": serving_file_leg(fa, torch, dev, args.serving_file_n)}),
+        print(json.dumps({"serving_file": serving_file_leg(
+            fa, torch, dev, args.serving_file_n, cache_fraction=args.serving_file_cache)}),
               flush=True)
         return
     if args.f32_only:
@@ -1121,7 +1156,8 @@ def main():
                                         args.batched_file_cache)
     serving_file = None
     if args.serving_file_n:
-        serving_file = serving_file_leg(fa, torch, dev, args.serving_file_n)
+        serving_file = serving_file_leg(fa, torch, dev, args.serving_file_n,
+                                        cache_fraction=args.serving_file_cache)
     f32_file = None
     if args.f32_file_n:
         f32_file = f32_file_leg(fa, torch, dev, args.f32_file_n, args.f32_R, args.f32_nq,
